@@ -1,0 +1,214 @@
+#!/usr/bin/env python3
+"""RK4 steps/s of the QTT Navier-Stokes step on one MI355X.
+
+Workload: 2048 x 2048 periodic grid (11 quantics sites, d = 4), bond
+dimension chi = 128, decaying-jet shear layer (App. C of the paper) at
+Re = 1e7, dt = 5e-5.  The state is compressed from the dense initial field
+on the GPU, advanced `--warmup` untimed RK4 steps in float64 (the bonds grow
+from the jet's low rank towards chi), and then both solver paths advance the
+same state `--steps` timed RK4 steps:
+  * mixed: float32-MFMA contractions of the convection networks, float64 QR /
+    SVD / CG residual / overlap term, learned-preconditioner setting as given
+    by --precond;
+  * f64:   every contraction in float64 MFMA, unpreconditioned CG.
+`value` is the mixed path's steps/s; the line also carries the float64 path's
+steps/s, their relative L2 difference, the roofline of the dominant GEMM
+kernel (HIP events around sampled launches, executed flops counted on the
+device), and the CPU oracle timed on a bounded sample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK = {0: 78.6, 1: 157.3}          # TFLOP/s: float64 MFMA, float32 MFMA (MI355X)
+KERNEL_NAME = {0: 'k_gemm<double> (float64 MFMA GEMM)', 1: 'k_gemm<float> (float32 MFMA GEMM)'}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument('--gpus', type=int, default=1)
+    ap.add_argument('--steps', type=int, default=2)
+    ap.add_argument('--warmup', type=int, default=1)
+    ap.add_argument('--n', type=int, default=11)
+    ap.add_argument('--chi', type=int, default=128)
+    ap.add_argument('--re', type=float, default=1e7)
+    ap.add_argument('--dt', type=float, default=5e-5)
+    ap.add_argument('--sweeps', type=int, default=2)
+    ap.add_argument('--cg-rtol', type=float, default=1e-10)
+    ap.add_argument('--cg-maxit', type=int, default=1000)
+    ap.add_argument('--paths', default='mixed,f64')
+    ap.add_argument('--precond', type=int, default=0)
+    ap.add_argument('--sample-every', type=int, default=8)
+    ap.add_argument('--cpu-sample', type=int, default=1, help='time the CPU oracle sample')
+    return ap.parse_args()
+
+
+def log(*a):
+    print('[bench]', *a, file=sys.stderr, flush=True)
+
+
+def clone(Q, m):
+    return Q.MPS(list(m.bonds), m.data.clone())
+
+
+def rel_l2(Q, ctx, x, y, chi):
+    d = Q.add(ctx, [1.0, -1.0], [x, y])
+    Q.truncate(ctx, d, 4 * chi, 0.0)     # canonical form; keeps every direction
+    nd = max(Q.inner(ctx, d, d), 0.0) ** 0.5
+    ny = max(Q.inner(ctx, y, y), 0.0) ** 0.5
+    return nd / ny
+
+
+def cpu_sample(n, chi, re, dt, gpu_env_ms):
+    """Oracle right-environment build of one projection stage at the
+    workload's size (all 20 networks, sites n-1..1) on a saturated state."""
+    import numpy as np
+    from oracle import mps as M
+    from oracle import sweep as S
+    from paper_2406_17823_amd import inputs as I
+    u = I.spectrum(n, 5, k0=16.0)
+    uc = [M.tt_svd(u[i], chi, 1e-12)[0] for i in range(2)]
+    a = [M.scale(c, 0.25) for c in uc]
+    prm = S.Params(re=re, dt=dt, chi=chi, dx=1.0 / (1 << n))
+    v = [M.right_canonicalize(x) for x in a]
+    rhs, pen = S.build_networks(a, uc, dt / 6, prm, n)
+    t0 = time.perf_counter()
+    for net in rhs + list(pen.values()):
+        net.init(v, n)
+    t = time.perf_counter() - t0
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except Exception:
+        cores = os.cpu_count()
+    threads = int(os.environ.get('OMP_NUM_THREADS', cores))
+    return t, min(threads, cores), [M.bonds(x) for x in uc]
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f'bench.py runs on one GPU only; --gpus {args.gpus} is not supported '
+              '(the QTT step is not sharded across GPUs in this build)', flush=True)
+        sys.exit(2)
+    import torch
+    from paper_2406_17823_amd import inputs as I
+    from paper_2406_17823_amd import qtt as Q
+
+    n, chi = args.n, args.chi
+    dx = 1.0 / (1 << n)
+    ctx = Q.Context(0)
+    cap = Q.mps_size(Q.canonical_bonds(n, chi))
+    t0 = time.perf_counter()
+    u0 = I.decaying_jet(n)
+    state = [Q.from_dense(ctx, torch.from_numpy(u0[c]).cuda(), chi, 1e-12, capacity=cap)
+             for c in range(2)]
+    log('initial bonds', state[0].bonds, state[1].bonds, f'{time.perf_counter() - t0:.1f}s')
+
+    def prm_for(path):
+        return Q.params(re=args.re, dt=args.dt, chi=chi, dx=dx, cg_rtol=args.cg_rtol,
+                        cg_maxit=args.cg_maxit, max_sweeps=args.sweeps, svd_rtol=1e-12,
+                        prec=Q.PREC_F32 if path == 'mixed' else Q.PREC_F64,
+                        precond=args.precond if path == 'mixed' else Q.PC_NONE)
+
+    for w in range(args.warmup):
+        t1 = time.perf_counter()
+        rc, st = Q.rk4_step(ctx, state, prm_for('f64'))
+        torch.cuda.synchronize()
+        log(f'warmup {w} {time.perf_counter() - t1:.2f}s bonds', state[0].bonds, state[1].bonds,
+            'cg', st['cg_iters_total'], st['cg_iters_max'])
+
+    paths = [p for p in args.paths.split(',') if p]
+    results, finals, kstats = {}, {}, {}
+    for path in paths:
+        u = [clone(Q, state[0]), clone(Q, state[1])]
+        prm = prm_for(path)
+        Q.kernel_timing(ctx, True, args.sample_every)
+        cg_total, cg_solves = 0, 0
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for s in range(args.steps):
+            rc, st = Q.rk4_step(ctx, u, prm)
+            cg_total += st['cg_iters_total']
+            cg_solves += st['cg_solves']
+            log(f'{path} step {s} {time.perf_counter() - t1:.2f}s cg {st["cg_iters_total"]}')
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t1
+        kstats[path] = {k: Q.kernel_stats(ctx, k) for k in (0, 1)}
+        Q.kernel_timing(ctx, False)
+        results[path] = dict(seconds=el, steps_per_s=args.steps / el,
+                             cg_iters_per_solve=cg_total / max(cg_solves, 1))
+        finals[path] = u
+        log(path, results[path])
+
+    main_path = 'mixed' if 'mixed' in results else paths[0]
+    rel = None
+    if 'mixed' in finals and 'f64' in finals:
+        rel = max(rel_l2(Q, ctx, finals['mixed'][i], finals['f64'][i], chi) for i in range(2))
+
+    # roofline of the dominant kernel of the timed (value) path
+    ks = kstats[main_path]
+
+    def est_time(k):
+        s = ks[k]
+        return (s['timed_ms'] / s['timed'] * s['launches']) if s['timed'] else 0.0
+
+    dom = max((0, 1), key=est_time)
+    s = ks[dom]
+    avg_ms = s['timed_ms'] / max(s['timed'], 1)
+    flops_per_launch = s['flops'] / max(s['launches'], 1)
+    achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
+    roofline = dict(bound='mfma', kernel=KERNEL_NAME[dom], achieved=round(achieved, 3),
+                    peak=PEAK[dom], unit='TFLOP/s', frac=round(achieved / PEAK[dom], 4),
+                    traffic=None, launches=s['launches'], avg_launch_ms=round(avg_ms, 5),
+                    flops_per_launch=flops_per_launch,
+                    kernel_share=round(est_time(dom) / (results[main_path]['seconds'] * 1e3), 3))
+
+    cpu = None
+    if args.cpu_sample:
+        # GPU time of the same sample (stage-1 environment build), phase-timed
+        os.environ['QTT_TIMING'] = '1'
+        tctx = Q.Context(0)
+        os.environ.pop('QTT_TIMING')
+        u = [clone(Q, state[0]), clone(Q, state[1])]
+        prm = prm_for(main_path)
+        prm.max_sweeps = 1
+        a = [clone(Q, u[0]), clone(Q, u[1])]
+        for x in a:
+            x.data[:x.bonds[1] * 4] *= 0.25
+        v = [clone(Q, a[0]), clone(Q, a[1])]
+        rc, st = Q.project(tctx, a, u, args.dt / 6, prm, v)
+        gpu_env_ms = st['phase_ms'][1]
+        del tctx
+        t_cpu, cores, cpu_bonds = cpu_sample(n, chi, args.re, args.dt, gpu_env_ms)
+        step_s = results[main_path]['seconds'] / args.steps
+        cpu_step_s = step_s * (t_cpu * 1e3) / max(gpu_env_ms, 1e-9)
+        cpu = dict(value=round(1.0 / cpu_step_s, 6), unit='RK4 steps/s', cores=cores,
+                   kind='oracle',
+                   sample=(f'oracle right-environment build of one projection stage (20 networks, '
+                           f'sites {n - 1}..1) at {1 << n}^2, chi={chi}, bonds {cpu_bonds[0]}: '
+                           f'{t_cpu:.1f} s on CPU vs {gpu_env_ms:.1f} ms for the same phase on the '
+                           f'GPU; steps/s scaled by that ratio'))
+
+    line = dict(metric='RK4 steps/s, 2^11^2 grid chi=128, mixed vs FP64 plain at <=1e-5 rel L2',
+                value=round(results[main_path]['steps_per_s'], 5), unit='RK4 steps/s',
+                n_gpus=1, steps=args.steps, warmup=args.warmup,
+                ms_per_step=round(1e3 * results[main_path]['seconds'] / args.steps, 2),
+                higher_is_better=True, scaling='weak', vs_baseline=None,
+                dtype='f32' if main_path == 'mixed' else 'f64', data='synthetic',
+                config=dict(workload=f'decaying jet, {1 << n}x{1 << n} grid ({n} sites), '
+                                     f'chi={chi}, Re={args.re:g}, dt={args.dt:g}',
+                            sweeps=args.sweeps, cg_rtol=args.cg_rtol, precond=args.precond),
+                paths={k: dict(v, **({} if k not in kstats else {})) for k, v in results.items()},
+                rel_l2_mixed_vs_f64=rel,
+                roofline=roofline, cpu_baseline=cpu)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == '__main__':
+    main()

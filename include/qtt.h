@@ -1,0 +1,212 @@
+/*
+ * qtt.h -- C ABI of the MI355X (gfx950) quantics-tensor-train Navier-Stokes
+ * library.
+ *
+ * What it computes (arXiv 2406.17823, "Quantum-Inspired Fluid Simulation of
+ * 2D Turbulence with GPU Acceleration"): the velocity components u_1, u_2 of
+ * 2D incompressible flow on a periodic 2^n x 2^n grid are each held as a
+ * matrix product state over the quantics index omega_k = 2*bit_k(x1) +
+ * bit_k(x2) (Sec. II.B, bit 0 = most significant, site 0 = coarsest scale).
+ * One time step is RK4 written as four Euler minimisations of the penalty
+ * cost Theta (App. B, Eq. Theta, Table RK4, Eqs. U1-U4), each minimised by
+ * a one-site variational sweep with conjugate-gradient local solves
+ * (Sec. II.C, App. B).
+ *
+ * Memory and ownership
+ *   All tensors are caller-owned device memory on the context's device,
+ *   float64.  The library allocates only its own workspace, inside the
+ *   context, and frees it in qtt_ctx_destroy.  Output bond dimensions are
+ *   computed by the library; a caller buffer that is too small yields
+ *   QTT_E_CAPACITY and the required number of doubles in qtt_last_error().
+ *
+ * Streams
+ *   Every call is enqueued on the stream given to qtt_ctx_create and
+ *   returns after the stream has finished the call's work unless stated
+ *   otherwise, so host-side results (discarded weights, statistics, bonds)
+ *   are valid on return.
+ *
+ * Errors
+ *   0 = success, > 0 = warning (result valid), < 0 = error (outputs
+ *   undefined).  No C++ exception crosses this interface.  One context per
+ *   host thread; a context is not thread-safe.
+ */
+#ifndef QTT_H
+#define QTT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define QTT_MAX_SITES 16
+
+enum {
+  QTT_OK = 0,
+  QTT_W_CG_MAXIT = 1,          /* a local CG solve stopped at cg_maxit          */
+  QTT_W_SWEEP_MAXIT = 2,       /* the sweep stopped at max_sweeps (sweep_rtol>0) */
+  QTT_W_PRECOND_FALLBACK = 3,  /* the learned preconditioner was rejected        */
+  QTT_E_ARG = -1,
+  QTT_E_SHAPE = -2,
+  QTT_E_CAPACITY = -3,
+  QTT_E_HIP = -4,
+  QTT_E_NAN = -5,
+  QTT_E_UNSUPPORTED = -6
+};
+
+/* contraction precision of the expensive networks (the QR / SVD, the CG
+ * residual and the overlap term always stay float64) */
+enum { QTT_PREC_F64 = 0, QTT_PREC_F32 = 1 };
+
+/* preconditioner of the local CG solves */
+enum { QTT_PC_NONE = 0, QTT_PC_BLOCK_JACOBI = 1, QTT_PC_LEARNED = 2 };
+
+typedef struct qtt_ctx qtt_ctx;
+
+/* One MPS (one velocity component).  Core k occupies
+ * bond[k] * 4 * bond[k+1] doubles, row-major [bond[k]][4][bond[k+1]], and
+ * the cores are packed in site order from data[0].  bond[0] = bond[n] = 1. */
+typedef struct {
+  int32_t n;                        /* sites, 1 <= n <= QTT_MAX_SITES     */
+  int32_t bond[QTT_MAX_SITES + 1];  /* bond dimensions                    */
+  int64_t capacity;                 /* doubles available at data          */
+  double *data;                     /* device pointer                     */
+} qtt_mps;
+
+/* One MPO.  Core k is row-major [bond[k]][4][4][bond[k+1]] (output physical
+ * index first, then the index contracted with the MPS), packed like qtt_mps. */
+typedef struct {
+  int32_t n;
+  int32_t bond[QTT_MAX_SITES + 1];
+  int64_t capacity;
+  double *data;                     /* device pointer */
+} qtt_mpo;
+
+typedef struct {
+  double re;          /* Reynolds number                                      */
+  double dt;          /* time step                                            */
+  double mu;          /* penalty factor (App. B: 2.5e5)                       */
+  double dx;          /* grid spacing, 1 / 2^n on the periodic unit square    */
+  int32_t chi;        /* maximal bond dimension                               */
+  double svd_rtol;    /* singular values <= svd_rtol * sigma_max are dropped  */
+  double cg_rtol;     /* CG stops at ||r|| <= cg_rtol ||rhs||                 */
+  int32_t cg_maxit;   /* CG iteration cap (paper: 100)                        */
+  double sweep_rtol;  /* sweep stops when |dN| <= sweep_rtol N; 0 = never     */
+  int32_t max_sweeps; /* sweep cap                                            */
+  int32_t lap_mode;   /* 0 = three-point D_j^2, 1 = D_j o D_j                 */
+  int32_t prec;       /* QTT_PREC_*                                           */
+  int32_t precond;    /* QTT_PC_*                                             */
+} qtt_params;
+
+typedef struct {
+  int32_t sweeps[4];        /* sweeps per RK4 stage (qtt_project: [0])          */
+  int32_t cg_iters_total;   /* CG iterations over all local solves             */
+  int32_t cg_iters_max;     /* largest iteration count of one local solve      */
+  int32_t cg_solves;        /* local solves                                    */
+  int32_t cg_maxit_hits;    /* local solves that stopped at cg_maxit           */
+  int32_t fallbacks;        /* learned preconditioner rejections               */
+  double discarded_sq;      /* summed discarded singular weight of truncations */
+  double phase_ms[8];       /* host-timed phases: 0 add/truncate, 1 env build,
+                               2 local rhs, 3 CG, 4 shift, 5 env update        */
+} qtt_stats;
+
+/* Context on HIP device `device`, enqueuing on `hip_stream` (a hipStream_t,
+ * NULL = the null stream).  Returns QTT_E_HIP if the device is unusable. */
+int qtt_ctx_create(qtt_ctx **ctx, int device, void *hip_stream);
+void qtt_ctx_destroy(qtt_ctx *ctx);
+/* Message of the last failing call on this context ("" if none). */
+const char *qtt_last_error(const qtt_ctx *ctx);
+
+/* Doubles needed for an MPS with the given n + 1 bonds. */
+int64_t qtt_mps_size(int32_t n, const int32_t *bond);
+
+/* Finite-difference MPO (Sec. II.B, Eq. fdm; App. A, Table diff_mpo):
+ * axis 1 acts on x1, axis 2 on x2; order 1 is the central difference
+ * (u(x+1) - u(x-1)) / (2 dx), order 2 the three-point second difference.
+ * Periodic.  Fills out->bond and out->data (capacity >= n * 144 doubles). */
+int qtt_mpo_derivative(qtt_ctx *ctx, int32_t n, int32_t axis, int32_t order, double dx,
+                       qtt_mpo *out);
+
+/* y = sum_j coef[j] * x[j]  (exact; Sec. II.C, the RK4 step is a sum of
+ * Euler steps).  Bonds add (ends stay 1); cores are block-diagonal with the
+ * coefficients folded into site 0.  coef and x are host arrays of length k;
+ * the x[j].data and y->data are device pointers. */
+int qtt_add(qtt_ctx *ctx, int32_t k, const double *coef, const qtt_mps *x, qtt_mps *y);
+
+/* In-place TT-rounding (Sec. II.B/II.C, compression to chi by repeated
+ * SVDs): left-to-right QR sweep, then right-to-left SVD keeping
+ * min(chi, 4^k, 4^(n-k), #sigma > svd_rtol * sigma_max) values at each bond.
+ * The orthogonality centre ends at site 0.  *discarded_sq (host, may be
+ * NULL) receives the summed squares of the dropped singular values, which
+ * equals ||y_in - y_out||^2. */
+int qtt_truncate(qtt_ctx *ctx, qtt_mps *y, int32_t chi, double svd_rtol, double *discarded_sq);
+
+/* y = W x (App. A; the MPO's second physical index contracts with x).
+ * chi = 0: exact, bonds multiply; chi > 0: followed by qtt_truncate. */
+int qtt_apply_mpo(qtt_ctx *ctx, const qtt_mpo *W, const qtt_mps *x, int32_t chi,
+                  double svd_rtol, qtt_mps *y, double *discarded_sq);
+
+/* y = a (.) b pointwise (Sec. II.B, copy tensors): cores
+ * y[(al,al'),w,(be,be')] = a[al,w,be] b[al',w,be'], bonds multiply;
+ * chi > 0 truncates afterwards. */
+int qtt_hadamard(qtt_ctx *ctx, const qtt_mps *a, const qtt_mps *b, int32_t chi,
+                 double svd_rtol, qtt_mps *y, double *discarded_sq);
+
+/* <x|y> (host result). */
+int qtt_inner(qtt_ctx *ctx, const qtt_mps *x, const qtt_mps *y, double *out);
+
+/* Dense grid (device, N x N, x1-major, float64) of an MPS, n <= 13. */
+int qtt_to_dense(qtt_ctx *ctx, const qtt_mps *x, double *grid);
+
+/* Input compression of a dense grid (device, N x N, x1-major) into an MPS
+ * with bonds <= min(chi, 4^k, 4^(n-k)) by sequential truncated
+ * eigen-decompositions of the unfoldings' Gram matrices (input preparation,
+ * not part of the time step).  The Gram route resolves singular values only
+ * down to about 1e-8 sigma_max, so singular values below
+ * max(svd_rtol, 1e-7) * sigma_max are dropped; results agree with an exact
+ * TT-SVD to about 1e-7 relative L2. */
+int qtt_from_dense(qtt_ctx *ctx, const double *grid, int32_t n, int32_t chi, double svd_rtol,
+                   qtt_mps *out);
+
+/* One Euler minimisation (App. B, Eq. Theta; Eqs. first/second, big_LS):
+ *   v = argmin Theta(v; a, b, h)
+ * over MPS v_1, v_2 with the bonds of the guess v (in: guess, out: result,
+ * centre at site 0).  Local systems
+ *   C_i + mu h^2 sum_j P_i^T D_i^T D_j P_j C_j = P_i^T a_i - h P_i^T B_i(b)
+ * are solved by CG on the GPU; B_i contains the skew-symmetric convection
+ * through Hadamard MPOs of b and the diffusion through D_j^2.  a, b, v are
+ * arrays of two MPS; the bonds of v must satisfy
+ * bond[k+1] <= 4 bond[k] and bond[k] <= 4 bond[k+1]. */
+int qtt_project(qtt_ctx *ctx, const qtt_mps *a, const qtt_mps *b, double h,
+                const qtt_params *p, qtt_mps *v, qtt_stats *stats);
+
+/* One RK4 step in place on u (array of two MPS; App. B, Table RK4, Eqs.
+ * U1-U4): a = u/4; stage k solves Theta with h = dt/6, dt/3, dt/3, dt/6 and
+ * b = u, 3 U1 + u/4, 3/2 U2 + 5/8 u, 3 U3 + u/4 (each truncated to chi);
+ * u <- truncate(U1 + U2 + U3 + U4, chi).  u[i].capacity must hold the
+ * bonds min(chi, 4^k, 4^(n-k)). */
+int qtt_rk4_step(qtt_ctx *ctx, qtt_mps *u, const qtt_params *p, qtt_stats *stats);
+
+/* Kernel timing for roofline reporting.  While enabled, every launch of the
+ * two GEMM kernels (0 = float64 MFMA, 1 = float32 MFMA) is counted, the
+ * kernel adds the flops it executed (2 M N K per batch entry; 0 when it
+ * returned early because its CG solve had converged) to a device counter,
+ * and every sample_every-th launch is bracketed by HIP events on the
+ * context stream.  Enabling starts a new window; reading synchronises the
+ * stream. */
+typedef struct {
+  int64_t launches;   /* launches in the window                          */
+  int64_t timed;      /* launches bracketed by events                    */
+  double flops;       /* flops executed by all launches                  */
+  double timed_ms;    /* summed event time of the timed launches         */
+} qtt_kernel_stats;
+
+int qtt_kernel_timing(qtt_ctx *ctx, int32_t enable, int32_t sample_every);
+int qtt_kernel_stats_read(qtt_ctx *ctx, int32_t kernel, qtt_kernel_stats *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QTT_H */

@@ -1,0 +1,311 @@
+// extern "C" entry points declared in include/qtt.h.  Each converts the C
+// descriptors, runs the device work on the context stream, and maps
+// qtt::Error to the return code (message kept for qtt_last_error).
+#include "qtt_internal.h"
+
+#include <cstdlib>
+#include <cstring>
+#include <sstream>
+
+struct qtt_ctx {
+  qtt::Ctx c;
+};
+
+namespace {
+
+template <typename F>
+int guard(qtt_ctx *ctx, F &&f) {
+  if (!ctx) return QTT_E_ARG;
+  ctx->c.err.clear();
+  ctx->c.user_ranges.clear();
+  try {
+    HIPC(hipSetDevice(ctx->c.device));
+    f();
+    return QTT_OK;
+  } catch (qtt::Error &e) {
+    ctx->c.err = e.msg;
+    if (e.code > 0) return e.code;
+    // leave the stream idle before reporting
+    hipStreamSynchronize(ctx->c.stream);
+    return e.code;
+  } catch (std::exception &e) {
+    ctx->c.err = e.what();
+    return QTT_E_HIP;
+  }
+}
+
+void reg(qtt::Ctx &c, const qtt_mps &m) { c.register_user(m.data, (size_t)m.capacity * 8); }
+
+void check_finite(qtt::Ctx &c, const qtt::Mps &x, const char *what) {
+  if (qtt::any_nonfinite(c, x.data, x.size())) qtt::fail(QTT_E_NAN, std::string(what) + ": NaN/Inf");
+}
+
+void check_params(const qtt_params *p) {
+  if (!p) qtt::fail(QTT_E_ARG, "params: null");
+  if (!(p->dx > 0.0) || !(p->re > 0.0) || !(p->mu >= 0.0) || p->chi < 1)
+    qtt::fail(QTT_E_ARG, "params: dx, re must be > 0, mu >= 0, chi >= 1");
+  if (!(p->cg_rtol >= 0.0) || p->cg_maxit < 1 || p->max_sweeps < 1)
+    qtt::fail(QTT_E_ARG, "params: cg_rtol >= 0, cg_maxit >= 1, max_sweeps >= 1");
+  if (p->lap_mode != 0 && p->lap_mode != 1) qtt::fail(QTT_E_ARG, "params: lap_mode");
+}
+
+}  // namespace
+
+extern "C" {
+
+int qtt_ctx_create(qtt_ctx **out, int device, void *hip_stream) {
+  if (!out) return QTT_E_ARG;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return QTT_E_HIP;
+  if (hipSetDevice(device) != hipSuccess) return QTT_E_HIP;
+  qtt_ctx *c = new qtt_ctx();
+  c->c.device = device;
+  c->c.stream = (hipStream_t)hip_stream;
+  const char *t = std::getenv("QTT_TIMING");
+  c->c.timing = (t && t[0] == '1');
+  *out = c;
+  return QTT_OK;
+}
+
+void qtt_ctx_destroy(qtt_ctx *ctx) {
+  if (!ctx) return;
+  hipSetDevice(ctx->c.device);
+  delete ctx;
+}
+
+const char *qtt_last_error(const qtt_ctx *ctx) { return ctx ? ctx->c.err.c_str() : "null context"; }
+
+int64_t qtt_mps_size(int32_t n, const int32_t *bond) {
+  if (n < 1 || n > QTT_MAX_SITES || !bond) return -1;
+  int64_t s = 0;
+  for (int k = 0; k < n; ++k) s += (int64_t)bond[k] * 4 * bond[k + 1];
+  return s;
+}
+
+int qtt_mpo_derivative(qtt_ctx *ctx, int32_t n, int32_t axis, int32_t order, double dx,
+                       qtt_mpo *out) {
+  return guard(ctx, [&] {
+    if (!out || n < 1 || n > QTT_MAX_SITES || (axis != 1 && axis != 2) ||
+        (order != 1 && order != 2) || !(dx > 0.0))
+      qtt::fail(QTT_E_ARG, "mpo_derivative: bad arguments");
+    std::vector<double> cores;
+    int bond[QTT_MAX_SITES + 1];
+    qtt::build_derivative_host(n, axis, order, dx, cores, bond);
+    if ((int64_t)cores.size() > out->capacity) {
+      std::ostringstream s;
+      s << "mpo_derivative: needs " << cores.size() << " doubles";
+      qtt::fail(QTT_E_CAPACITY, s.str());
+    }
+    if (!out->data) qtt::fail(QTT_E_ARG, "mpo_derivative: null data");
+    out->n = n;
+    for (int k = 0; k <= QTT_MAX_SITES; ++k) out->bond[k] = (k <= n) ? bond[k] : 0;
+    HIPC(hipMemcpyAsync(out->data, cores.data(), cores.size() * sizeof(double),
+                        hipMemcpyHostToDevice, ctx->c.stream));
+    ctx->c.sync();
+  });
+}
+
+int qtt_add(qtt_ctx *ctx, int32_t k, const double *coef, const qtt_mps *x, qtt_mps *y) {
+  return guard(ctx, [&] {
+    if (k < 1 || !coef || !x || !y) qtt::fail(QTT_E_ARG, "add: bad arguments");
+    std::vector<qtt::Mps> xs;
+    for (int j = 0; j < k; ++j) {
+      reg(ctx->c, x[j]);
+      xs.push_back(qtt::from_c(x[j]));
+    }
+    reg(ctx->c, *y);
+    qtt::Mps out;
+    out.data = y->data;
+    out.capacity = y->capacity;
+    if (!out.data) qtt::fail(QTT_E_ARG, "add: null output");
+    qtt::mps_add(ctx->c, k, coef, xs.data(), out);
+    ctx->c.sync();
+    qtt::to_c(out, y);
+  });
+}
+
+int qtt_truncate(qtt_ctx *ctx, qtt_mps *y, int32_t chi, double svd_rtol, double *discarded_sq) {
+  return guard(ctx, [&] {
+    if (!y || chi < 1 || !(svd_rtol >= 0.0)) qtt::fail(QTT_E_ARG, "truncate: bad arguments");
+    reg(ctx->c, *y);
+    qtt::Mps m = qtt::from_c(*y);
+    double disc = 0.0;
+    qtt::mps_truncate(ctx->c, {&m}, chi, svd_rtol, &disc);
+    qtt::to_c(m, y);
+    if (discarded_sq) *discarded_sq = disc;
+  });
+}
+
+int qtt_apply_mpo(qtt_ctx *ctx, const qtt_mpo *W, const qtt_mps *x, int32_t chi, double svd_rtol,
+                  qtt_mps *y, double *discarded_sq) {
+  return guard(ctx, [&] {
+    if (!W || !x || !y || chi < 0) qtt::fail(QTT_E_ARG, "apply_mpo: bad arguments");
+    reg(ctx->c, *x);
+    reg(ctx->c, *y);
+    ctx->c.register_user(W->data, (size_t)W->capacity * 8);
+    qtt::Mps xm = qtt::from_c(*x);
+    if (W->n != xm.n || !W->data) qtt::fail(QTT_E_SHAPE, "apply_mpo: MPO does not match");
+    qtt::Mpo w;
+    w.n = W->n;
+    for (int k = 0; k <= W->n; ++k) w.bond[k] = W->bond[k];
+    if (w.bond[0] != 1 || w.bond[w.n] != 1) qtt::fail(QTT_E_SHAPE, "apply_mpo: MPO end bonds");
+    if (w.off(w.n) > W->capacity) qtt::fail(QTT_E_CAPACITY, "apply_mpo: MPO capacity");
+    w.fwd = W->data;
+    qtt::Mps out;
+    out.data = y->data;
+    out.capacity = y->capacity;
+    qtt::mps_apply_mpo(ctx->c, w, xm, out);
+    double disc = 0.0;
+    if (chi > 0) qtt::mps_truncate(ctx->c, {&out}, chi, svd_rtol, &disc);
+    ctx->c.sync();
+    qtt::to_c(out, y);
+    if (discarded_sq) *discarded_sq = disc;
+  });
+}
+
+int qtt_hadamard(qtt_ctx *ctx, const qtt_mps *a, const qtt_mps *b, int32_t chi, double svd_rtol,
+                 qtt_mps *y, double *discarded_sq) {
+  return guard(ctx, [&] {
+    if (!a || !b || !y || chi < 0) qtt::fail(QTT_E_ARG, "hadamard: bad arguments");
+    reg(ctx->c, *a);
+    reg(ctx->c, *b);
+    reg(ctx->c, *y);
+    qtt::Mps am = qtt::from_c(*a), bm = qtt::from_c(*b);
+    qtt::Mps out;
+    out.data = y->data;
+    out.capacity = y->capacity;
+    qtt::mps_hadamard(ctx->c, am, bm, out);
+    double disc = 0.0;
+    if (chi > 0) qtt::mps_truncate(ctx->c, {&out}, chi, svd_rtol, &disc);
+    ctx->c.sync();
+    qtt::to_c(out, y);
+    if (discarded_sq) *discarded_sq = disc;
+  });
+}
+
+int qtt_inner(qtt_ctx *ctx, const qtt_mps *x, const qtt_mps *y, double *out) {
+  return guard(ctx, [&] {
+    if (!x || !y || !out) qtt::fail(QTT_E_ARG, "inner: bad arguments");
+    reg(ctx->c, *x);
+    reg(ctx->c, *y);
+    *out = qtt::mps_inner(ctx->c, qtt::from_c(*x), qtt::from_c(*y));
+  });
+}
+
+int qtt_to_dense(qtt_ctx *ctx, const qtt_mps *x, double *grid) {
+  return guard(ctx, [&] {
+    if (!x || !grid) qtt::fail(QTT_E_ARG, "to_dense: bad arguments");
+    reg(ctx->c, *x);
+    if (x->n < 1 || x->n > 13) qtt::fail(QTT_E_UNSUPPORTED, "to_dense: n must be 1..13");
+    ctx->c.register_user(grid, ((size_t)1 << (2 * x->n)) * 8);
+    qtt::mps_to_dense(ctx->c, qtt::from_c(*x), grid);
+    ctx->c.sync();
+  });
+}
+
+int qtt_from_dense(qtt_ctx *ctx, const double *grid, int32_t n, int32_t chi, double svd_rtol,
+                   qtt_mps *out) {
+  return guard(ctx, [&] {
+    if (!grid || !out || chi < 1 || !(svd_rtol >= 0.0)) qtt::fail(QTT_E_ARG, "from_dense: bad arguments");
+    if (n < 1 || n > 13) qtt::fail(QTT_E_UNSUPPORTED, "from_dense: n must be 1..13");
+    ctx->c.register_user(grid, ((size_t)1 << (2 * n)) * 8);
+    reg(ctx->c, *out);
+    qtt::Mps m;
+    m.data = out->data;
+    m.capacity = out->capacity;
+    if (!m.data) qtt::fail(QTT_E_ARG, "from_dense: null output");
+    qtt::mps_from_dense(ctx->c, grid, n, chi, svd_rtol, m);
+    qtt::to_c(m, out);
+  });
+}
+
+int qtt_project(qtt_ctx *ctx, const qtt_mps *a, const qtt_mps *b, double h, const qtt_params *p,
+                qtt_mps *v, qtt_stats *stats) {
+  return guard(ctx, [&] {
+    check_params(p);
+    if (!a || !b || !v) qtt::fail(QTT_E_ARG, "project: bad arguments");
+    for (int i = 0; i < 2; ++i) {
+      reg(ctx->c, a[i]);
+      reg(ctx->c, b[i]);
+      reg(ctx->c, v[i]);
+    }
+    qtt::Mps am[2] = {qtt::from_c(a[0]), qtt::from_c(a[1])};
+    qtt::Mps bm[2] = {qtt::from_c(b[0]), qtt::from_c(b[1])};
+    qtt::Mps vm[2] = {qtt::from_c(v[0]), qtt::from_c(v[1])};
+    for (int i = 0; i < 2; ++i) {
+      check_finite(ctx->c, am[i], "project: a");
+      check_finite(ctx->c, bm[i], "project: b");
+      check_finite(ctx->c, vm[i], "project: guess");
+    }
+    if (stats) std::memset(stats, 0, sizeof(qtt_stats));
+    int warn = 0;
+    try {
+      qtt::project(ctx->c, am, bm, h, *p, vm, stats, 0);
+    } catch (qtt::Error &e) {
+      if (e.code <= 0) throw;
+      warn = e.code;
+    }
+    qtt::to_c(vm[0], &v[0]);
+    qtt::to_c(vm[1], &v[1]);
+    if (warn) throw qtt::Error{warn, "project: warning"};
+  });
+}
+
+int qtt_rk4_step(qtt_ctx *ctx, qtt_mps *u, const qtt_params *p, qtt_stats *stats) {
+  return guard(ctx, [&] {
+    check_params(p);
+    if (!u) qtt::fail(QTT_E_ARG, "rk4_step: bad arguments");
+    reg(ctx->c, u[0]);
+    reg(ctx->c, u[1]);
+    qtt::Mps um[2] = {qtt::from_c(u[0]), qtt::from_c(u[1])};
+    for (int i = 0; i < 2; ++i) check_finite(ctx->c, um[i], "rk4_step: state");
+    if (stats) std::memset(stats, 0, sizeof(qtt_stats));
+    int warn = 0;
+    try {
+      qtt::rk4_step(ctx->c, um, *p, stats);
+    } catch (qtt::Error &e) {
+      if (e.code <= 0) throw;
+      warn = e.code;
+    }
+    qtt::to_c(um[0], &u[0]);
+    qtt::to_c(um[1], &u[1]);
+    if (warn) throw qtt::Error{warn, "rk4_step: warning"};
+  });
+}
+
+int qtt_kernel_timing(qtt_ctx *ctx, int32_t enable, int32_t sample_every) {
+  return guard(ctx, [&] {
+    qtt::Ctx &c = ctx->c;
+    c.resolve_events();
+    for (int k = 0; k < 2; ++k) {
+      c.kt.launches[k] = 0;
+      c.kt.timed[k] = 0;
+      c.kt.timed_ms[k] = 0.0;
+    }
+    c.kt.every = sample_every < 1 ? 1 : sample_every;
+    c.kt.on = enable != 0;
+    if (c.kt.on) {
+      c.kt.flop_ctr = (double *)c.raw("kt_flops", 2 * sizeof(double));
+      HIPC(hipMemsetAsync(c.kt.flop_ctr, 0, 2 * sizeof(double), c.stream));
+      c.sync();
+    }
+  });
+}
+
+int qtt_kernel_stats_read(qtt_ctx *ctx, int32_t kernel, qtt_kernel_stats *out) {
+  return guard(ctx, [&] {
+    if (!out || kernel < 0 || kernel > 1) qtt::fail(QTT_E_ARG, "kernel_stats_read: bad arguments");
+    qtt::Ctx &c = ctx->c;
+    c.resolve_events();
+    double fl[2] = {0.0, 0.0};
+    if (c.kt.flop_ctr)
+      HIPC(hipMemcpy(fl, c.kt.flop_ctr, 2 * sizeof(double), hipMemcpyDeviceToHost));
+    out->launches = c.kt.launches[kernel];
+    out->timed = c.kt.timed[kernel];
+    out->flops = fl[kernel];
+    out->timed_ms = c.kt.timed_ms[kernel];
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,330 @@
+// Context, workspace buffers, and the host-side construction of the
+// finite-difference MPOs (App. A carry logic, uploaded once per (n, dx)).
+#include "qtt_internal.h"
+
+#include <cmath>
+#include <cstring>
+#include <sstream>
+
+namespace qtt {
+
+void fail(int code, const std::string &msg) { throw Error{code, msg}; }
+
+void hip_check(hipError_t e, const char *what) {
+  if (e != hipSuccess) fail(QTT_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+double *Ctx::buf(const std::string &name, int64_t ndouble) {
+  return (double *)raw(name, (size_t)std::max<int64_t>(ndouble, 1) * sizeof(double));
+}
+
+void *Ctx::raw(const std::string &name, size_t bytes) {
+  DevBuf &b = bufs[name];
+  if (b.bytes < bytes) {
+    if (b.ptr) {
+      sync();
+      HIPC(hipFree(b.ptr));
+      b.ptr = nullptr;
+      b.bytes = 0;
+    }
+    const size_t alloc = ((bytes + bytes / 4 + 4095) / 4096) * 4096;
+    HIPC(hipMalloc(&b.ptr, alloc));
+    b.bytes = alloc;
+  }
+  return b.ptr;
+}
+
+void Ctx::sync() { HIPC(hipStreamSynchronize(stream)); }
+
+void Ctx::register_user(const void *p, size_t bytes) {
+  if (p && bytes) user_ranges.push_back({(uintptr_t)p, bytes});
+}
+
+void Ctx::check_range(const void *p, int64_t lo, int64_t hi, size_t esize,
+                      const char *what) const {
+  if (hi < lo) return;
+  const uintptr_t a = (uintptr_t)p + (intptr_t)(lo * (int64_t)esize);
+  const uintptr_t b = (uintptr_t)p + (intptr_t)((hi + 1) * (int64_t)esize);
+  auto inside = [&](uintptr_t base, size_t bytes) { return a >= base && b <= base + bytes; };
+  for (auto &kv : bufs)
+    if (kv.second.ptr && inside((uintptr_t)kv.second.ptr, kv.second.bytes)) return;
+  for (auto &r : user_ranges)
+    if (inside(r.first, r.second)) return;
+  for (size_t i = 0; i < owned_sizes.size(); ++i)
+    if (inside((uintptr_t)owned[i], owned_sizes[i])) return;
+  std::ostringstream s;
+  s << what << ": access [" << lo << ", " << hi << "] outside every known allocation";
+  fail(QTT_E_ARG, s.str());
+}
+
+double *Ctx::alloc_owned(int64_t ndouble) {
+  void *p = nullptr;
+  const size_t bytes = (size_t)std::max<int64_t>(ndouble, 1) * sizeof(double);
+  HIPC(hipMalloc(&p, bytes));
+  owned.push_back(p);
+  owned_sizes.push_back(bytes);
+  return (double *)p;
+}
+
+hipEvent_t Ctx::take_event() {
+  if (kt.pool.empty()) {
+    hipEvent_t e;
+    HIPC(hipEventCreate(&e));
+    return e;
+  }
+  hipEvent_t e = kt.pool.back();
+  kt.pool.pop_back();
+  return e;
+}
+
+void Ctx::resolve_events() {
+  sync();
+  for (int k = 0; k < 2; ++k) {
+    for (auto &pr : kt.pending[k]) {
+      float ms = 0.f;
+      HIPC(hipEventElapsedTime(&ms, pr.first, pr.second));
+      kt.timed_ms[k] += ms;
+      kt.timed[k] += 1;
+      kt.pool.push_back(pr.first);
+      kt.pool.push_back(pr.second);
+    }
+    kt.pending[k].clear();
+  }
+}
+
+Ctx::~Ctx() {
+  hipStreamSynchronize(stream);
+  for (int k = 0; k < 2; ++k)
+    for (auto &pr : kt.pending[k]) {
+      hipEventDestroy(pr.first);
+      hipEventDestroy(pr.second);
+    }
+  for (hipEvent_t e : kt.pool) hipEventDestroy(e);
+  for (auto &kv : bufs)
+    if (kv.second.ptr) hipFree(kv.second.ptr);
+  for (void *p : owned) hipFree(p);
+  if (pinned) hipHostFree(pinned);
+}
+
+Mps from_c(const qtt_mps &m) {
+  Mps r;
+  if (m.n < 1 || m.n > QTT_MAX_SITES) fail(QTT_E_ARG, "mps: n out of range");
+  r.n = m.n;
+  for (int k = 0; k <= m.n; ++k) {
+    r.bond[k] = m.bond[k];
+    if (m.bond[k] < 1) fail(QTT_E_SHAPE, "mps: bond < 1");
+  }
+  if (m.bond[0] != 1 || m.bond[m.n] != 1) fail(QTT_E_SHAPE, "mps: end bonds must be 1");
+  r.data = m.data;
+  r.capacity = m.capacity;
+  if (r.size() > r.capacity) {
+    std::ostringstream s;
+    s << "mps: capacity " << r.capacity << " < size " << r.size();
+    fail(QTT_E_CAPACITY, s.str());
+  }
+  if (!r.data) fail(QTT_E_ARG, "mps: null data");
+  return r;
+}
+
+void to_c(const Mps &m, qtt_mps *out) {
+  out->n = m.n;
+  for (int k = 0; k <= QTT_MAX_SITES; ++k) out->bond[k] = (k <= m.n) ? m.bond[k] : 0;
+}
+
+// ---------------------------------------------------------------- MPO construction
+// Central node C[a][w][w'][b] of the periodic first/second difference along
+// one axis: the finer sites request op = b (0: keep, 1: +1, 2: -1) on this
+// site's bit; a carry (wrap of the bit) is passed to the coarser site as a = op.
+static void carry_core(int axis, double *C /* 3*4*4*3 */) {
+  std::memset(C, 0, sizeof(double) * 144);
+  const int shift = (axis == 1) ? 1 : 0;
+  const int delta[3] = {0, 1, -1};
+  for (int op = 0; op < 3; ++op)
+    for (int w = 0; w < 4; ++w) {
+      const int bit = (w >> shift) & 1;
+      const int nb = bit + delta[op];
+      const int carry = (nb >= 0 && nb <= 1) ? 0 : op;
+      const int win = (w & ~(1 << shift)) | (((nb + 2) % 2) << shift);
+      C[((carry * 4 + w) * 4 + win) * 3 + op] = 1.0;
+    }
+}
+
+struct HostMpo {
+  int n;
+  std::vector<int> bond;
+  std::vector<std::vector<double>> core;  // [a][w][w'][b]
+};
+
+static HostMpo derivative(int n, int axis, int order, double dx) {
+  double C[144];
+  carry_core(axis, C);
+  double L[3] = {1.0, 1.0, 1.0};
+  double R[3];
+  if (order == 1) {
+    R[0] = 0.0;
+    R[1] = 1.0 / (2.0 * dx);
+    R[2] = -1.0 / (2.0 * dx);
+  } else {
+    R[0] = -2.0 / (dx * dx);
+    R[1] = 1.0 / (dx * dx);
+    R[2] = 1.0 / (dx * dx);
+  }
+  HostMpo m;
+  m.n = n;
+  m.bond.assign(n + 1, 3);
+  m.bond[0] = 1;
+  m.bond[n] = 1;
+  for (int k = 0; k < n; ++k) {
+    const int al = m.bond[k], ar = m.bond[k + 1];
+    std::vector<double> c((size_t)al * 16 * ar, 0.0);
+    for (int a = 0; a < al; ++a)
+      for (int w = 0; w < 4; ++w)
+        for (int v = 0; v < 4; ++v)
+          for (int b = 0; b < ar; ++b) {
+            double s = 0.0;
+            for (int aa = 0; aa < 3; ++aa) {
+              if (al != 1 && aa != a) continue;
+              const double la = (al == 1) ? L[aa] : 1.0;
+              for (int bb = 0; bb < 3; ++bb) {
+                if (ar != 1 && bb != b) continue;
+                const double rb = (ar == 1) ? R[bb] : 1.0;
+                s += la * C[((aa * 4 + w) * 4 + v) * 3 + bb] * rb;
+              }
+            }
+            c[((a * 4 + w) * 4 + v) * ar + b] = s;
+          }
+    m.core.push_back(c);
+  }
+  return m;
+}
+
+static HostMpo sum(const HostMpo &A, const HostMpo &B) {
+  HostMpo m;
+  m.n = A.n;
+  m.bond.resize(A.n + 1);
+  for (int k = 0; k <= A.n; ++k) m.bond[k] = (k == 0 || k == A.n) ? 1 : A.bond[k] + B.bond[k];
+  for (int k = 0; k < A.n; ++k) {
+    const int al = m.bond[k], ar = m.bond[k + 1];
+    std::vector<double> c((size_t)al * 16 * ar, 0.0);
+    const int a1 = A.bond[k], b1 = A.bond[k + 1], a2 = B.bond[k], b2 = B.bond[k + 1];
+    // A block at offset (0, 0); B block at offset (a1 or 0, b1 or 0)
+    const int oa = (k == 0) ? 0 : a1, ob = (k == A.n - 1) ? 0 : b1;
+    for (int a = 0; a < a1; ++a)
+      for (int wv = 0; wv < 16; ++wv)
+        for (int b = 0; b < b1; ++b) c[(a * 16 + wv) * ar + b] += A.core[k][(a * 16 + wv) * b1 + b];
+    for (int a = 0; a < a2; ++a)
+      for (int wv = 0; wv < 16; ++wv)
+        for (int b = 0; b < b2; ++b)
+          c[((oa + a) * 16 + wv) * ar + ob + b] += B.core[k][(a * 16 + wv) * b2 + b];
+    m.core.push_back(c);
+  }
+  return m;
+}
+
+// W1 W2 (W2 applied first)
+static HostMpo compose(const HostMpo &A, const HostMpo &B) {
+  HostMpo m;
+  m.n = A.n;
+  m.bond.resize(A.n + 1);
+  for (int k = 0; k <= A.n; ++k) m.bond[k] = A.bond[k] * B.bond[k];
+  for (int k = 0; k < A.n; ++k) {
+    const int a1 = A.bond[k], b1 = A.bond[k + 1], a2 = B.bond[k], b2 = B.bond[k + 1];
+    std::vector<double> c((size_t)a1 * a2 * 16 * b1 * b2, 0.0);
+    for (int x = 0; x < a1; ++x)
+      for (int y = 0; y < a2; ++y)
+        for (int w = 0; w < 4; ++w)
+          for (int v = 0; v < 4; ++v)
+            for (int p = 0; p < b1; ++p)
+              for (int q = 0; q < b2; ++q) {
+                double s = 0.0;
+                for (int u = 0; u < 4; ++u)
+                  s += A.core[k][((x * 4 + w) * 4 + u) * b1 + p] *
+                       B.core[k][((y * 4 + u) * 4 + v) * b2 + q];
+                c[((((int64_t)(x * a2 + y) * 4 + w) * 4 + v) * b1 + p) * b2 + q] = s;
+              }
+    m.core.push_back(c);
+  }
+  return m;
+}
+
+static HostMpo transpose(const HostMpo &A) {
+  HostMpo m = A;
+  for (int k = 0; k < A.n; ++k) {
+    const int al = A.bond[k], ar = A.bond[k + 1];
+    for (int a = 0; a < al; ++a)
+      for (int w = 0; w < 4; ++w)
+        for (int v = 0; v < 4; ++v)
+          for (int b = 0; b < ar; ++b)
+            m.core[k][((a * 4 + w) * 4 + v) * ar + b] = A.core[k][((a * 4 + v) * 4 + w) * ar + b];
+  }
+  return m;
+}
+
+void build_derivative_host(int n, int axis, int order, double dx, std::vector<double> &cores,
+                           int *bond) {
+  HostMpo m = derivative(n, axis, order, dx);
+  cores.clear();
+  for (int k = 0; k <= n; ++k) bond[k] = m.bond[k];
+  for (auto &c : m.core) cores.insert(cores.end(), c.begin(), c.end());
+}
+
+static std::shared_ptr<Mpo> upload(Ctx &c, const HostMpo &h) {
+  auto m = std::make_shared<Mpo>();
+  m->n = h.n;
+  for (int k = 0; k <= h.n; ++k) m->bond[k] = h.bond[k];
+  const int64_t tot = m->off(h.n);
+  std::vector<double> fwd, perm, rperm;
+  fwd.reserve(tot);
+  perm.reserve(tot);
+  rperm.reserve(tot);
+  for (int k = 0; k < h.n; ++k) {
+    const int al = h.bond[k], ar = h.bond[k + 1];
+    const std::vector<double> &C = h.core[k];
+    fwd.insert(fwd.end(), C.begin(), C.end());
+    std::vector<double> p(C.size()), rp(C.size());
+    for (int a = 0; a < al; ++a)
+      for (int w = 0; w < 4; ++w)
+        for (int v = 0; v < 4; ++v)
+          for (int b = 0; b < ar; ++b) {
+            const double x = C[((a * 4 + w) * 4 + v) * ar + b];
+            p[((a * 4 + v) * 4 + w) * ar + b] = x;   // [a][w'][w][b]
+            rp[((b * 4 + v) * 4 + w) * al + a] = x;  // [b][w'][w][a]
+          }
+    perm.insert(perm.end(), p.begin(), p.end());
+    rperm.insert(rperm.end(), rp.begin(), rp.end());
+  }
+  m->fwd = c.alloc_owned(tot);
+  m->perm = c.alloc_owned(tot);
+  m->rperm = c.alloc_owned(tot);
+  HIPC(hipMemcpy(m->fwd, fwd.data(), tot * sizeof(double), hipMemcpyHostToDevice));
+  HIPC(hipMemcpy(m->perm, perm.data(), tot * sizeof(double), hipMemcpyHostToDevice));
+  HIPC(hipMemcpy(m->rperm, rperm.data(), tot * sizeof(double), hipMemcpyHostToDevice));
+  return m;
+}
+
+// kinds: "D1", "D2", "D1T", "D2T", "LAP"
+std::shared_ptr<Mpo> get_mpo(Ctx &c, int n, const std::string &kind, double dx, int lap_mode) {
+  std::ostringstream key;
+  key.precision(17);
+  key << kind << ':' << n << ':' << dx << ':' << lap_mode;
+  auto it = c.mpos.find(key.str());
+  if (it != c.mpos.end()) return it->second;
+  HostMpo h;
+  if (kind == "D1") h = derivative(n, 1, 1, dx);
+  else if (kind == "D2") h = derivative(n, 2, 1, dx);
+  else if (kind == "D1T") h = transpose(derivative(n, 1, 1, dx));
+  else if (kind == "D2T") h = transpose(derivative(n, 2, 1, dx));
+  else if (kind == "LAP") {
+    if (lap_mode == 0)
+      h = sum(derivative(n, 1, 2, dx), derivative(n, 2, 2, dx));
+    else {
+      HostMpo a = derivative(n, 1, 1, dx), b = derivative(n, 2, 1, dx);
+      h = sum(compose(a, a), compose(b, b));
+    }
+  } else fail(QTT_E_ARG, "unknown mpo kind " + kind);
+  auto m = upload(c, h);
+  c.mpos[key.str()] = m;
+  return m;
+}
+
+}  // namespace qtt

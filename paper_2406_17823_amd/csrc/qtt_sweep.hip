@@ -1,0 +1,761 @@
+// One-site variational sweep (App. B) and the RK4 step as four Euler
+// minimisations (App. B, Table RK4, Eqs. U1-U4), orchestrated on the host,
+// every contraction on the device.
+//
+// Tensor networks.  With v_i in mixed-canonical form around site d, the local
+// system is  C_i + mu h^2 sum_j P_i^T D_i^T D_j P_j C_j = P_i^T a_i - h P_i^T B_i(b)
+// (Eqs. first/second).  Each term is a network <v_i| W_1 .. W_p |ket>:
+//   overlap      <v_i| a_i>                              (p = 0)
+//   convection   <v_i| b_j (.) D_j |b_i>, <v_i| D_j b_j (.) |b_i>   (p = 2)
+//   diffusion    <v_i| (D_1^2 + D_2^2) |b_i>             (p = 1)
+//   penalty      <v_i| D_i^T D_j |v_j>                   (p = 2, ket = trial)
+// The environment of a network at bond b has layout
+// [bra bond][layer bonds...][ket bond]; left environments (bonds <= d) and
+// right environments (bonds > d) share one array per network because the two
+// never hold the same bond at the same time.
+//
+// A "chain" contracts an environment with the ket core and then the layer
+// cores of one site (ket first), leaving the bra index open:
+//   T[bra][omega][layer bonds'][ket bond'].
+// The local right-hand side is T contracted with the opposite environment;
+// after the centre shift the new environment is the new bra core contracted
+// with the same T, so each site costs one chain per network.  Moving right
+// uses the cores as stored; moving left uses site-reversed copies
+// ([r][w][l]), so one chain routine serves both directions.
+#include "qtt_internal.h"
+#include "qtt_cg.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <sstream>
+
+namespace qtt {
+
+namespace {
+
+enum { LAYER_MPO = 0, LAYER_HAD = 1 };
+
+struct Layer {
+  int kind = LAYER_MPO;
+  const Mpo *mpo = nullptr;
+  const Mps *had = nullptr;
+  const double *had_rev = nullptr;
+  int bond(int b) const { return kind == LAYER_MPO ? mpo->bond[b] : had->bond[b]; }
+  const double *core(int d, bool rev) const {
+    if (kind == LAYER_MPO) return (rev ? mpo->rperm : mpo->perm) + mpo->off(d);
+    return (rev ? had_rev : had->data) + had->off(d);
+  }
+};
+
+struct Net {
+  int bra = 0;
+  int nl = 0;
+  Layer lay[2];
+  bool trial_ket = false;
+  int ket_comp = 0;
+  const Mps *ket = nullptr;
+  const double *ket_rev = nullptr;
+  double coef = 1.0;
+  bool f32 = false;
+  double *env = nullptr;
+  std::vector<int64_t> eoff;
+  double *T = nullptr;
+};
+
+struct Sweep {
+  Ctx &c;
+  const qtt_params &p;
+  int n;
+  Mps *v;                 // the two trial MPS
+  double *vrev[2];        // site-reversed copies of v
+  std::vector<Net> rhs;   // right-hand-side networks
+  std::vector<Net> pen;   // penalty networks, index 2*i + j
+  double mu_h2;
+  double *tmp = nullptr, *Tpen = nullptr;
+  int64_t tmp_size = 0;
+  CGState *st = nullptr;
+  CGState *st_host = nullptr;
+  double *part = nullptr;
+  qtt_stats *stats = nullptr;
+  int warn = 0;
+
+  Sweep(Ctx &cc, const qtt_params &pp) : c(cc), p(pp) {}
+
+  const Mps &ketmps(const Net &N) const { return N.trial_ket ? v[N.ket_comp] : *N.ket; }
+
+  int64_t env_size(const Net &N, int b) const {
+    int64_t s = (int64_t)v[N.bra].bond[b] * ketmps(N).bond[b];
+    for (int l = 0; l < N.nl; ++l) s *= N.lay[l].bond(b);
+    return s;
+  }
+
+  // largest intermediate of a chain through site d in either direction
+  int64_t chain_max(const Net &N, int d) const {
+    int64_t mx = 0;
+    for (int dir = 0; dir < 2; ++dir) {
+      const int bi = dir ? d + 1 : d, bo = dir ? d : d + 1;
+      const int64_t a = v[N.bra].bond[bi];
+      const int64_t g = ketmps(N).bond[bo];
+      int64_t s = a * 4 * g;
+      for (int l = 0; l < N.nl; ++l) s *= N.lay[l].bond(bi);
+      mx = std::max(mx, s);
+      for (int l = N.nl - 1; l >= 0; --l) {
+        int64_t pre = a, post = g;
+        for (int i = 0; i < l; ++i) pre *= N.lay[i].bond(bi);
+        for (int i = l + 1; i < N.nl; ++i) post *= N.lay[i].bond(bo);
+        mx = std::max(mx, pre * 4 * N.lay[l].bond(bo) * post);
+      }
+    }
+    return mx;
+  }
+
+  void gemm_for(const Net &N, const Gemm &g) {
+    if (N.f32) gemm_f32(c, g);
+    else gemm(c, g);
+  }
+
+  // T = chain through site d from the environment at the input bond
+  void chain(const Net &N, int d, bool rev, const double *E, const double *ketcore, double *T,
+             const int *skip) {
+    const int bi = rev ? d + 1 : d, bo = rev ? d : d + 1;
+    const int a = v[N.bra].bond[bi];
+    const Mps &kx = ketmps(N);
+    const int g = kx.bond[bi], gp = kx.bond[bo];
+    const int pl = N.nl;
+    int mi[2] = {1, 1}, mo[2] = {1, 1};
+    int64_t Pin = 1;
+    for (int l = 0; l < pl; ++l) {
+      mi[l] = N.lay[l].bond(bi);
+      mo[l] = N.lay[l].bond(bo);
+      Pin *= mi[l];
+    }
+    double *bufs[2] = {T, tmp};
+    int cur = (pl % 2 == 0) ? 0 : 1;
+    {
+      Gemm q;
+      q.M = (int)(a * Pin);
+      q.N = 4 * gp;
+      q.K = g;
+      q.A = E;
+      q.sAm = g;
+      q.sAk = 1;
+      q.B = ketcore;
+      q.sBk = 4 * gp;
+      q.sBn = 1;
+      q.C = bufs[cur];
+      q.sCm = 4 * gp;
+      q.sCn = 1;
+      q.skip = skip;
+      gemm_for(N, q);
+    }
+    for (int l = pl - 1; l >= 0; --l) {
+      int64_t pre = a, post = gp;
+      for (int i = 0; i < l; ++i) pre *= mi[i];
+      for (int i = l + 1; i < pl; ++i) post *= mo[i];
+      const double *src = bufs[cur];
+      double *dst = bufs[1 - cur];
+      const double *core = N.lay[l].core(d, rev);
+      Gemm q;
+      q.skip = skip;
+      if (N.lay[l].kind == LAYER_MPO) {
+        q.B1 = (int)pre;
+        q.M = (int)post;
+        q.N = 4 * mo[l];
+        q.K = 4 * mi[l];
+        q.A = src;
+        q.sAm = 1;
+        q.sAk = post;
+        q.sAb1 = 4 * mi[l] * post;
+        q.B = core;
+        q.sBk = 4 * mo[l];
+        q.sBn = 1;
+        q.C = dst;
+        q.sCm = 1;
+        q.sCn = post;
+        q.sCb1 = 4 * mo[l] * post;
+      } else {
+        q.B1 = (int)pre;
+        q.B2 = 4;
+        q.M = mo[l];
+        q.N = (int)post;
+        q.K = mi[l];
+        q.A = core;
+        q.sAm = 1;
+        q.sAk = 4 * mo[l];
+        q.sAb1 = 0;
+        q.sAb2 = mo[l];
+        q.B = src;
+        q.sBk = 4 * post;
+        q.sBn = 1;
+        q.sBb1 = 4 * mi[l] * post;
+        q.sBb2 = post;
+        q.C = dst;
+        q.sCm = post;
+        q.sCn = 1;
+        q.sCb1 = 4 * mo[l] * post;
+        q.sCb2 = mo[l] * post;
+      }
+      gemm_for(N, q);
+      cur = 1 - cur;
+    }
+  }
+
+  // out_i += alpha * (T contracted with the opposite environment)
+  void open_into(const Net &N, int d, bool rev, const double *T, double *out, double alpha,
+                 const int *skip) {
+    const int al = v[N.bra].bond[d], ar = v[N.bra].bond[d + 1];
+    const int bo = rev ? d : d + 1;
+    const int64_t rest = env_size(N, bo) / v[N.bra].bond[bo];
+    Gemm q;
+    q.skip = skip;
+    q.alpha = alpha;
+    q.beta = 1.0;
+    if (!rev) {
+      const double *R = N.env + N.eoff[d + 1];
+      q.M = 4 * al;
+      q.N = ar;
+      q.K = (int)rest;
+      q.A = T;
+      q.sAm = rest;
+      q.sAk = 1;
+      q.B = R;
+      q.sBk = 1;
+      q.sBn = rest;
+      q.C = out;
+      q.sCm = ar;
+      q.sCn = 1;
+    } else {
+      const double *L = N.env + N.eoff[d];
+      q.B2 = 4;
+      q.M = ar;
+      q.N = al;
+      q.K = (int)rest;
+      q.A = T;
+      q.sAm = 4 * rest;
+      q.sAk = 1;
+      q.sAb2 = rest;
+      q.B = L;
+      q.sBk = 1;
+      q.sBn = rest;
+      q.C = out;
+      q.sCm = 1;
+      q.sCn = 4 * ar;
+      q.sCb2 = ar;
+    }
+    gemm_for(N, q);
+  }
+
+  // environment at the output bond from T and the (new) bra core of site d
+  void env_from_T(const Net &N, int d, bool rev, const double *T) {
+    const int al = v[N.bra].bond[d], ar = v[N.bra].bond[d + 1];
+    const int bo = rev ? d : d + 1;
+    const int64_t rest = env_size(N, bo) / v[N.bra].bond[bo];
+    Gemm q;
+    if (!rev) {
+      q.M = ar;
+      q.N = (int)rest;
+      q.K = 4 * al;
+      q.A = v[N.bra].core(d);
+      q.sAm = 1;
+      q.sAk = ar;
+    } else {
+      q.M = al;
+      q.N = (int)rest;
+      q.K = 4 * ar;
+      q.A = vrev[N.bra] + v[N.bra].off(d);
+      q.sAm = 1;
+      q.sAk = al;
+    }
+    q.B = T;
+    q.sBk = rest;
+    q.sBn = 1;
+    q.C = N.env + N.eoff[bo];
+    q.sCm = rest;
+    q.sCn = 1;
+    gemm_for(N, q);
+  }
+
+  const double *ket_core(const Net &N, int d, bool rev) const {
+    if (N.trial_ket) return rev ? vrev[N.ket_comp] + v[N.ket_comp].off(d) : v[N.ket_comp].core(d);
+    return rev ? N.ket_rev + N.ket->off(d) : N.ket->core(d);
+  }
+
+  void reverse_core(const Mps &x, double *rev, int d) {
+    const int l = x.bond[d], r = x.bond[d + 1];
+    permute3(c, rev + x.off(d), x.core(d), r, 4, l, 1, r, 4 * (int64_t)r);
+  }
+
+  // environments and chain buffers live in context buffers that persist
+  // across calls (no allocation once the largest shapes have been seen)
+  void alloc(std::vector<Net *> all) {
+    int64_t tmx = 1;
+    int idx = 0;
+    for (Net *N : all) {
+      N->eoff.assign(n + 2, 0);
+      int64_t o = 0;
+      for (int b = 0; b <= n; ++b) {
+        N->eoff[b] = o;
+        o += env_size(*N, b);
+      }
+      N->env = c.buf("sw_env" + std::to_string(idx), o);
+      fill(c, N->env + N->eoff[0], 1, 1.0);
+      fill(c, N->env + N->eoff[n], 1, 1.0);
+      int64_t own = 1;
+      for (int d = 0; d < n; ++d) own = std::max(own, chain_max(*N, d));
+      tmx = std::max(tmx, own);
+      if (!N->trial_ket) N->T = c.buf("sw_T" + std::to_string(idx), own);
+      ++idx;
+    }
+    tmp = c.buf("sw_tmp", tmx);
+    Tpen = c.buf("sw_Tpen", tmx);
+    tmp_size = tmx;
+  }
+
+  int64_t centre_size(int i, int d) const { return v[i].core_size(d); }
+
+  void matvec(int d, const double *x, double *y, const int *skip) {
+    const int64_t s0 = centre_size(0, d), s1 = centre_size(1, d);
+    copy_skip(x, y, s0 + s1, skip);
+    const double *xs[2] = {x, x + s0};
+    double *ys[2] = {y, y + s0};
+    for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 2; ++j) {
+        Net &N = pen[2 * i + j];
+        chain(N, d, false, N.env + N.eoff[d], xs[j], Tpen, skip);
+        open_into(N, d, false, Tpen, ys[i], mu_h2, skip);
+      }
+  }
+
+  void copy_skip(const double *x, double *y, int64_t n_, const int *skip);
+
+  void local_solve(int d, bool rev) {
+    const int64_t s0 = centre_size(0, d), s1 = centre_size(1, d), ntot = s0 + s1;
+    double *rhs = c.buf("sw_rhs", ntot);
+    double *x = c.buf("sw_x", ntot);
+    double *r = c.buf("sw_r", ntot);
+    double *pp = c.buf("sw_p", ntot);
+    double *q = c.buf("sw_q", ntot);
+    fill(c, rhs, ntot, 0.0);
+    double *rh[2] = {rhs, rhs + s0};
+    auto t0 = std::chrono::steady_clock::now();
+    for (Net &N : rhs_nets()) {
+      const double *E = rev ? N.env + N.eoff[d + 1] : N.env + N.eoff[d];
+      chain(N, d, rev, E, ket_core(N, d, rev), N.T, nullptr);
+      open_into(N, d, rev, N.T, rh[N.bra], N.coef, nullptr);
+    }
+    HIPC(hipMemcpyAsync(x, v[0].core(d), s0 * sizeof(double), hipMemcpyDeviceToDevice, c.stream));
+    HIPC(hipMemcpyAsync(x + s0, v[1].core(d), s1 * sizeof(double), hipMemcpyDeviceToDevice,
+                        c.stream));
+    if (stats && c.timing) {
+      c.sync();
+      stats->phase_ms[2] += ms_since(t0);
+    }
+    t0 = std::chrono::steady_clock::now();
+    // CG (Sec. II.C): device-resident scalars, host checks once per chunk
+    st_host->rtol = p.cg_rtol;
+    st_host->maxit = p.cg_maxit;
+    st_host->counter = 0;
+    st_host->done = 0;
+    HIPC(hipMemcpyAsync(st, st_host, sizeof(CGState), hipMemcpyHostToDevice, c.stream));
+    matvec(d, x, q, nullptr);
+    cg_init(c, rhs, q, r, pp, x, ntot, st, part);
+    const int chunk = 8;
+    for (;;) {
+      for (int k = 0; k < chunk; ++k) {
+        matvec(d, pp, q, &st->done);
+        cg_alpha(c, pp, q, ntot, st, part);
+        cg_update(c, x, r, pp, q, ntot, st, part);
+        cg_pupdate(c, r, pp, ntot, st);
+      }
+      HIPC(hipMemcpyAsync(st_host, st, sizeof(CGState), hipMemcpyDeviceToHost, c.stream));
+      c.sync();
+      if (st_host->done) break;
+    }
+    if (stats) {
+      stats->cg_iters_total += st_host->iters;
+      stats->cg_iters_max = std::max(stats->cg_iters_max, st_host->iters);
+      stats->cg_solves += 1;
+      if (!st_host->converged) {
+        stats->cg_maxit_hits += 1;
+        warn = std::max(warn, (int)QTT_W_CG_MAXIT);
+      }
+      if (c.timing) stats->phase_ms[3] += ms_since(t0);
+    } else if (!st_host->converged) {
+      warn = std::max(warn, (int)QTT_W_CG_MAXIT);
+    }
+    HIPC(hipMemcpyAsync(v[0].core(d), x, s0 * sizeof(double), hipMemcpyDeviceToDevice, c.stream));
+    HIPC(hipMemcpyAsync(v[1].core(d), x + s0, s1 * sizeof(double), hipMemcpyDeviceToDevice,
+                        c.stream));
+  }
+
+  static double ms_since(std::chrono::steady_clock::time_point t0) {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0)
+        .count();
+  }
+
+  std::vector<Net> &rhs_nets() { return rhs; }
+
+  void shift(int d, bool right) {
+    ConstMatView A[2];
+    MatView Q[2], R[2];
+    int64_t ro = 0, to = 0;
+    int64_t rsz = 0, tsz = 0;
+    for (int i = 0; i < 2; ++i) {
+      const int l = v[i].bond[d], r = v[i].bond[d + 1];
+      rsz += right ? (int64_t)r * r : (int64_t)l * l;
+      tsz += right ? v[i].core_size(d + 1) : v[i].core_size(d - 1);
+    }
+    double *Rb = c.buf("sh_R", rsz);
+    double *Tb = c.buf("sh_T", tsz);
+    for (int i = 0; i < 2; ++i) {
+      const int l = v[i].bond[d], r = v[i].bond[d + 1];
+      if (right) {
+        A[i] = ConstMatView{v[i].core(d), 4 * l, r, r, 1};
+        Q[i] = MatView{v[i].core(d), 4 * l, r, r, 1};
+        R[i] = MatView{Rb + ro, r, r, r, 1};
+        ro += (int64_t)r * r;
+      } else {
+        A[i] = ConstMatView{v[i].core(d), 4 * r, l, 1, 4 * (int64_t)r};
+        Q[i] = MatView{v[i].core(d), 4 * r, l, 1, 4 * (int64_t)r};
+        R[i] = MatView{Rb + ro, l, l, l, 1};
+        ro += (int64_t)l * l;
+      }
+    }
+    qr_batch(c, 2, A, Q, R);
+    ro = 0;
+    for (int i = 0; i < 2; ++i) {
+      const int l = v[i].bond[d], r = v[i].bond[d + 1];
+      Gemm g;
+      if (right) {
+        const int r2 = v[i].bond[d + 2];
+        g.M = r;
+        g.N = 4 * r2;
+        g.K = r;
+        g.A = Rb + ro;
+        g.sAm = r;
+        g.sAk = 1;
+        g.B = v[i].core(d + 1);
+        g.sBk = 4 * r2;
+        g.sBn = 1;
+        g.C = Tb + to;
+        g.sCm = 4 * r2;
+        g.sCn = 1;
+        gemm(c, g);
+        HIPC(hipMemcpyAsync(v[i].core(d + 1), Tb + to, v[i].core_size(d + 1) * sizeof(double),
+                            hipMemcpyDeviceToDevice, c.stream));
+        ro += (int64_t)r * r;
+        to += v[i].core_size(d + 1);
+      } else {
+        const int lp = v[i].bond[d - 1];
+        g.M = 4 * lp;
+        g.N = l;
+        g.K = l;
+        g.A = v[i].core(d - 1);
+        g.sAm = l;
+        g.sAk = 1;
+        g.B = Rb + ro;
+        g.sBk = 1;
+        g.sBn = l;
+        g.C = Tb + to;
+        g.sCm = l;
+        g.sCn = 1;
+        gemm(c, g);
+        HIPC(hipMemcpyAsync(v[i].core(d - 1), Tb + to, v[i].core_size(d - 1) * sizeof(double),
+                            hipMemcpyDeviceToDevice, c.stream));
+        ro += (int64_t)l * l;
+        to += v[i].core_size(d - 1);
+        reverse_core(v[i], vrev[i], d);
+      }
+    }
+  }
+
+  void update_envs(int d, bool rev) {
+    for (Net &N : rhs) env_from_T(N, d, rev, N.T);
+    for (Net &N : pen) {
+      const double *E = rev ? N.env + N.eoff[d + 1] : N.env + N.eoff[d];
+      chain(N, d, rev, E, ket_core(N, d, rev), Tpen, nullptr);
+      env_from_T(N, d, rev, Tpen);
+    }
+  }
+
+  double norm_sq_site0() {
+    double *o = c.buf("sw_norm", 2);
+    dot(c, v[0].core(0), v[0].core(0), v[0].core_size(0), o);
+    dot(c, v[1].core(0), v[1].core(0), v[1].core_size(0), o + 1);
+    double h[2];
+    HIPC(hipMemcpyAsync(h, o, 2 * sizeof(double), hipMemcpyDeviceToHost, c.stream));
+    c.sync();
+    return h[0] + h[1];
+  }
+};
+
+__global__ void k_copy_skip(const double *x, double *y, int64_t n, const int *skip) {
+  if (skip && *skip) return;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = x[i];
+}
+
+void Sweep::copy_skip(const double *x, double *y, int64_t n_, const int *skip) {
+  c.check_range(x, 0, n_ - 1, 8, "copy_skip x");
+  c.check_range(y, 0, n_ - 1, 8, "copy_skip y");
+  unsigned g = (unsigned)std::min<int64_t>(1024, std::max<int64_t>(1, (n_ + 255) / 256));
+  hipLaunchKernelGGL(k_copy_skip, dim3(g), dim3(256), 0, c.stream, x, y, n_, skip);
+  HIPC(hipGetLastError());
+}
+
+void check_profile(const Mps &x, const char *what) {
+  for (int k = 0; k < x.n; ++k)
+    if (x.bond[k] > 4 * x.bond[k + 1] || x.bond[k + 1] > 4 * x.bond[k])
+      fail(QTT_E_SHAPE, std::string(what) + ": bond profile must satisfy b[k] <= 4 b[k+1] and "
+                                            "b[k+1] <= 4 b[k]");
+}
+
+}  // namespace
+
+void project(Ctx &c, const Mps a[2], const Mps b[2], double h, const qtt_params &p, Mps v[2],
+             qtt_stats *st, int stage) {
+  const int n = v[0].n;
+  for (int i = 0; i < 2; ++i) {
+    if (a[i].n != n || b[i].n != n || v[i].n != n) fail(QTT_E_SHAPE, "project: site counts differ");
+    check_profile(v[i], "project: guess");
+  }
+  if (n < 2) fail(QTT_E_UNSUPPORTED, "project: n < 2");
+  if (p.max_sweeps < 1 || p.cg_maxit < 1) fail(QTT_E_ARG, "project: max_sweeps/cg_maxit < 1");
+  if (p.prec != QTT_PREC_F64 && p.prec != QTT_PREC_F32) fail(QTT_E_ARG, "project: prec");
+  if (p.precond != QTT_PC_NONE) fail(QTT_E_UNSUPPORTED, "project: preconditioner not built");
+
+  auto t0 = std::chrono::steady_clock::now();
+  Sweep S(c, p);
+  S.n = n;
+  S.v = v;
+  S.stats = st;
+  S.mu_h2 = p.mu * h * h;
+
+  mps_right_canonicalize(c, {&v[0], &v[1]});
+
+  // site-reversed copies of the fixed MPS and the trial MPS
+  double *arev[2], *brev[2];
+  for (int i = 0; i < 2; ++i) {
+    arev[i] = c.buf("sw_arev" + std::to_string(i), a[i].size());
+    brev[i] = c.buf("sw_brev" + std::to_string(i), b[i].size());
+    S.vrev[i] = c.buf("sw_vrev" + std::to_string(i), v[i].size());
+    for (int d = 0; d < n; ++d) {
+      S.reverse_core(a[i], arev[i], d);
+      S.reverse_core(b[i], brev[i], d);
+      S.reverse_core(v[i], S.vrev[i], d);
+    }
+  }
+  auto D1 = get_mpo(c, n, "D1", p.dx, 0), D2 = get_mpo(c, n, "D2", p.dx, 0);
+  auto D1T = get_mpo(c, n, "D1T", p.dx, 0), D2T = get_mpo(c, n, "D2T", p.dx, 0);
+  auto LAP = get_mpo(c, n, "LAP", p.dx, p.lap_mode);
+  const Mpo *D[2] = {D1.get(), D2.get()};
+  const Mpo *DT[2] = {D1T.get(), D2T.get()};
+  const bool f32 = (p.prec == QTT_PREC_F32);
+
+  for (int i = 0; i < 2; ++i) {
+    Net ov;
+    ov.bra = i;
+    ov.nl = 0;
+    ov.ket = &a[i];
+    ov.ket_rev = arev[i];
+    ov.coef = 1.0;
+    S.rhs.push_back(ov);
+    for (int j = 0; j < 2; ++j)
+      for (int form = 0; form < 2; ++form) {
+        // form 0: b_j (.) D_j b_i ; form 1: D_j (b_j (.) b_i) ; weight -h/2
+        Net N;
+        N.bra = i;
+        N.nl = 2;
+        Layer H;
+        H.kind = LAYER_HAD;
+        H.had = &b[j];
+        H.had_rev = brev[j];
+        Layer Dl;
+        Dl.kind = LAYER_MPO;
+        Dl.mpo = D[j];
+        N.lay[0] = form == 0 ? H : Dl;
+        N.lay[1] = form == 0 ? Dl : H;
+        N.ket = &b[i];
+        N.ket_rev = brev[i];
+        N.coef = -0.5 * h;
+        N.f32 = f32;
+        S.rhs.push_back(N);
+      }
+    Net df;
+    df.bra = i;
+    df.nl = 1;
+    df.lay[0].kind = LAYER_MPO;
+    df.lay[0].mpo = LAP.get();
+    df.ket = &b[i];
+    df.ket_rev = brev[i];
+    df.coef = h / p.re;
+    S.rhs.push_back(df);
+  }
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) {
+      Net N;
+      N.bra = i;
+      N.nl = 2;
+      N.lay[0].kind = LAYER_MPO;
+      N.lay[0].mpo = DT[i];
+      N.lay[1].kind = LAYER_MPO;
+      N.lay[1].mpo = D[j];
+      N.trial_ket = true;
+      N.ket_comp = j;
+      N.coef = S.mu_h2;
+      S.pen.push_back(N);
+    }
+
+  // device state: CG scalars, partial sums
+  S.st = (CGState *)c.raw("sw_cgstate", sizeof(CGState));
+  S.part = c.buf("sw_part", 2048);
+  if (!c.pinned) HIPC(hipHostMalloc((void **)&c.pinned, 4096 * sizeof(double), 0));
+  S.st_host = (CGState *)c.pinned;
+
+  std::vector<Net *> all;
+  for (Net &N : S.rhs) all.push_back(&N);
+  for (Net &N : S.pen) all.push_back(&N);
+  S.alloc(all);
+
+  // right environments, sites n-1 .. 1
+  for (int d = n - 1; d >= 1; --d)
+    for (Net *N : all) {
+      S.chain(*N, d, true, N->env + N->eoff[d + 1], S.ket_core(*N, d, true), S.Tpen, nullptr);
+      S.env_from_T(*N, d, true, S.Tpen);
+    }
+  if (st && c.timing) {
+    c.sync();
+    st->phase_ms[1] += Sweep::ms_since(t0);
+  }
+
+  double nrm_prev = S.norm_sq_site0();
+  int sweeps = 0;
+  bool converged = false;
+  for (int s = 0; s < p.max_sweeps; ++s) {
+    for (int d = 0; d < n - 1; ++d) {
+      S.local_solve(d, false);
+      auto t1 = std::chrono::steady_clock::now();
+      S.shift(d, true);
+      S.update_envs(d, false);
+      if (st && c.timing) {
+        c.sync();
+        st->phase_ms[5] += Sweep::ms_since(t1);
+      }
+    }
+    for (int d = n - 1; d >= 1; --d) {
+      S.local_solve(d, true);
+      auto t1 = std::chrono::steady_clock::now();
+      S.shift(d, false);
+      S.update_envs(d, true);
+      if (st && c.timing) {
+        c.sync();
+        st->phase_ms[5] += Sweep::ms_since(t1);
+      }
+    }
+    ++sweeps;
+    const double nrm = S.norm_sq_site0();
+    if (p.sweep_rtol > 0.0 && std::fabs(nrm - nrm_prev) <= p.sweep_rtol * nrm) {
+      converged = true;
+      break;
+    }
+    nrm_prev = nrm;
+  }
+  if (p.sweep_rtol > 0.0 && !converged) S.warn = std::max(S.warn, (int)QTT_W_SWEEP_MAXIT);
+  if (st && stage >= 0 && stage < 4) st->sweeps[stage] += sweeps;
+  c.sync();
+  if (S.warn) throw Error{S.warn, "project: warning"};
+}
+
+void rk4_step(Ctx &c, Mps u[2], const qtt_params &p, qtt_stats *st) {
+  const int n = u[0].n;
+  if (u[1].n != n) fail(QTT_E_SHAPE, "rk4: site counts differ");
+  for (int i = 0; i < 2; ++i) {
+    check_profile(u[i], "rk4: state");
+    Mps cap;
+    cap.n = n;
+    cap.bond[0] = cap.bond[n] = 1;
+    for (int k = 1; k < n; ++k)
+      cap.bond[k] = std::min(p.chi, 1 << std::min(30, 2 * std::min(k, n - k)));
+    if (u[i].capacity < cap.size()) {
+      std::ostringstream s;
+      s << "rk4: state capacity must hold " << cap.size() << " doubles";
+      fail(QTT_E_CAPACITY, s.str());
+    }
+  }
+  static const double hs[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
+  static const double bc[3][2] = {{3.0, 0.25}, {1.5, 0.625}, {3.0, 0.25}};
+  int warn = 0;
+  Mps a[2], U[4][2], bb[2], sum[2];
+  for (int i = 0; i < 2; ++i) {
+    const int64_t sz = u[i].size();
+    a[i] = u[i];
+    a[i].data = c.buf("rk4_a" + std::to_string(i), sz);
+    a[i].capacity = sz;
+    scale_copy(c, a[i].data, u[i].data, sz, 1.0);
+    scale_copy(c, a[i].data, u[i].data, u[i].core_size(0), 0.25);
+    for (int k = 0; k < 4; ++k) {
+      U[k][i] = u[i];
+      U[k][i].data = c.buf("rk4_U" + std::to_string(k) + std::to_string(i), sz);
+      U[k][i].capacity = sz;
+    }
+    // capacities of the 2-term and 4-term sums (bonds add)
+    Mps two = u[i], four = u[i];
+    for (int k = 1; k < n; ++k) {
+      two.bond[k] = 2 * u[i].bond[k];
+      four.bond[k] = 4 * u[i].bond[k];
+    }
+    bb[i].data = c.buf("rk4_b" + std::to_string(i), two.size());
+    bb[i].capacity = two.size();
+    sum[i].data = c.buf("rk4_sum" + std::to_string(i), four.size());
+    sum[i].capacity = four.size();
+  }
+  auto run = [&](auto &&f) {
+    try {
+      f();
+    } catch (Error &e) {
+      if (e.code > 0) warn = std::max(warn, e.code);
+      else throw;
+    }
+  };
+  for (int k = 0; k < 4; ++k) {
+    const Mps *b = u;
+    if (k > 0) {
+      auto t0 = std::chrono::steady_clock::now();
+      for (int i = 0; i < 2; ++i) {
+        const double coef[2] = {bc[k - 1][0], bc[k - 1][1]};
+        Mps xs[2] = {U[k - 1][i], u[i]};
+        mps_add(c, 2, coef, xs, bb[i]);
+      }
+      double disc[2];
+      mps_truncate(c, {&bb[0], &bb[1]}, p.chi, p.svd_rtol, disc);
+      if (st) {
+        st->discarded_sq += disc[0] + disc[1];
+        st->phase_ms[0] += std::chrono::duration<double, std::milli>(
+                               std::chrono::steady_clock::now() - t0).count();
+      }
+      b = bb;
+    }
+    for (int i = 0; i < 2; ++i) mps_copy(c, a[i], U[k][i]);
+    run([&] { project(c, a, b, hs[k] * p.dt, p, U[k], st, k); });
+  }
+  auto t0 = std::chrono::steady_clock::now();
+  for (int i = 0; i < 2; ++i) {
+    const double coef[4] = {1.0, 1.0, 1.0, 1.0};
+    Mps xs[4] = {U[0][i], U[1][i], U[2][i], U[3][i]};
+    mps_add(c, 4, coef, xs, sum[i]);
+  }
+  double disc[2];
+  mps_truncate(c, {&sum[0], &sum[1]}, p.chi, p.svd_rtol, disc);
+  for (int i = 0; i < 2; ++i) mps_copy(c, sum[i], u[i]);
+  c.sync();
+  if (st) {
+    st->discarded_sq += disc[0] + disc[1];
+    st->phase_ms[0] +=
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+  if (warn) throw Error{warn, "rk4: warning"};
+}
+
+}  // namespace qtt

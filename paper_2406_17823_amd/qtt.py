@@ -1,0 +1,345 @@
+"""Python binding of libqtt.so (argument marshalling only).
+
+Every operation runs in the HIP library; this module only converts torch
+device tensors and Python lists to the C descriptors of include/qtt.h.
+Importing it on a machine without the built library raises immediately.
+"""
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+MAX_SITES = 16
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, 'libqtt.so')
+
+PREC_F64, PREC_F32 = 0, 1
+PC_NONE, PC_BLOCK_JACOBI, PC_LEARNED = 0, 1, 2
+W_CG_MAXIT, W_SWEEP_MAXIT, W_PRECOND_FALLBACK = 1, 2, 3
+ERRORS = {-1: 'QTT_E_ARG', -2: 'QTT_E_SHAPE', -3: 'QTT_E_CAPACITY', -4: 'QTT_E_HIP',
+          -5: 'QTT_E_NAN', -6: 'QTT_E_UNSUPPORTED'}
+
+
+class c_mps(ctypes.Structure):
+    _fields_ = [('n', ctypes.c_int32), ('bond', ctypes.c_int32 * (MAX_SITES + 1)),
+                ('capacity', ctypes.c_int64), ('data', ctypes.c_void_p)]
+
+
+class c_mpo(ctypes.Structure):
+    _fields_ = [('n', ctypes.c_int32), ('bond', ctypes.c_int32 * (MAX_SITES + 1)),
+                ('capacity', ctypes.c_int64), ('data', ctypes.c_void_p)]
+
+
+class c_params(ctypes.Structure):
+    _fields_ = [('re', ctypes.c_double), ('dt', ctypes.c_double), ('mu', ctypes.c_double),
+                ('dx', ctypes.c_double), ('chi', ctypes.c_int32), ('svd_rtol', ctypes.c_double),
+                ('cg_rtol', ctypes.c_double), ('cg_maxit', ctypes.c_int32),
+                ('sweep_rtol', ctypes.c_double), ('max_sweeps', ctypes.c_int32),
+                ('lap_mode', ctypes.c_int32), ('prec', ctypes.c_int32), ('precond', ctypes.c_int32)]
+
+
+class c_stats(ctypes.Structure):
+    _fields_ = [('sweeps', ctypes.c_int32 * 4), ('cg_iters_total', ctypes.c_int32),
+                ('cg_iters_max', ctypes.c_int32), ('cg_solves', ctypes.c_int32),
+                ('cg_maxit_hits', ctypes.c_int32), ('fallbacks', ctypes.c_int32),
+                ('discarded_sq', ctypes.c_double), ('phase_ms', ctypes.c_double * 8)]
+
+    def as_dict(self):
+        return dict(sweeps=list(self.sweeps), cg_iters_total=self.cg_iters_total,
+                    cg_iters_max=self.cg_iters_max, cg_solves=self.cg_solves,
+                    cg_maxit_hits=self.cg_maxit_hits, fallbacks=self.fallbacks,
+                    discarded_sq=self.discarded_sq, phase_ms=list(self.phase_ms))
+
+
+class c_kstats(ctypes.Structure):
+    _fields_ = [('launches', ctypes.c_int64), ('timed', ctypes.c_int64),
+                ('flops', ctypes.c_double), ('timed_ms', ctypes.c_double)]
+
+
+SYMBOLS = ['qtt_kernel_timing', 'qtt_kernel_stats_read', 'qtt_ctx_create', 'qtt_ctx_destroy', 'qtt_last_error', 'qtt_mps_size',
+           'qtt_mpo_derivative', 'qtt_add', 'qtt_truncate', 'qtt_apply_mpo', 'qtt_hadamard',
+           'qtt_inner', 'qtt_to_dense', 'qtt_from_dense', 'qtt_project', 'qtt_rk4_step']
+
+_lib = None
+
+
+def lib():
+    """The loaded libqtt.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f'libqtt.so not built ({LIB_PATH}); run __graft_entry__.build()')
+    L = ctypes.CDLL(LIB_PATH)
+    P, I32, I64, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    pm, pmo = ctypes.POINTER(c_mps), ctypes.POINTER(c_mpo)
+    pd = ctypes.POINTER(ctypes.c_double)
+    sig = {
+        'qtt_ctx_create': (I32, [ctypes.POINTER(P), I32, P]),
+        'qtt_ctx_destroy': (None, [P]),
+        'qtt_last_error': (ctypes.c_char_p, [P]),
+        'qtt_mps_size': (I64, [I32, ctypes.POINTER(I32)]),
+        'qtt_mpo_derivative': (I32, [P, I32, I32, I32, D, pmo]),
+        'qtt_add': (I32, [P, I32, pd, pm, pm]),
+        'qtt_truncate': (I32, [P, pm, I32, D, pd]),
+        'qtt_apply_mpo': (I32, [P, pmo, pm, I32, D, pm, pd]),
+        'qtt_hadamard': (I32, [P, pm, pm, I32, D, pm, pd]),
+        'qtt_inner': (I32, [P, pm, pm, pd]),
+        'qtt_to_dense': (I32, [P, pm, P]),
+        'qtt_from_dense': (I32, [P, P, I32, I32, D, pm]),
+        'qtt_project': (I32, [P, pm, pm, D, ctypes.POINTER(c_params), pm,
+                              ctypes.POINTER(c_stats)]),
+        'qtt_rk4_step': (I32, [P, pm, ctypes.POINTER(c_params), ctypes.POINTER(c_stats)]),
+        'qtt_kernel_timing': (I32, [P, I32, I32]),
+        'qtt_kernel_stats_read': (I32, [P, I32, ctypes.POINTER(c_kstats)]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+class QttError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f'{ERRORS.get(code, code)}: {msg}')
+        self.code = code
+
+
+class Context:
+    """One library context on a device, enqueuing on torch's current stream."""
+
+    def __init__(self, device=0):
+        L = lib()
+        self.device = device
+        with torch.cuda.device(device):
+            stream = torch.cuda.current_stream().cuda_stream
+        h = ctypes.c_void_p()
+        rc = L.qtt_ctx_create(ctypes.byref(h), device, ctypes.c_void_p(stream))
+        if rc != 0:
+            raise QttError(rc, 'qtt_ctx_create failed')
+        self.h = h
+        self.last_warning = 0
+
+    def close(self):
+        if getattr(self, 'h', None):
+            lib().qtt_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def check(self, rc, what):
+        if rc < 0:
+            msg = lib().qtt_last_error(self.h).decode()
+            raise QttError(rc, f'{what}: {msg}')
+        self.last_warning = rc
+        return rc
+
+
+def mps_size(bonds):
+    return int(sum(bonds[k] * 4 * bonds[k + 1] for k in range(len(bonds) - 1)))
+
+
+class MPS:
+    """A device MPS: bonds [1, ..., 1] and a float64 torch tensor holding the
+    packed cores (capacity >= the packed size)."""
+
+    def __init__(self, bonds, data):
+        self.bonds = list(int(b) for b in bonds)
+        self.data = data
+        assert data.dtype == torch.float64 and data.is_cuda
+
+    @property
+    def n(self):
+        return len(self.bonds) - 1
+
+    @property
+    def size(self):
+        return mps_size(self.bonds)
+
+    @classmethod
+    def empty(cls, bonds, capacity=None, device='cuda'):
+        cap = mps_size(bonds) if capacity is None else int(capacity)
+        return cls(bonds, torch.zeros(max(cap, 1), dtype=torch.float64, device=device))
+
+    @classmethod
+    def from_cores(cls, cores, capacity=None, device='cuda'):
+        bonds = [int(cores[0].shape[0])] + [int(c.shape[2]) for c in cores]
+        flat = np.concatenate([np.ascontiguousarray(c, dtype=np.float64).ravel() for c in cores])
+        cap = flat.size if capacity is None else max(int(capacity), flat.size)
+        t = torch.zeros(cap, dtype=torch.float64, device=device)
+        t[:flat.size] = torch.from_numpy(flat).to(device)
+        return cls(bonds, t)
+
+    def cores(self):
+        flat = self.data[:self.size].cpu().numpy()
+        out, o = [], 0
+        for k in range(self.n):
+            l, r = self.bonds[k], self.bonds[k + 1]
+            out.append(flat[o:o + l * 4 * r].reshape(l, 4, r).copy())
+            o += l * 4 * r
+        return out
+
+    def struct(self):
+        s = c_mps()
+        s.n = self.n
+        for k, b in enumerate(self.bonds):
+            s.bond[k] = b
+        s.capacity = self.data.numel()
+        s.data = self.data.data_ptr()
+        return s
+
+    def take(self, s):
+        self.bonds = [int(s.bond[k]) for k in range(s.n + 1)]
+
+
+class MPO:
+    def __init__(self, bonds, data):
+        self.bonds = list(bonds)
+        self.data = data
+
+    def struct(self):
+        s = c_mpo()
+        s.n = len(self.bonds) - 1
+        for k, b in enumerate(self.bonds):
+            s.bond[k] = b
+        s.capacity = self.data.numel()
+        s.data = self.data.data_ptr()
+        return s
+
+
+def params(re, dt, chi, dx, mu=2.5e5, svd_rtol=1e-12, cg_rtol=1e-12, cg_maxit=1000,
+           sweep_rtol=0.0, max_sweeps=2, lap_mode=0, prec=PREC_F64, precond=PC_NONE):
+    p = c_params()
+    p.re, p.dt, p.mu, p.dx, p.chi = re, dt, mu, dx, chi
+    p.svd_rtol, p.cg_rtol, p.cg_maxit = svd_rtol, cg_rtol, cg_maxit
+    p.sweep_rtol, p.max_sweeps, p.lap_mode = sweep_rtol, max_sweeps, lap_mode
+    p.prec, p.precond = prec, precond
+    return p
+
+
+# ---------------------------------------------------------------- operations
+def mpo_derivative(ctx, n, axis, order, dx):
+    data = torch.zeros(n * 144, dtype=torch.float64, device=f'cuda:{ctx.device}')
+    s = c_mpo()
+    s.capacity = data.numel()
+    s.data = data.data_ptr()
+    ctx.check(lib().qtt_mpo_derivative(ctx.h, n, axis, order, dx, ctypes.byref(s)),
+              'mpo_derivative')
+    return MPO([s.bond[k] for k in range(n + 1)], data)
+
+
+def add(ctx, coefs, xs, y=None):
+    k = len(xs)
+    bonds = [1] + [sum(x.bonds[s] for x in xs) for s in range(1, xs[0].n)] + [1]
+    if y is None:
+        y = MPS.empty(bonds, device=xs[0].data.device)
+    arr = (c_mps * k)(*[x.struct() for x in xs])
+    co = (ctypes.c_double * k)(*[float(c) for c in coefs])
+    ys = y.struct()
+    ctx.check(lib().qtt_add(ctx.h, k, co, arr, ctypes.byref(ys)), 'add')
+    y.take(ys)
+    return y
+
+
+def truncate(ctx, y, chi, svd_rtol=1e-12):
+    ys = y.struct()
+    disc = ctypes.c_double()
+    ctx.check(lib().qtt_truncate(ctx.h, ctypes.byref(ys), chi, svd_rtol, ctypes.byref(disc)),
+              'truncate')
+    y.take(ys)
+    return disc.value
+
+
+def apply_mpo(ctx, W, x, chi=0, svd_rtol=1e-12, y=None):
+    if y is None:
+        y = MPS.empty([a * b for a, b in zip(W.bonds, x.bonds)], device=x.data.device)
+    ws, xs, ys = W.struct(), x.struct(), y.struct()
+    disc = ctypes.c_double()
+    ctx.check(lib().qtt_apply_mpo(ctx.h, ctypes.byref(ws), ctypes.byref(xs), chi, svd_rtol,
+                                  ctypes.byref(ys), ctypes.byref(disc)), 'apply_mpo')
+    y.take(ys)
+    return y, disc.value
+
+
+def hadamard(ctx, a, b, chi=0, svd_rtol=1e-12, y=None):
+    if y is None:
+        y = MPS.empty([p * q for p, q in zip(a.bonds, b.bonds)], device=a.data.device)
+    as_, bs, ys = a.struct(), b.struct(), y.struct()
+    disc = ctypes.c_double()
+    ctx.check(lib().qtt_hadamard(ctx.h, ctypes.byref(as_), ctypes.byref(bs), chi, svd_rtol,
+                                 ctypes.byref(ys), ctypes.byref(disc)), 'hadamard')
+    y.take(ys)
+    return y, disc.value
+
+
+def inner(ctx, x, y):
+    out = ctypes.c_double()
+    xs, ys = x.struct(), y.struct()
+    ctx.check(lib().qtt_inner(ctx.h, ctypes.byref(xs), ctypes.byref(ys), ctypes.byref(out)),
+              'inner')
+    return out.value
+
+
+def to_dense(ctx, x):
+    N = 1 << x.n
+    g = torch.empty((N, N), dtype=torch.float64, device=x.data.device)
+    xs = x.struct()
+    ctx.check(lib().qtt_to_dense(ctx.h, ctypes.byref(xs), ctypes.c_void_p(g.data_ptr())),
+              'to_dense')
+    return g
+
+
+def canonical_bonds(n, chi):
+    return [1] + [min(chi, 4 ** k, 4 ** (n - k)) for k in range(1, n)] + [1]
+
+
+def from_dense(ctx, grid, chi, svd_rtol=1e-12, capacity=None):
+    N = grid.shape[0]
+    n = N.bit_length() - 1
+    cap = mps_size(canonical_bonds(n, chi)) if capacity is None else capacity
+    out = MPS.empty(canonical_bonds(n, chi), capacity=cap, device=grid.device)
+    g = grid.contiguous()
+    os_ = out.struct()
+    ctx.check(lib().qtt_from_dense(ctx.h, ctypes.c_void_p(g.data_ptr()), n, chi, svd_rtol,
+                                   ctypes.byref(os_)), 'from_dense')
+    out.take(os_)
+    return out
+
+
+def project(ctx, a, b, h, prm, v, stats=True):
+    A = (c_mps * 2)(a[0].struct(), a[1].struct())
+    B = (c_mps * 2)(b[0].struct(), b[1].struct())
+    V = (c_mps * 2)(v[0].struct(), v[1].struct())
+    st = c_stats()
+    rc = ctx.check(lib().qtt_project(ctx.h, A, B, h, ctypes.byref(prm), V, ctypes.byref(st)),
+                   'project')
+    v[0].take(V[0])
+    v[1].take(V[1])
+    return rc, st.as_dict()
+
+
+def rk4_step(ctx, u, prm):
+    U = (c_mps * 2)(u[0].struct(), u[1].struct())
+    st = c_stats()
+    rc = ctx.check(lib().qtt_rk4_step(ctx.h, U, ctypes.byref(prm), ctypes.byref(st)), 'rk4_step')
+    u[0].take(U[0])
+    u[1].take(U[1])
+    return rc, st.as_dict()
+
+
+def kernel_timing(ctx, enable=True, sample_every=1):
+    ctx.check(lib().qtt_kernel_timing(ctx.h, 1 if enable else 0, sample_every), 'kernel_timing')
+
+
+def kernel_stats(ctx, kernel):
+    """kernel 0: float64 GEMM, 1: float32 GEMM."""
+    s = c_kstats()
+    ctx.check(lib().qtt_kernel_stats_read(ctx.h, kernel, ctypes.byref(s)), 'kernel_stats_read')
+    return dict(launches=s.launches, timed=s.timed, flops=s.flops, timed_ms=s.timed_ms)
