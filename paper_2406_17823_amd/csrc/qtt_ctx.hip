@@ -302,7 +302,7 @@ static std::shared_ptr<Mpo> upload(Ctx &c, const HostMpo &h) {
   return m;
 }
 
-// kinds: "D1", "D2", "D1T", "D2T", "LAP"
+// kinds: "D1", "D2", "D1T", "D2T", "P11", "P12", "P21", "P22" (D_i^T D_j), "LAP"
 std::shared_ptr<Mpo> get_mpo(Ctx &c, int n, const std::string &kind, double dx, int lap_mode) {
   std::ostringstream key;
   key.precision(17);
@@ -314,7 +314,11 @@ std::shared_ptr<Mpo> get_mpo(Ctx &c, int n, const std::string &kind, double dx, 
   else if (kind == "D2") h = derivative(n, 2, 1, dx);
   else if (kind == "D1T") h = transpose(derivative(n, 1, 1, dx));
   else if (kind == "D2T") h = transpose(derivative(n, 2, 1, dx));
-  else if (kind == "LAP") {
+  else if (kind.size() == 3 && kind[0] == 'P') {
+    // penalty pair D_i^T D_j (i, j in {1, 2}) as one MPO of bond 9
+    const int i = kind[1] - '0', j = kind[2] - '0';
+    h = compose(transpose(derivative(n, i, 1, dx)), derivative(n, j, 1, dx));
+  } else if (kind == "LAP") {
     if (lap_mode == 0)
       h = sum(derivative(n, 1, 2, dx), derivative(n, 2, 2, dx));
     else {

@@ -153,6 +153,10 @@ void place_block(Ctx &c, double *dst, int dl, int dr, const double *src, int l, 
 void hadamard_core(Ctx &c, double *y, const double *a, int la, int ra, const double *b, int lb,
                    int rb);
 void mpo_core(Ctx &c, double *y, const double *W, int wl, int wr, const double *x, int l, int r);
+// one MPO layer of a network chain (sparse, HBM-streaming):
+// Tout[p][w_out][m'][q] = sum W[m][w_in][w_out][m'] T[p][m][w_in][q]
+void mpo_layer(Ctx &c, const double *T, double *Tout, const double *W, int64_t pre, int mi, int mo,
+               int64_t post, const int *skip);
 void morton_gather(Ctx &c, double *grid, const double *vec, int n);   // vec (Morton) -> grid
 void morton_scatter(Ctx &c, double *vec, const double *grid, int n);  // grid -> vec (Morton)
 void dot(Ctx &c, const double *x, const double *y, int64_t n, double *out_dev);

@@ -8,7 +8,8 @@
 //   overlap      <v_i| a_i>                              (p = 0)
 //   convection   <v_i| b_j (.) D_j |b_i>, <v_i| D_j b_j (.) |b_i>   (p = 2)
 //   diffusion    <v_i| (D_1^2 + D_2^2) |b_i>             (p = 1)
-//   penalty      <v_i| D_i^T D_j |v_j>                   (p = 2, ket = trial)
+//   penalty      <v_i| D_i^T D_j |v_j>                   (p = 1, the pair
+//                composed into one MPO of bond 9; ket = trial)
 // The environment of a network at bond b has layout
 // [bra bond][layer bonds...][ket bond]; left environments (bonds <= d) and
 // right environments (bonds > d) share one array per network because the two
@@ -156,25 +157,14 @@ struct Sweep {
       const double *src = bufs[cur];
       double *dst = bufs[1 - cur];
       const double *core = N.lay[l].core(d, rev);
+      if (N.lay[l].kind == LAYER_MPO) {
+        mpo_layer(c, src, dst, core, pre, mi[l], mo[l], post, skip);
+        cur = 1 - cur;
+        continue;
+      }
       Gemm q;
       q.skip = skip;
-      if (N.lay[l].kind == LAYER_MPO) {
-        q.B1 = (int)pre;
-        q.M = (int)post;
-        q.N = 4 * mo[l];
-        q.K = 4 * mi[l];
-        q.A = src;
-        q.sAm = 1;
-        q.sAk = post;
-        q.sAb1 = 4 * mi[l] * post;
-        q.B = core;
-        q.sBk = 4 * mo[l];
-        q.sBn = 1;
-        q.C = dst;
-        q.sCm = 1;
-        q.sCn = post;
-        q.sCb1 = 4 * mo[l] * post;
-      } else {
+      {
         q.B1 = (int)pre;
         q.B2 = 4;
         q.M = mo[l];
@@ -548,10 +538,8 @@ void project(Ctx &c, const Mps a[2], const Mps b[2], double h, const qtt_params 
     }
   }
   auto D1 = get_mpo(c, n, "D1", p.dx, 0), D2 = get_mpo(c, n, "D2", p.dx, 0);
-  auto D1T = get_mpo(c, n, "D1T", p.dx, 0), D2T = get_mpo(c, n, "D2T", p.dx, 0);
   auto LAP = get_mpo(c, n, "LAP", p.dx, p.lap_mode);
   const Mpo *D[2] = {D1.get(), D2.get()};
-  const Mpo *DT[2] = {D1T.get(), D2T.get()};
   const bool f32 = (p.prec == QTT_PREC_F32);
 
   for (int i = 0; i < 2; ++i) {
@@ -593,15 +581,18 @@ void project(Ctx &c, const Mps a[2], const Mps b[2], double h, const qtt_params 
     df.coef = h / p.re;
     S.rhs.push_back(df);
   }
+  std::shared_ptr<Mpo> PEN[2][2];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j)
+      PEN[i][j] = get_mpo(c, n, "P" + std::to_string(i + 1) + std::to_string(j + 1), p.dx, 0);
   for (int i = 0; i < 2; ++i)
     for (int j = 0; j < 2; ++j) {
+      // <v_i| D_i^T D_j |v_j> with the two MPOs composed into one of bond 9
       Net N;
       N.bra = i;
-      N.nl = 2;
+      N.nl = 1;
       N.lay[0].kind = LAYER_MPO;
-      N.lay[0].mpo = DT[i];
-      N.lay[1].kind = LAYER_MPO;
-      N.lay[1].mpo = D[j];
+      N.lay[0].mpo = PEN[i][j].get();
       N.trial_ket = true;
       N.ket_comp = j;
       N.coef = S.mu_h2;
