@@ -20,10 +20,12 @@
  *   QTT_E_CAPACITY and the required number of doubles in qtt_last_error().
  *
  * Streams
- *   Every call is enqueued on the stream given to qtt_ctx_create and
- *   returns after the stream has finished the call's work unless stated
- *   otherwise, so host-side results (discarded weights, statistics, bonds)
- *   are valid on return.
+ *   Every call is enqueued on the stream given to qtt_ctx_create (NULL: a
+ *   stream owned by the context, which waits for the null stream at the
+ *   start of every call) and returns after that stream has finished the
+ *   call's work, so host-side results (discarded weights, statistics, bonds)
+ *   and device outputs are valid on return.  Inner CG iterations are
+ *   replayed from captured HIP graphs (QTT_GRAPHS=0 disables this).
  *
  * Errors
  *   0 = success, > 0 = warning (result valid), < 0 = error (outputs
@@ -204,6 +206,44 @@ typedef struct {
 
 int qtt_kernel_timing(qtt_ctx *ctx, int32_t enable, int32_t sample_every);
 int qtt_kernel_stats_read(qtt_ctx *ctx, int32_t kernel, qtt_kernel_stats *out);
+
+/* Learned preconditioner of the local CG solves (an addition: the paper
+ * solves the local systems of App. B, Eq. big_LS, by plain CG).  With
+ * params.precond = QTT_PC_LEARNED every (alpha, beta) position of a centre
+ * tensor gets a 4 x 4 block M = L L^T over the physical index, L lower
+ * triangular with exp on the diagonal, from a shared-weight perceptron
+ * QTT_PC_IN -> QTT_PC_WIDTH -> QTT_PC_WIDTH -> QTT_PC_OUT (ReLU; bfloat16
+ * MFMA products, float64 weights) fed with the normalised diagonal block of
+ * the local matrix at that position, log of its mean diagonal, the site,
+ * log10(mu h^2 / dx^2), the component and the two bond sizes.  PCG runs with
+ * M; afterwards the float64 residual of the result is recomputed and plain
+ * CG continues from it whenever it misses cg_rtol (stats->fallbacks,
+ * return QTT_W_PRECOND_FALLBACK).  QTT_PC_BLOCK_JACOBI uses the exact
+ * inverse of the same diagonal blocks instead (the baseline).
+ *
+ * qtt_precond_config: train_per_solve > 0 turns on training: before every
+ * local solve the network takes that many Adam steps (learning rate lr) on
+ * the loss ||z - M A z||^2 / ||z||^2 of the solve's own operator A with a
+ * fresh Gaussian probe z drawn on the device; 0 = inference only.
+ * reset != 0 (or the first call) draws the weights from `seed` and clears
+ * the Adam state.  Weights persist in the context. */
+enum { QTT_PC_IN = 16, QTT_PC_WIDTH = 256, QTT_PC_OUT = 10 };
+int qtt_precond_config(qtt_ctx *ctx, int32_t train_per_solve, double lr, uint64_t seed,
+                       int32_t reset);
+/* Number of parameters, Adam steps taken, probe loss of the first and of the
+ * latest training step (-1 before any).  Any pointer may be NULL. */
+int qtt_precond_info(qtt_ctx *ctx, int64_t *nparam, int64_t *steps, double *first_loss,
+                     double *last_loss);
+/* Copy the float64 parameters (W1 [W][IN], b1 [W], W2 [W][W], b2 [W],
+ * W3 [OUT][W], b3 [OUT], row-major, packed in this order) to (set = 0) or
+ * from (set = 1) the host array w of n = nparam doubles. */
+int qtt_precond_weights(qtt_ctx *ctx, int32_t set, double *w, int64_t n);
+/* Network forward and backward on given rows (device pointers): X is
+ * npos x QTT_PC_IN, dY and Y are npos x QTT_PC_OUT, grad holds nparam
+ * doubles.  Y = network output, grad = gradient of sum(dY * Y) with respect
+ * to the parameters (layout as in qtt_precond_weights). */
+int qtt_precond_grad(qtt_ctx *ctx, const double *X, int64_t npos, const double *dY, double *Y,
+                     double *grad);
 
 #ifdef __cplusplus
 }

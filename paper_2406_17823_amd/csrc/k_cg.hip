@@ -82,6 +82,7 @@ __global__ __launch_bounds__(CG_THREADS) void k_cg_init(const double *rhs, const
     sum_parts(part, gridDim.x, rr, bn);
     st->rr = rr;
     st->rz = rr;
+    st->rr_new = rr;
     st->bnorm2 = bn;
     st->tol2 = st->rtol * st->rtol * bn;
     st->iters = 0;
@@ -139,8 +140,16 @@ __global__ __launch_bounds__(CG_THREADS) void k_cg_update(double *x, double *r, 
     double rr, dummy;
     sum_parts(part, gridDim.x, rr, dummy);
     st->iters += 1;
+    // plain CG: rr <- previous r.r (for beta), rr_new = rz <- new r.r (for
+    // beta and the next alpha); PCG keeps rz = r.z for pcg_next
+    if (!st->precond) {
+      st->rr = st->rz;
+      st->rz = rr;
+    }
     st->rr_new = rr;
-    if (rr <= st->tol2) {
+    if (!(rr == rr)) {
+      st->done = 1;  // NaN: stop, not converged
+    } else if (rr <= st->tol2) {
       st->done = 1;
       st->converged = 1;
     } else if (st->iters >= st->maxit) {
@@ -158,13 +167,6 @@ __global__ __launch_bounds__(CG_THREADS) void k_cg_pupdate(const double *r, doub
   for (int64_t i = blockIdx.x * (int64_t)CG_THREADS + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * CG_THREADS)
     p[i] = r[i] + beta * p[i];
-}
-
-// the scalar bookkeeping after p has been updated by every block
-__global__ void k_cg_shift_rr(CGState *st) {
-  if (st->done) return;
-  st->rr = st->rr_new;
-  st->rz = st->rr_new;
 }
 
 // preconditioned: rz_new = r . z ; beta = rz_new / rz ; p = z + beta p (two kernels)
@@ -261,7 +263,6 @@ void cg_update(Ctx &c, double *x, double *r, const double *p, const double *q, i
 
 void cg_pupdate(Ctx &c, const double *r, double *p, int64_t n, CGState *st) {
   hipLaunchKernelGGL(k_cg_pupdate, dim3(cg_grid(n)), dim3(CG_THREADS), 0, c.stream, r, p, n, st);
-  hipLaunchKernelGGL(k_cg_shift_rr, dim3(1), dim3(1), 0, c.stream, st);
   HIPC(hipGetLastError());
 }
 

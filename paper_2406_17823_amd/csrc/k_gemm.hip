@@ -1,36 +1,53 @@
-// Strided batched GEMM on CDNA4 matrix cores.
+// Strided, batched and grouped GEMM on CDNA4 matrix cores.
 //
 // Every tensor-network contraction of the library (environment updates,
 // local right-hand sides, the penalty matvec, QR/SVD factor products) is
-// expressed as C[b1,b2](m,n) = alpha sum_k A(m,k) B(k,n) + beta C with
+// expressed as C[b1,b2](m,n) = alpha sum_k A(m,k) B(k,n) + beta X with
 // arbitrary element strides, so that no tensor is ever transposed in HBM.
+// One launch carries up to GEMM_GROUP independent problems (the four penalty
+// pair terms of a CG matvec go out as one launch per step).
 //
 // Tiling: 64 x 64 output tile per 256-thread workgroup (4 wave64s in a 2 x 2
 // arrangement, 32 x 32 per wave = 2 x 2 blocks of 16 x 16), K staged through
 // LDS in slices of 16.  The loader picks the thread-to-element map from the
 // operand's unit-stride dimension so that global loads stay coalesced.
 // float64: v_mfma_f64_16x16x4_f64; float32: v_mfma_f32_16x16x4_f32 with
-// float64 operands rounded to float32 on the way into LDS.
+// float64 operands rounded to float32 on the way into LDS (float64 sums of
+// the float32 16-deep slices).
+// When the output tiles cannot fill the 256 compute units, K is split across
+// workgroups; the partial tiles are summed in split order by a second kernel
+// (deterministic).  That kernel also sums several problems into one output
+// (the two pair terms j = 1, 2 of y_i) and adds a separate input X.
 #include "qtt_internal.h"
+
+#include <cstdio>
 
 namespace qtt {
 
 typedef double d4v __attribute__((ext_vector_type(4)));
 typedef float f4v __attribute__((ext_vector_type(4)));
+typedef __bf16 b4v __attribute__((ext_vector_type(4)));
 
 namespace {
 
 constexpr int MT = 64, NT = 64, KT = 16, PADM = 1;
 
-struct GemmK {
-  int M, N, K, B1, B2, tm, tn;
+struct Prob {
+  int M, N, K, B1, B2, tm, tn, ksplit, kchunk, direct;
+  int64_t block0;
   const double *A;
   int64_t sAm, sAk, sAb1, sAb2;
   const double *B;
   int64_t sBk, sBn, sBb1, sBb2;
-  double *C;
+  double *C;  // direct mode: C = alpha acc + beta C
   int64_t sCm, sCn, sCb1, sCb2;
   double alpha, beta;
+  double *part;  // partial mode: part[ks][b][m][n]
+};
+
+struct GemmK {
+  int np;
+  Prob p[GEMM_GROUP];
   const int *skip;
   double *flop_ctr;
   double flops;
@@ -79,13 +96,54 @@ __device__ inline void mfma_step<float>(const float (*As)[MT + PADM], const floa
     f[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, f[1][0], 0, 0, 0);
     f[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, f[1][1], 0, 0, 0);
   }
-  // the K slice is accumulated in float32, slices are summed in float64
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) acc[i][j][r] += (double)f[i][j][r];
+}
+
+// bfloat16 operands, float32 accumulation (v_mfma_f32_16x16x16_bf16): lane l
+// holds A[l % 16][4 (l / 16) + 0..3] and B[4 (l / 16) + 0..3][l % 16]
+template <>
+__device__ inline void mfma_step<__bf16>(const __bf16 (*As)[MT + PADM],
+                                         const __bf16 (*Bs)[NT + PADM], int lane, int wm, int wn,
+                                         d4v (&acc)[2][2]) {
+  f4v f[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+      f[i][j] = f4v{0.f, 0.f, 0.f, 0.f};
+  b4v a0, a1, b0, b1;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int kk = 4 * (lane >> 4) + e;
+    a0[e] = As[kk][wm * 32 + (lane & 15)];
+    a1[e] = As[kk][wm * 32 + 16 + (lane & 15)];
+    b0[e] = Bs[kk][wn * 32 + (lane & 15)];
+    b1[e] = Bs[kk][wn * 32 + 16 + (lane & 15)];
+  }
+  f[0][0] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a0, b0, f[0][0], 0, 0, 0);
+  f[0][1] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a0, b1, f[0][1], 0, 0, 0);
+  f[1][0] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1, b0, f[1][0], 0, 0, 0);
+  f[1][1] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1, b1, f[1][1], 0, 0, 0);
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[i][j][r] += (double)f[i][j][r];
+}
+
+template <typename T>
+__device__ inline T to_op(double v) {
+  return (T)v;
+}
+template <>
+__device__ inline __bf16 to_op<__bf16>(double v) {
+  return (__bf16)(float)v;
 }
 
 template <typename T>
@@ -100,20 +158,29 @@ __global__ __launch_bounds__(256) void k_gemm(GemmK g) {
   const int wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
 
-  int64_t bid = blockIdx.x;
-  const int tiles = g.tm * g.tn;
-  const int t = (int)(bid % tiles);
-  const int64_t bb = bid / tiles;
-  const int b1 = (int)(bb % g.B1);
-  const int b2 = (int)(bb / g.B1);
-  const int m0 = (t % g.tm) * MT;
-  const int n0 = (t / g.tm) * NT;
+  int pi = 0;
+#pragma unroll
+  for (int i = 1; i < GEMM_GROUP; ++i)
+    if (i < g.np && (int64_t)blockIdx.x >= g.p[i].block0) pi = i;
+  const Prob &P = g.p[pi];
 
-  const double *A = g.A + b1 * g.sAb1 + b2 * g.sAb2;
-  const double *B = g.B + b1 * g.sBb1 + b2 * g.sBb2;
-  double *C = g.C + b1 * g.sCb1 + b2 * g.sCb2;
-  const bool a_m_unit = (g.sAm == 1);
-  const bool b_n_unit = (g.sBn == 1);
+  const int64_t bid = (int64_t)blockIdx.x - P.block0;
+  const int tiles = P.tm * P.tn;
+  const int t = (int)(bid % tiles);
+  int64_t bb = bid / tiles;
+  const int ks = (int)(bb % P.ksplit);
+  bb /= P.ksplit;
+  const int b1 = (int)(bb % P.B1);
+  const int b2 = (int)(bb / P.B1);
+  const int kbeg = ks * P.kchunk;
+  const int kend = min(P.K, kbeg + P.kchunk);
+  const int m0 = (t % P.tm) * MT;
+  const int n0 = (t / P.tm) * NT;
+
+  const double *A = P.A + b1 * P.sAb1 + b2 * P.sAb2;
+  const double *B = P.B + b1 * P.sBb1 + b2 * P.sBb2;
+  const bool a_m_unit = (P.sAm == 1);
+  const bool b_n_unit = (P.sBn == 1);
 
   d4v acc[2][2];
 #pragma unroll
@@ -121,7 +188,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmK g) {
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = d4v{0.0, 0.0, 0.0, 0.0};
 
-  for (int k0 = 0; k0 < g.K; k0 += KT) {
+  for (int k0 = kbeg; k0 < kend; k0 += KT) {
 #pragma unroll
     for (int i = 0; i < (MT * KT) / 256; ++i) {
       const int idx = tid + 256 * i;
@@ -135,8 +202,8 @@ __global__ __launch_bounds__(256) void k_gemm(GemmK g) {
       }
       const int gm = m0 + mm, gk = k0 + kk;
       double v = 0.0;
-      if (gm < g.M && gk < g.K) v = A[gm * g.sAm + gk * g.sAk];
-      As[kk][mm] = (T)v;
+      if (gm < P.M && gk < kend) v = A[gm * P.sAm + gk * P.sAk];
+      As[kk][mm] = to_op<T>(v);
     }
 #pragma unroll
     for (int i = 0; i < (NT * KT) / 256; ++i) {
@@ -151,8 +218,8 @@ __global__ __launch_bounds__(256) void k_gemm(GemmK g) {
       }
       const int gn = n0 + nn, gk = k0 + kk;
       double v = 0.0;
-      if (gn < g.N && gk < g.K) v = B[gk * g.sBk + gn * g.sBn];
-      Bs[kk][nn] = (T)v;
+      if (gn < P.N && gk < kend) v = B[gk * P.sBk + gn * P.sBn];
+      Bs[kk][nn] = to_op<T>(v);
     }
     __syncthreads();
     mfma_step<T>(As, Bs, lane, wm, wn, acc);
@@ -170,73 +237,183 @@ __global__ __launch_bounds__(256) void k_gemm(GemmK g) {
         const int row = (sizeof(T) == 8) ? (4 * r + (lane >> 4)) : ((lane >> 4) * 4 + r);
         const int gm = m0 + wm * 32 + i * 16 + row;
         const int gn = n0 + wn * 32 + j * 16 + (lane & 15);
-        if (gm < g.M && gn < g.N) {
-          double *cp = C + gm * g.sCm + gn * g.sCn;
-          double v = g.alpha * acc[i][j][r];
-          if (g.beta != 0.0) v += g.beta * *cp;
-          *cp = v;
+        if (gm < P.M && gn < P.N) {
+          if (!P.direct) {
+            const int64_t bidx = (int64_t)b2 * P.B1 + b1;
+            P.part[(((int64_t)ks * P.B1 * P.B2 + bidx) * P.M + gm) * P.N + gn] = acc[i][j][r];
+          } else {
+            double *cp = P.C + b1 * P.sCb1 + b2 * P.sCb2 + gm * P.sCm + gn * P.sCn;
+            double v = P.alpha * acc[i][j][r];
+            if (P.beta != 0.0) v += P.beta * *cp;
+            *cp = v;
+          }
         }
       }
 }
 
-template <typename T>
-void launch(Ctx &c, const Gemm &q) {
-  if (q.M <= 0 || q.N <= 0 || q.B1 <= 0 || q.B2 <= 0) return;
-  GemmK g;
-  g.M = q.M;
-  g.N = q.N;
-  g.K = q.K;
-  g.B1 = q.B1;
-  g.B2 = q.B2;
-  g.tm = (q.M + MT - 1) / MT;
-  g.tn = (q.N + NT - 1) / NT;
-  g.A = q.A;
-  g.sAm = q.sAm;
-  g.sAk = q.sAk;
-  g.sAb1 = q.sAb1;
-  g.sAb2 = q.sAb2;
-  g.B = q.B;
-  g.sBk = q.sBk;
-  g.sBn = q.sBn;
-  g.sBb1 = q.sBb1;
-  g.sBb2 = q.sBb2;
-  g.C = q.C;
-  g.sCm = q.sCm;
-  g.sCn = q.sCn;
-  g.sCb1 = q.sCb1;
-  g.sCb2 = q.sCb2;
-  g.alpha = q.alpha;
-  g.beta = q.beta;
-  g.skip = q.skip;
-  {
-    int64_t lo = 0, hi = 0;
-    span(lo, hi, q.M, q.sAm);
-    span(lo, hi, q.K, q.sAk);
-    span(lo, hi, q.B1, q.sAb1);
-    span(lo, hi, q.B2, q.sAb2);
-    if (q.K > 0) c.check_range(q.A, lo, hi, sizeof(double), "gemm A");
-    lo = hi = 0;
-    span(lo, hi, q.K, q.sBk);
-    span(lo, hi, q.N, q.sBn);
-    span(lo, hi, q.B1, q.sBb1);
-    span(lo, hi, q.B2, q.sBb2);
-    if (q.K > 0) c.check_range(q.B, lo, hi, sizeof(double), "gemm B");
-    lo = hi = 0;
-    span(lo, hi, q.M, q.sCm);
-    span(lo, hi, q.N, q.sCn);
-    span(lo, hi, q.B1, q.sCb1);
-    span(lo, hi, q.B2, q.sCb2);
-    c.check_range(q.C, lo, hi, sizeof(double), "gemm C");
+struct RedSrc {
+  const double *part;
+  int ksplit;
+};
+struct RedOut {
+  double *C;
+  int64_t sCm, sCn, sCb1, sCb2;
+  const double *X;  // beta term input (may be C)
+  int64_t sXm, sXn, sXb1, sXb2;
+  int M, N, B1, B2;
+  double alpha, beta;
+  int nsrc;
+  RedSrc src[2];
+  int64_t elem0;
+};
+struct RedK {
+  int nout;
+  RedOut o[GEMM_GROUP];
+  const int *skip;
+  int64_t total;
+};
+
+// out = alpha * (sum over sources, splits in order) + beta * X
+__global__ __launch_bounds__(256) void k_splitk_reduce(RedK R) {
+  if (R.skip && *R.skip) return;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < R.total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    int oi = 0;
+#pragma unroll
+    for (int k = 1; k < GEMM_GROUP; ++k)
+      if (k < R.nout && e >= R.o[k].elem0) oi = k;
+    const RedOut &O = R.o[oi];
+    const int64_t idx = e - O.elem0;
+    const int64_t per = (int64_t)O.M * O.N;
+    const int64_t tot = per * O.B1 * O.B2;
+    double s = 0.0;
+    for (int q = 0; q < O.nsrc; ++q)
+      for (int k = 0; k < O.src[q].ksplit; ++k) s += O.src[q].part[(int64_t)k * tot + idx];
+    const int64_t bidx = idx / per;
+    const int64_t r = idx % per;
+    const int gm = (int)(r / O.N), gn = (int)(r % O.N);
+    const int b1 = (int)(bidx % O.B1), b2 = (int)(bidx / O.B1);
+    double v = O.alpha * s;
+    if (O.beta != 0.0)
+      v += O.beta * O.X[b1 * O.sXb1 + b2 * O.sXb2 + gm * O.sXm + gn * O.sXn];
+    O.C[b1 * O.sCb1 + b2 * O.sCb2 + gm * O.sCm + gn * O.sCn] = v;
   }
-  const int64_t blocks = (int64_t)g.tm * g.tn * g.B1 * g.B2;
+}
+
+void check_operands(Ctx &c, const Gemm &q) {
+  int64_t lo = 0, hi = 0;
+  span(lo, hi, q.M, q.sAm);
+  span(lo, hi, q.K, q.sAk);
+  span(lo, hi, q.B1, q.sAb1);
+  span(lo, hi, q.B2, q.sAb2);
+  if (q.K > 0) c.check_range(q.A, lo, hi, sizeof(double), "gemm A");
+  lo = hi = 0;
+  span(lo, hi, q.K, q.sBk);
+  span(lo, hi, q.N, q.sBn);
+  span(lo, hi, q.B1, q.sBb1);
+  span(lo, hi, q.B2, q.sBb2);
+  if (q.K > 0) c.check_range(q.B, lo, hi, sizeof(double), "gemm B");
+  lo = hi = 0;
+  span(lo, hi, q.M, q.sCm);
+  span(lo, hi, q.N, q.sCn);
+  span(lo, hi, q.B1, q.sCb1);
+  span(lo, hi, q.B2, q.sCb2);
+  c.check_range(q.C, lo, hi, sizeof(double), "gemm C");
+}
+
+// np problems; problem i belongs to output group group[i] (a group holds
+// one or two problems that share C; X[group] is the beta input, nullptr = C).
+template <typename T>
+void launch_group(Ctx &c, int np, const Gemm *q, int ngroups, const int *group,
+                  const double *const *X, const int *skip) {
+  GemmK g{};
+  g.np = 0;
+  g.skip = skip;
+  g.flops = 0.0;
+  const int kind = (sizeof(T) == 8) ? 0 : (sizeof(T) == 4 ? 1 : 2);
+  int64_t blocks = 0;
+  int nsrc[GEMM_GROUP] = {0};
+  for (int i = 0; i < np; ++i) {
+    if (group[i] < 0 || group[i] >= ngroups || ngroups > GEMM_GROUP)
+      fail(QTT_E_ARG, "gemm group: bad output group");
+    nsrc[group[i]] += 1;
+  }
+  int64_t part_need = 0;
+  int64_t part_off[GEMM_GROUP] = {0};
+  int keep[GEMM_GROUP];
+  int64_t grp_tiles = 0;
+  for (int i = 0; i < np; ++i)
+    grp_tiles += (int64_t)((q[i].M + MT - 1) / MT) * ((q[i].N + NT - 1) / NT) * q[i].B1 * q[i].B2;
+  for (int i = 0; i < np; ++i) {
+    const Gemm &s = q[i];
+    keep[i] = -1;
+    if (s.M <= 0 || s.N <= 0 || s.B1 <= 0 || s.B2 <= 0) continue;
+    check_operands(c, s);
+    Prob &P = g.p[g.np];
+    keep[i] = g.np++;
+    P.M = s.M;
+    P.N = s.N;
+    P.K = s.K;
+    P.B1 = s.B1;
+    P.B2 = s.B2;
+    P.tm = (s.M + MT - 1) / MT;
+    P.tn = (s.N + NT - 1) / NT;
+    P.A = s.A;
+    P.sAm = s.sAm;
+    P.sAk = s.sAk;
+    P.sAb1 = s.sAb1;
+    P.sAb2 = s.sAb2;
+    P.B = s.B;
+    P.sBk = s.sBk;
+    P.sBn = s.sBn;
+    P.sBb1 = s.sBb1;
+    P.sBb2 = s.sBb2;
+    P.C = s.C;
+    P.sCm = s.sCm;
+    P.sCn = s.sCn;
+    P.sCb1 = s.sCb1;
+    P.sCb2 = s.sCb2;
+    P.alpha = s.alpha;
+    P.beta = s.beta;
+    P.part = nullptr;
+    g.flops += 2.0 * s.M * (double)s.N * s.K * s.B1 * s.B2;
+    const int64_t out_tiles = (int64_t)P.tm * P.tn * P.B1 * P.B2;
+    P.ksplit = 1;
+    P.kchunk = std::max(s.K, 1);
+    // split K when the group's output tiles cannot fill the compute units
+    if (grp_tiles < 256 && s.K >= 4 * KT) {
+      const int64_t want = (512 + grp_tiles - 1) / grp_tiles;
+      const int64_t maxs = s.K / (2 * KT);
+      int ks = (int)std::max<int64_t>(1, std::min<int64_t>(want, maxs));
+      if (ks > 1) {
+        int chunk = (s.K + ks - 1) / ks;
+        chunk = ((chunk + KT - 1) / KT) * KT;
+        ks = (s.K + chunk - 1) / chunk;
+        P.ksplit = ks;
+        P.kchunk = chunk;
+      }
+    }
+    P.direct = (P.ksplit == 1 && nsrc[group[i]] == 1 && X[group[i]] == nullptr) ? 1 : 0;
+    part_off[g.np - 1] = part_need;
+    if (!P.direct) part_need += (int64_t)P.ksplit * P.M * P.N * P.B1 * P.B2;
+    P.block0 = blocks;
+    blocks += out_tiles * P.ksplit;
+  }
+  if (g.np == 0) return;
   if (blocks > 0x7fffffffLL) fail(QTT_E_UNSUPPORTED, "gemm grid too large");
-  const int kind = (sizeof(T) == 8) ? 0 : 1;
-  g.flop_ctr = nullptr;
-  g.flops = 2.0 * q.M * (double)q.N * q.K * q.B1 * q.B2;
+  if (part_need > ((int64_t)64 << 20)) fail(QTT_E_UNSUPPORTED, "gemm split-K buffer too large");
+  if (part_need > 0) {
+    double *part = c.buf(kind == 0 ? "gemm_splitk64" : (kind == 1 ? "gemm_splitk32" : "gemm_splitk16"), part_need);
+    for (int i = 0; i < g.np; ++i)
+      if (!g.p[i].direct) g.p[i].part = part + part_off[i];
+  }
+
   bool timed = false;
   std::pair<hipEvent_t, hipEvent_t> ev;
-  if (c.kt.on) {
-    g.flop_ctr = c.kt.flop_ctr + kind;
+  if (c.kt.on && kind < 2) g.flop_ctr = c.kt.flop_ctr + kind;
+  if (c.capturing) {
+    if (kind < 2) c.cap_launches[kind] += 1;
+  } else if (c.kt.on && kind < 2) {
     timed = (c.kt.launches[kind] % c.kt.every) == 0;
     c.kt.launches[kind] += 1;
     if (timed) {
@@ -246,17 +423,118 @@ void launch(Ctx &c, const Gemm &q) {
       HIPC(hipEventRecord(ev.first, c.stream));
     }
   }
+  std::pair<hipEvent_t, hipEvent_t> sev;
+  const bool shape_rec = c.shape_stats && !c.capturing;
+  if (shape_rec) {
+    sev.first = c.take_event();
+    sev.second = c.take_event();
+    HIPC(hipEventRecord(sev.first, c.stream));
+  }
   hipLaunchKernelGGL(k_gemm<T>, dim3((unsigned)blocks), dim3(256), 0, c.stream, g);
   HIPC(hipGetLastError());
+  if (shape_rec) {
+    HIPC(hipEventRecord(sev.second, c.stream));
+    char key[200];
+    const Prob &P = g.p[0];
+    std::snprintf(key, sizeof key, "%s x%d M=%d N=%d K=%d B=%dx%d split=%d %s%s",
+                  kind == 0 ? "f64" : (kind == 1 ? "f32" : "bf16"), g.np, P.M, P.N, P.K, P.B1, P.B2, P.ksplit,
+                  P.sAm == 1 ? "Am" : "Ak", P.sBn == 1 ? "Bn" : "Bk");
+    c.shape_pending.push_back({key, sev});
+    c.shape_flops_pending.push_back(g.flops);
+    if (c.shape_pending.size() > 8192) c.resolve_shapes();
+  }
   if (timed) {
     HIPC(hipEventRecord(ev.second, c.stream));
     c.kt.pending[kind].push_back(ev);
+  }
+  // reduction of split / summed outputs
+  if (part_need > 0) {
+    RedK R{};
+    R.skip = skip;
+    int64_t total = 0;
+    for (int gi = 0; gi < ngroups; ++gi) {
+      RedOut O{};
+      bool any = false;
+      for (int i = 0; i < np; ++i) {
+        if (group[i] != gi || keep[i] < 0) continue;
+        const Prob &P = g.p[keep[i]];
+        if (P.direct) continue;
+        if (O.nsrc >= 2) fail(QTT_E_ARG, "gemm group: at most two problems per output");
+        const Gemm &s = q[i];
+        if (!any) {
+          O.C = s.C;
+          O.sCm = s.sCm;
+          O.sCn = s.sCn;
+          O.sCb1 = s.sCb1;
+          O.sCb2 = s.sCb2;
+          O.X = X[gi] ? X[gi] : s.C;
+          O.sXm = s.sCm;
+          O.sXn = s.sCn;
+          O.sXb1 = s.sCb1;
+          O.sXb2 = s.sCb2;
+          O.M = s.M;
+          O.N = s.N;
+          O.B1 = s.B1;
+          O.B2 = s.B2;
+          O.alpha = s.alpha;
+          O.beta = s.beta;
+          any = true;
+        } else if (s.M != O.M || s.N != O.N || s.B1 != O.B1 || s.B2 != O.B2 || s.C != O.C ||
+                   s.alpha != O.alpha || s.beta != O.beta) {
+          fail(QTT_E_ARG, "gemm group: summed problems must share the output");
+        }
+        O.src[O.nsrc].part = P.part;
+        O.src[O.nsrc].ksplit = P.ksplit;
+        O.nsrc += 1;
+      }
+      if (!any) continue;
+      if (R.nout >= GEMM_GROUP) fail(QTT_E_ARG, "gemm group: too many reduced outputs");
+      if (X[gi]) {
+        int64_t lo = 0, hi = 0;
+        span(lo, hi, O.M, O.sXm);
+        span(lo, hi, O.N, O.sXn);
+        span(lo, hi, O.B1, O.sXb1);
+        span(lo, hi, O.B2, O.sXb2);
+        c.check_range(O.X, lo, hi, sizeof(double), "gemm X");
+      }
+      O.elem0 = total;
+      total += (int64_t)O.M * O.N * O.B1 * O.B2;
+      R.o[R.nout++] = O;
+    }
+    R.total = total;
+    if (total > 0) {
+      const unsigned rg = (unsigned)std::min<int64_t>(4096, (total + 255) / 256);
+      hipLaunchKernelGGL(k_splitk_reduce, dim3(rg), dim3(256), 0, c.stream, R);
+      HIPC(hipGetLastError());
+    }
   }
 }
 
 }  // namespace
 
-void gemm(Ctx &c, const Gemm &g) { launch<double>(c, g); }
-void gemm_f32(Ctx &c, const Gemm &g) { launch<float>(c, g); }
+void gemm(Ctx &c, const Gemm &g) {
+  const int grp = 0;
+  const double *X = nullptr;
+  launch_group<double>(c, 1, &g, 1, &grp, &X, g.skip);
+}
+
+void gemm_f32(Ctx &c, const Gemm &g) {
+  const int grp = 0;
+  const double *X = nullptr;
+  launch_group<float>(c, 1, &g, 1, &grp, &X, g.skip);
+}
+
+void gemm_bf16(Ctx &c, const Gemm &g) {
+  const int grp = 0;
+  const double *X = nullptr;
+  launch_group<__bf16>(c, 1, &g, 1, &grp, &X, g.skip);
+}
+
+void gemm_grouped(Ctx &c, int np, const Gemm *q, int ngroups, const int *group,
+                  const double *const *X, const int *skip, bool f32) {
+  if (np < 1 || np > GEMM_GROUP) fail(QTT_E_ARG, "gemm_grouped: 1..4 problems");
+  if (f32) launch_group<float>(c, np, q, ngroups, group, X, skip);
+  else launch_group<double>(c, np, q, ngroups, group, X, skip);
+}
 
 }  // namespace qtt

@@ -3,84 +3,121 @@
 //   T'[p][w_out][m'][q] = sum_{m, w_in} W[m][w_in][w_out][m'] T[p][m][w_in][q],
 // where p runs over the bra and outer-layer bonds and q over the inner-layer
 // and ket bonds.  The finite-difference cores are sparse (12 of 144 entries
-// of the bond-3 derivative core are non-zero) and tiny, so this is a pure
-// HBM-streaming step: each thread owns one q column, reads its 4*mi inputs
-// once, writes its 4*mo outputs once, and takes the core from LDS.
+// of the bond-3 derivative core, at most 144 of 1296 of a composed bond-9
+// penalty core), so this is an HBM-streaming step: one thread per output
+// element, which sums the few non-zeros of its output column (compressed
+// columns built on the host once per MPO); q is the fastest index so loads
+// and stores are unit-stride across a wave.
 #include "qtt_internal.h"
 
 namespace qtt {
 
 namespace {
 
-template <int KI, int KO>
-__global__ __launch_bounds__(256) void k_mpo_layer(const double *T, double *Tout, const double *W,
-                                                   int64_t post, int nqc, const int *skip) {
+__global__ __launch_bounds__(256) void k_mpo_csc(const double *T, double *Tout,
+                                                 const int *colptr, const int *rowidx,
+                                                 const double *val, int KI, int KO, int64_t post,
+                                                 int64_t total, const int *skip) {
   if (skip && *skip) return;
-  __shared__ double w[KI * KO];
-  for (int i = threadIdx.x; i < KI * KO; i += 256) w[i] = W[i];
-  __syncthreads();
-  const int64_t b = blockIdx.x;
-  const int qc = (int)(b % nqc);
-  const int64_t p = b / nqc;
-  const int64_t q = (int64_t)qc * 256 + threadIdx.x;
-  if (q >= post) return;
-  const double *src = T + p * KI * post + q;
-  double in[KI];
-#pragma unroll
-  for (int k = 0; k < KI; ++k) in[k] = src[k * post];
-  double *dst = Tout + p * KO * post + q;
-#pragma unroll
-  for (int o = 0; o < KO; ++o) {
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t q = idx % post;
+    const int64_t t = idx / post;
+    const int o = (int)(t % KO);
+    const int64_t p = t / KO;
+    const double *src = T + p * KI * post + q;
     double s = 0.0;
-#pragma unroll
-    for (int k = 0; k < KI; ++k) {
-      const double wv = w[k * KO + o];
-      if (wv != 0.0) s += wv * in[k];
-    }
-    dst[o * post] = s;
+    const int e = colptr[o + 1];
+    for (int z = colptr[o]; z < e; ++z) s += val[z] * src[(int64_t)rowidx[z] * post];
+    Tout[idx] = s;
   }
 }
 
-template <int KI, int KO>
-void launch_t(Ctx &c, const double *T, double *Tout, const double *W, int64_t pre, int64_t post,
-              const int *skip) {
-  const int nqc = (int)((post + 255) / 256);
-  const int64_t blocks = pre * nqc;
-  if (blocks > 0x7fffffffLL) fail(QTT_E_UNSUPPORTED, "mpo_layer grid too large");
-  hipLaunchKernelGGL((k_mpo_layer<KI, KO>), dim3((unsigned)blocks), dim3(256), 0, c.stream, T,
-                     Tout, W, post, nqc, skip);
-  HIPC(hipGetLastError());
-}
+struct MJob {
+  const double *T;
+  double *Tout;
+  const int *colptr, *rowidx;
+  const double *val;
+  int KI, KO;
+  int64_t post, total, elem0;
+};
+struct MJobs {
+  int nj;
+  MJob j[4];
+  int64_t total;
+};
 
-template <int KI>
-void launch_ko(Ctx &c, int mo, const double *T, double *Tout, const double *W, int64_t pre,
-               int64_t post, const int *skip) {
-  switch (mo) {
-    case 1: return launch_t<KI, 4>(c, T, Tout, W, pre, post, skip);
-    case 3: return launch_t<KI, 12>(c, T, Tout, W, pre, post, skip);
-    case 6: return launch_t<KI, 24>(c, T, Tout, W, pre, post, skip);
-    case 9: return launch_t<KI, 36>(c, T, Tout, W, pre, post, skip);
-    case 18: return launch_t<KI, 72>(c, T, Tout, W, pre, post, skip);
-    default: fail(QTT_E_UNSUPPORTED, "mpo_layer: MPO bond must be 1, 3, 6, 9 or 18");
+__global__ __launch_bounds__(256) void k_mpo_csc_grouped(MJobs J, const int *skip) {
+  if (skip && *skip) return;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < J.total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    int ji = 0;
+#pragma unroll
+    for (int i = 1; i < 4; ++i)
+      if (i < J.nj && e >= J.j[i].elem0) ji = i;
+    const MJob &M = J.j[ji];
+    const int64_t idx = e - M.elem0;
+    const int64_t q = idx % M.post;
+    const int64_t t = idx / M.post;
+    const int o = (int)(t % M.KO);
+    const int64_t p = t / M.KO;
+    const double *src = M.T + p * M.KI * M.post + q;
+    double s = 0.0;
+    const int end = M.colptr[o + 1];
+    for (int z = M.colptr[o]; z < end; ++z) s += M.val[z] * src[(int64_t)M.rowidx[z] * M.post];
+    M.Tout[idx] = s;
   }
 }
 
 }  // namespace
 
-void mpo_layer(Ctx &c, const double *T, double *Tout, const double *W, int64_t pre, int mi, int mo,
-               int64_t post, const int *skip) {
-  if (pre <= 0 || post <= 0) return;
-  c.check_range(T, 0, pre * mi * 4 * post - 1, 8, "mpo_layer in");
-  c.check_range(Tout, 0, pre * mo * 4 * post - 1, 8, "mpo_layer out");
-  c.check_range(W, 0, (int64_t)mi * 16 * mo - 1, 8, "mpo_layer core");
-  switch (mi) {
-    case 1: return launch_ko<4>(c, mo, T, Tout, W, pre, post, skip);
-    case 3: return launch_ko<12>(c, mo, T, Tout, W, pre, post, skip);
-    case 6: return launch_ko<24>(c, mo, T, Tout, W, pre, post, skip);
-    case 9: return launch_ko<36>(c, mo, T, Tout, W, pre, post, skip);
-    case 18: return launch_ko<72>(c, mo, T, Tout, W, pre, post, skip);
-    default: fail(QTT_E_UNSUPPORTED, "mpo_layer: MPO bond must be 1, 3, 6, 9 or 18");
+void mpo_layer_grouped(Ctx &c, int nj, const MpoJob *jobs, const int *skip) {
+  if (nj < 1 || nj > 4) fail(QTT_E_ARG, "mpo_layer_grouped: 1..4 jobs");
+  MJobs J{};
+  int64_t total = 0;
+  for (int i = 0; i < nj; ++i) {
+    const MpoJob &s = jobs[i];
+    const int KI = 4 * s.mi, KO = 4 * s.mo;
+    c.check_range(s.T, 0, s.pre * KI * s.post - 1, 8, "mpo_layer in");
+    c.check_range(s.Tout, 0, s.pre * KO * s.post - 1, 8, "mpo_layer out");
+    const MpoCsc &z = s.W->csc[s.rev ? 1 : 0];
+    MJob &m = J.j[J.nj++];
+    m.T = s.T;
+    m.Tout = s.Tout;
+    m.colptr = z.colptr + z.cp_off[s.site];
+    m.rowidx = z.rowidx + z.nz_off[s.site];
+    m.val = z.val + z.nz_off[s.site];
+    m.KI = KI;
+    m.KO = KO;
+    m.post = s.post;
+    m.total = s.pre * KO * s.post;
+    m.elem0 = total;
+    total += m.total;
   }
+  J.total = total;
+  if (total <= 0) return;
+  int64_t g = (total + 255) / 256;
+  if (g > 131072) g = 131072;
+  hipLaunchKernelGGL(k_mpo_csc_grouped, dim3((unsigned)g), dim3(256), 0, c.stream, J, skip);
+  HIPC(hipGetLastError());
+}
+
+void mpo_layer(Ctx &c, const double *T, double *Tout, const Mpo &W, int site, bool rev,
+               int64_t pre, int mi, int mo, int64_t post, const int *skip) {
+  if (pre <= 0 || post <= 0) return;
+  const int KI = 4 * mi, KO = 4 * mo;
+  c.check_range(T, 0, pre * KI * post - 1, 8, "mpo_layer in");
+  c.check_range(Tout, 0, pre * KO * post - 1, 8, "mpo_layer out");
+  const MpoCsc &z = W.csc[rev ? 1 : 0];
+  const int *cp = z.colptr + z.cp_off[site];
+  const int *ri = z.rowidx + z.nz_off[site];
+  const double *vv = z.val + z.nz_off[site];
+  const int64_t total = pre * KO * post;
+  int64_t g = (total + 255) / 256;
+  if (g > 131072) g = 131072;
+  hipLaunchKernelGGL(k_mpo_csc, dim3((unsigned)g), dim3(256), 0, c.stream, T, Tout, cp, ri, vv, KI,
+                     KO, post, total, skip);
+  HIPC(hipGetLastError());
 }
 
 }  // namespace qtt

@@ -1,0 +1,412 @@
+// Batched one-sided block-Jacobi SVD (float64) for the truncation sweeps.
+//
+// A (m x n, m >= n) is orthogonalised column-wise: A V = W with W's columns
+// mutually orthogonal, sigma_j = ||w_j||, u_j = w_j / sigma_j.  The columns
+// are split into blocks of b; every outer round pairs the blocks with a
+// round-robin schedule and one 1024-thread workgroup takes one block pair:
+// its 2b columns are staged in LDS, one Jacobi sweep over all column pairs of
+// the block pair runs there (one wave per pair and LDS-resident reductions),
+// the accumulated 2b x 2b rotation is applied to the matching columns of V
+// in HBM, and the columns go back.  Pairs of one round touch disjoint
+// columns, so a round is one launch with (#pairs x #matrices) workgroups.
+// Matrices with n <= 2b are one block pair and converge inside one launch.
+// Rotations are counted per matrix; a sweep without rotations ends the
+// iteration (the host reads the counters once per outer sweep).
+#include "qtt_internal.h"
+
+#include <cstdio>
+#include <cstdlib>
+
+namespace qtt {
+
+namespace {
+
+constexpr int SV_THREADS = 1024;
+constexpr int SV_WAVES = SV_THREADS / 64;
+constexpr int SV_MAXB = 8;
+constexpr double SV_TOL = 1e-15;
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+struct SvMat {
+  const double *A;
+  int m, n;
+  int64_t ars, acs;
+  double *W;   // m x n column-major
+  double *V;   // n x n column-major
+  int *count;  // rotations of the current sweep
+  int b;       // block width
+  int nb;      // blocks
+  int single;  // n <= 2b: whole matrix is one block pair
+  int first;   // first workgroup of this matrix in a round launch
+  double *U;
+  int64_t urs, ucs;
+  double *S;
+  double *Vout;
+  int64_t vrs, vcs;
+};
+struct SvBatch {
+  int count;
+  SvMat d[SV_MAXB];
+};
+
+__global__ __launch_bounds__(SV_THREADS) void k_sv_init(SvBatch B) {
+  const SvMat &D = B.d[blockIdx.x];
+  for (int64_t idx = threadIdx.x; idx < (int64_t)D.m * D.n; idx += SV_THREADS) {
+    const int i = (int)(idx % D.m), j = (int)(idx / D.m);
+    D.W[idx] = D.A[i * D.ars + j * D.acs];
+  }
+  for (int64_t idx = threadIdx.x; idx < (int64_t)D.n * D.n; idx += SV_THREADS) {
+    const int i = (int)(idx % D.n), j = (int)(idx / D.n);
+    D.V[idx] = (i == j) ? 1.0 : 0.0;
+  }
+  if (threadIdx.x == 0) *D.count = 0;
+}
+
+// one Jacobi sweep over the column pairs of the nc LDS columns; returns the
+// number of rotations (valid in every thread after the final barrier)
+__device__ int inner_sweep(double *cols, int m, int nc, double *Wacc, int *rot) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int np = nc + (nc & 1);
+  if (threadIdx.x == 0) *rot = 0;
+  __syncthreads();
+  for (int r = 0; r < np - 1; ++r) {
+    for (int pr = wave; pr < np / 2; pr += SV_WAVES) {
+      int p, q;
+      if (pr == 0) {
+        p = np - 1;
+        q = r;
+      } else {
+        p = (r + pr) % (np - 1);
+        q = (r - pr + np - 1) % (np - 1);
+      }
+      if (p >= nc || q >= nc) continue;
+      if (p > q) {
+        const int t = p;
+        p = q;
+        q = t;
+      }
+      double *cp = cols + (int64_t)p * m;
+      double *cq = cols + (int64_t)q * m;
+      double al = 0.0, be = 0.0, ga = 0.0;
+      for (int i = lane; i < m; i += 64) {
+        const double x = cp[i], y = cq[i];
+        al += x * x;
+        be += y * y;
+        ga += x * y;
+      }
+      al = wave_sum(al);
+      be = wave_sum(be);
+      ga = wave_sum(ga);
+      if (ga != 0.0 && fabs(ga) > SV_TOL * sqrt(al * be)) {
+        const double zeta = (be - al) / (2.0 * ga);
+        const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        const double cs = 1.0 / sqrt(1.0 + t * t);
+        const double sn = cs * t;
+        for (int i = lane; i < m; i += 64) {
+          const double x = cp[i], y = cq[i];
+          cp[i] = cs * x - sn * y;
+          cq[i] = sn * x + cs * y;
+        }
+        double *wp = Wacc + p * nc, *wq = Wacc + q * nc;
+        for (int i = lane; i < nc; i += 64) {
+          const double x = wp[i], y = wq[i];
+          wp[i] = cs * x - sn * y;
+          wq[i] = sn * x + cs * y;
+        }
+        if (lane == 0) atomicAdd(rot, 1);
+      }
+    }
+    __syncthreads();
+  }
+  return *rot;
+}
+
+// LDS: cols[nc][m], Wacc[nc][nc] (column-major: Wacc[c * nc + k]), colidx[nc], rot
+__global__ __launch_bounds__(SV_THREADS) void k_sv_round(SvBatch B, int round) {
+  extern __shared__ double lds[];
+  // which matrix and which pair
+  int mi = 0;
+  for (int i = 1; i < B.count; ++i)
+    if ((int)blockIdx.x >= B.d[i].first) mi = i;
+  const SvMat &D = B.d[mi];
+  const int t = (int)blockIdx.x - D.first;
+  const int m = D.m, n = D.n, b = D.b;
+  int blk[2];
+  int nblk;
+  if (D.single) {
+    blk[0] = 0;
+    nblk = 1;
+  } else {
+    const int nbp = D.nb + (D.nb & 1);
+    int P, Q;
+    if (t == 0) {
+      P = nbp - 1;
+      Q = round;
+    } else {
+      P = (round + t) % (nbp - 1);
+      Q = (round - t + nbp - 1) % (nbp - 1);
+    }
+    nblk = 0;
+    if (P < D.nb) blk[nblk++] = P;
+    if (Q < D.nb) blk[nblk++] = Q;
+    if (nblk == 2 && blk[0] > blk[1]) {
+      const int x = blk[0];
+      blk[0] = blk[1];
+      blk[1] = x;
+    }
+  }
+  // column list
+  __shared__ int colidx[2 * 64];
+  __shared__ int rot;
+  int nc = 0;
+  if (D.single) {
+    nc = n;
+  } else {
+    for (int k = 0; k < nblk; ++k) {
+      const int c0 = blk[k] * b, c1 = min(c0 + b, n);
+      nc += c1 - c0;
+    }
+  }
+  if (threadIdx.x == 0) {
+    int o = 0;
+    if (D.single) {
+      for (int c = 0; c < n; ++c) colidx[o++] = c;
+    } else {
+      for (int k = 0; k < nblk; ++k)
+        for (int c = blk[k] * b; c < min(blk[k] * b + b, n); ++c) colidx[o++] = c;
+    }
+  }
+  double *cols = lds;
+  double *Wacc = lds + (int64_t)nc * m;
+  __syncthreads();
+  for (int64_t idx = threadIdx.x; idx < (int64_t)nc * m; idx += SV_THREADS) {
+    const int k = (int)(idx / m), i = (int)(idx % m);
+    cols[idx] = D.W[(int64_t)colidx[k] * m + i];
+  }
+  for (int idx = threadIdx.x; idx < nc * nc; idx += SV_THREADS)
+    Wacc[idx] = ((idx / nc) == (idx % nc)) ? 1.0 : 0.0;
+  __syncthreads();
+
+  int total = 0, any = 0;
+  if (D.single) {
+    int last = 1;
+    for (int s = 0; s < 60 && last > 0; ++s) {
+      last = inner_sweep(cols, m, nc, Wacc, &rot);
+      any += last;
+      __syncthreads();
+    }
+    total = last;
+  } else {
+    total = inner_sweep(cols, m, nc, Wacc, &rot);
+    any = total;
+  }
+  __syncthreads();
+  // columns back to HBM
+  for (int64_t idx = threadIdx.x; idx < (int64_t)nc * m; idx += SV_THREADS) {
+    const int k = (int)(idx / m), i = (int)(idx % m);
+    D.W[(int64_t)colidx[k] * m + i] = cols[idx];
+  }
+  // V[:, cols] <- V[:, cols] Wacc, staged through the LDS the columns used
+  // (n <= m, so the n x nc slice fits)
+  if (any > 0) {
+    __syncthreads();
+    double *Vl = cols;
+    for (int64_t idx = threadIdx.x; idx < (int64_t)nc * n; idx += SV_THREADS) {
+      const int k = (int)(idx / n), i = (int)(idx % n);
+      Vl[idx] = D.V[(int64_t)colidx[k] * n + i];
+    }
+    __syncthreads();
+    for (int64_t idx = threadIdx.x; idx < (int64_t)nc * n; idx += SV_THREADS) {
+      const int cc = (int)(idx / n), i = (int)(idx % n);
+      double s = 0.0;
+      for (int k = 0; k < nc; ++k) s += Vl[(int64_t)k * n + i] * Wacc[cc * nc + k];
+      D.V[(int64_t)colidx[cc] * n + i] = s;
+    }
+  }
+  if (threadIdx.x == 0) {
+    if (D.single) *D.count = total;
+    else if (total > 0) atomicAdd(D.count, total);
+  }
+}
+
+// singular values, descending order, outputs
+__global__ __launch_bounds__(SV_THREADS) void k_sv_finish(SvBatch B) {
+  extern __shared__ double lds[];
+  const SvMat &D = B.d[blockIdx.x];
+  const int m = D.m, n = D.n;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double *sig = lds;
+  int *rank = (int *)(lds + n);
+  for (int j = wave; j < n; j += SV_WAVES) {
+    const double *wj = D.W + (int64_t)j * m;
+    double s = 0.0;
+    for (int i = lane; i < m; i += 64) s += wj[i] * wj[i];
+    s = wave_sum(s);
+    if (lane == 0) sig[j] = sqrt(s);
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < n; j += SV_THREADS) {
+    const double sj = sig[j];
+    int r = 0;
+    for (int i = 0; i < n; ++i) {
+      const double si = sig[i];
+      r += (si > sj || (si == sj && i < j)) ? 1 : 0;
+    }
+    rank[j] = r;
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < n; j += SV_THREADS) D.S[rank[j]] = sig[j];
+  for (int64_t idx = threadIdx.x; idx < (int64_t)m * n; idx += SV_THREADS) {
+    const int i = (int)(idx % m), j = (int)(idx / m);
+    const double s = sig[j];
+    D.U[i * D.urs + rank[j] * D.ucs] = (s > 0.0) ? D.W[idx] / s : 0.0;
+  }
+  for (int64_t idx = threadIdx.x; idx < (int64_t)n * n; idx += SV_THREADS) {
+    const int i = (int)(idx % n), j = (int)(idx / n);
+    D.Vout[i * D.vrs + rank[j] * D.vcs] = D.V[idx];
+  }
+}
+
+// dynamic LDS available to k_sv_round: the device's per-workgroup maximum
+// minus the kernel's static LDS (opted in once per process)
+size_t g_lds_limit = 0;
+
+size_t sv_lds_limit(Ctx &c) {
+  if (g_lds_limit) return g_lds_limit;
+  int maxsh = 0;
+  HIPC(hipDeviceGetAttribute(&maxsh, hipDeviceAttributeMaxSharedMemoryPerBlock, c.device));
+  hipFuncAttributes fa;
+  HIPC(hipFuncGetAttributes(&fa, (const void *)k_sv_round));
+  size_t lim = (size_t)maxsh > fa.sharedSizeBytes + 256 ? (size_t)maxsh - fa.sharedSizeBytes - 256
+                                                        : 32768;
+  if (lim > 65536 - fa.sharedSizeBytes - 256) {
+    if (hipFuncSetAttribute((const void *)k_sv_round, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lim) != hipSuccess) {
+      (void)hipGetLastError();
+      lim = 65536 - fa.sharedSizeBytes - 256;
+    }
+  }
+  g_lds_limit = lim;
+  const char *vb = std::getenv("QTT_VERBOSE");
+  if (vb && vb[0] == '1')
+    std::fprintf(stderr, "[qtt] svd: device LDS per workgroup %d, static %zu, dynamic limit %zu\n",
+                 maxsh, (size_t)fa.sharedSizeBytes, lim);
+  return lim;
+}
+
+}  // namespace
+
+void svd_batch(Ctx &c, int count, const ConstMatView *A, const MatView *U, double *const *S,
+               const MatView *V) {
+  const size_t SV_LDS_LIMIT = sv_lds_limit(c);
+  for (int base = 0; base < count; base += SV_MAXB) {
+    const int cnt = std::min(SV_MAXB, count - base);
+    SvBatch B{};
+    B.count = cnt;
+    int64_t ws = 0;
+    size_t lds_round = 0, lds_fin = 0;
+    for (int i = 0; i < cnt; ++i) {
+      const ConstMatView &a = A[base + i];
+      const int m = a.rows, n = a.cols;
+      if (m < n) fail(QTT_E_SHAPE, "svd_batch: needs rows >= cols");
+      if (U[base + i].rows != m || U[base + i].cols != n || V[base + i].rows != n ||
+          V[base + i].cols != n)
+        fail(QTT_E_SHAPE, "svd_batch: output shapes");
+      {
+        int64_t lo = 0, hi = 0;
+        span(lo, hi, a.rows, a.rs);
+        span(lo, hi, a.cols, a.cs);
+        c.check_range(a.p, lo, hi, 8, "svd A");
+        lo = hi = 0;
+        span(lo, hi, U[base + i].rows, U[base + i].rs);
+        span(lo, hi, U[base + i].cols, U[base + i].cs);
+        c.check_range(U[base + i].p, lo, hi, 8, "svd U");
+        lo = hi = 0;
+        span(lo, hi, V[base + i].rows, V[base + i].rs);
+        span(lo, hi, V[base + i].cols, V[base + i].cs);
+        c.check_range(V[base + i].p, lo, hi, 8, "svd V");
+        c.check_range(S[base + i], 0, n - 1, 8, "svd S");
+      }
+      // block width: 2b columns of m rows (plus the rotation) must fit in LDS
+      int b = 32;
+      while (b > 1 && (size_t)(2 * b) * (m + 2 * b) * 8 > SV_LDS_LIMIT) b /= 2;
+      if ((size_t)(2 * b) * (m + 2 * b) * 8 > SV_LDS_LIMIT)
+        fail(QTT_E_UNSUPPORTED, "svd_batch: matrix too tall");
+      SvMat &d = B.d[i];
+      d.A = a.p;
+      d.m = m;
+      d.n = n;
+      d.ars = a.rs;
+      d.acs = a.cs;
+      d.b = b;
+      d.nb = (n + b - 1) / b;
+      d.single = (n <= 2 * b) ? 1 : 0;
+      if (d.single) d.nb = 1;
+      d.U = U[base + i].p;
+      d.urs = U[base + i].rs;
+      d.ucs = U[base + i].cs;
+      d.S = S[base + i];
+      d.Vout = V[base + i].p;
+      d.vrs = V[base + i].rs;
+      d.vcs = V[base + i].cs;
+      ws += (int64_t)m * n + (int64_t)n * n + 1;
+      const int nc = d.single ? n : 2 * b;
+      lds_round = std::max(lds_round, (size_t)nc * (m + nc) * 8);
+      lds_fin = std::max(lds_fin, (size_t)(2 * n + 4) * 8);
+    }
+    double *Wb = c.buf("svd_work", ws);
+    int *cnt_host = (int *)(c.pinned + 2048);
+    int *cnt_dev = (int *)c.raw("svd_counts", SV_MAXB * sizeof(int));
+    int64_t o = 0;
+    for (int i = 0; i < cnt; ++i) {
+      SvMat &d = B.d[i];
+      d.W = Wb + o;
+      o += (int64_t)d.m * d.n;
+      d.V = Wb + o;
+      o += (int64_t)d.n * d.n + 1;
+      d.count = cnt_dev + i;
+    }
+    hipLaunchKernelGGL(k_sv_init, dim3(cnt), dim3(SV_THREADS), 0, c.stream, B);
+    HIPC(hipGetLastError());
+    // rounds per sweep: the largest block count decides
+    int rounds = 1;
+    for (int i = 0; i < cnt; ++i)
+      if (!B.d[i].single) rounds = std::max(rounds, B.d[i].nb + (B.d[i].nb & 1) - 1);
+    for (int sweep = 0; sweep < 40; ++sweep) {
+      for (int r = 0; r < rounds; ++r) {
+        // workgroups of this round per matrix
+        SvBatch R = B;
+        int wg = 0;
+        int active = 0;
+        for (int i = 0; i < cnt; ++i) {
+          SvMat &d = R.d[i];
+          d.first = wg;
+          int pairs;
+          if (d.single) pairs = (r == 0) ? 1 : 0;
+          else pairs = (r < d.nb + (d.nb & 1) - 1) ? (d.nb + (d.nb & 1)) / 2 : 0;
+          wg += pairs;
+          active += pairs;
+        }
+        if (active == 0) continue;
+        // matrices with no work this round keep first = wg (no workgroup maps to them)
+        hipLaunchKernelGGL(k_sv_round, dim3(wg), dim3(SV_THREADS), lds_round, c.stream, R, r);
+        HIPC(hipGetLastError());
+      }
+      HIPC(hipMemcpyAsync(cnt_host, cnt_dev, cnt * sizeof(int), hipMemcpyDeviceToHost, c.stream));
+      c.sync();
+      bool done = true;
+      for (int i = 0; i < cnt; ++i) done = done && (cnt_host[i] == 0);
+      if (done) break;
+      HIPC(hipMemsetAsync(cnt_dev, 0, cnt * sizeof(int), c.stream));
+    }
+    hipLaunchKernelGGL(k_sv_finish, dim3(cnt), dim3(SV_THREADS), lds_fin, c.stream, B);
+    HIPC(hipGetLastError());
+  }
+}
+
+}  // namespace qtt

@@ -7,6 +7,9 @@
 #include <cstring>
 #include <sstream>
 
+static_assert(qtt::PC_IN == QTT_PC_IN && qtt::PC_W == QTT_PC_WIDTH && qtt::PC_OUT == QTT_PC_OUT,
+              "preconditioner sizes");
+
 struct qtt_ctx {
   qtt::Ctx c;
 };
@@ -20,10 +23,12 @@ int guard(qtt_ctx *ctx, F &&f) {
   ctx->c.user_ranges.clear();
   try {
     HIPC(hipSetDevice(ctx->c.device));
+    if (ctx->c.own_stream) HIPC(hipStreamSynchronize(nullptr));
     f();
     return QTT_OK;
   } catch (qtt::Error &e) {
     ctx->c.err = e.msg;
+    (void)hipGetLastError();
     if (e.code > 0) return e.code;
     // leave the stream idle before reporting
     hipStreamSynchronize(ctx->c.stream);
@@ -62,8 +67,29 @@ int qtt_ctx_create(qtt_ctx **out, int device, void *hip_stream) {
   qtt_ctx *c = new qtt_ctx();
   c->c.device = device;
   c->c.stream = (hipStream_t)hip_stream;
+  if (!c->c.stream) {
+    // the legacy null stream cannot be captured into graphs: work goes to a
+    // context-owned stream (default priority) that first waits for the null
+    // stream at every call; every call ends with a stream synchronisation
+    if (hipStreamCreateWithFlags(&c->c.stream, hipStreamNonBlocking) != hipSuccess) {
+      (void)hipGetLastError();
+      delete c;
+      return QTT_E_HIP;
+    }
+    c->c.own_stream = true;
+  }
+  if (hipHostMalloc((void **)&c->c.pinned, 4096 * sizeof(double), 0) != hipSuccess) {
+    (void)hipGetLastError();
+    c->c.pinned = nullptr;
+    delete c;
+    return QTT_E_HIP;
+  }
   const char *t = std::getenv("QTT_TIMING");
   c->c.timing = (t && t[0] == '1');
+  const char *gr = std::getenv("QTT_GRAPHS");
+  c->c.use_graphs = !(gr && gr[0] == '0');
+  const char *gs = std::getenv("QTT_GEMM_STATS");
+  c->c.shape_stats = (gs && gs[0] == '1');
   *out = c;
   return QTT_OK;
 }
@@ -305,6 +331,58 @@ int qtt_kernel_stats_read(qtt_ctx *ctx, int32_t kernel, qtt_kernel_stats *out) {
     out->timed = c.kt.timed[kernel];
     out->flops = fl[kernel];
     out->timed_ms = c.kt.timed_ms[kernel];
+  });
+}
+
+int qtt_precond_config(qtt_ctx *ctx, int32_t train_per_solve, double lr, uint64_t seed,
+                       int32_t reset) {
+  return guard(ctx, [&] {
+    if (train_per_solve < 0 || !(lr > 0.0)) qtt::fail(QTT_E_ARG, "precond_config: bad arguments");
+    qtt::Ctx &c = ctx->c;
+    if (reset || !c.pc.ready) qtt::pc_reset(c, seed);
+    c.pc.train_per_solve = train_per_solve;
+    c.pc.lr = lr;
+  });
+}
+
+int qtt_precond_info(qtt_ctx *ctx, int64_t *nparam, int64_t *steps, double *first_loss,
+                     double *last_loss) {
+  return guard(ctx, [&] {
+    const qtt::PrecondNet &net = ctx->c.pc;
+    if (nparam) *nparam = net.param_count();
+    if (steps) *steps = net.steps;
+    if (first_loss) *first_loss = net.first_loss;
+    if (last_loss) *last_loss = net.last_loss;
+  });
+}
+
+int qtt_precond_weights(qtt_ctx *ctx, int32_t set, double *w, int64_t n) {
+  return guard(ctx, [&] {
+    qtt::Ctx &c = ctx->c;
+    qtt::pc_init(c);
+    if (!w || n != c.pc.nparam) qtt::fail(QTT_E_ARG, "precond_weights: n must equal nparam");
+    c.sync();
+    if (set) {
+      HIPC(hipMemcpy(c.pc.w, w, n * sizeof(double), hipMemcpyHostToDevice));
+    } else {
+      HIPC(hipMemcpy(w, c.pc.w, n * sizeof(double), hipMemcpyDeviceToHost));
+    }
+  });
+}
+
+int qtt_precond_grad(qtt_ctx *ctx, const double *X, int64_t npos, const double *dY, double *Y,
+                     double *grad) {
+  return guard(ctx, [&] {
+    qtt::Ctx &c = ctx->c;
+    qtt::pc_init(c);
+    if (!X || !dY || !Y || !grad || npos < 1 || npos > (int64_t)1 << 24)
+      qtt::fail(QTT_E_ARG, "precond_grad: bad arguments");
+    c.register_user(X, (size_t)npos * qtt::PC_IN * 8);
+    c.register_user(dY, (size_t)npos * qtt::PC_OUT * 8);
+    c.register_user(Y, (size_t)npos * qtt::PC_OUT * 8);
+    c.register_user(grad, (size_t)c.pc.nparam * 8);
+    qtt::pc_net_grad(c, X, npos, dY, Y, grad);
+    c.sync();
   });
 }
 

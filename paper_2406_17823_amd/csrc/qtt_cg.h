@@ -8,6 +8,7 @@ namespace qtt {
 struct CGState {
   double rr, rr_new, rz, pq, alpha, beta, bnorm2, tol2, rtol;
   int done, iters, maxit, converged, zero_x;
+  int precond;  // PCG: rz is r . z, maintained by pcg_start / pcg_next
   unsigned int counter;
 };
 

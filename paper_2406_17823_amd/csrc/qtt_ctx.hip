@@ -2,7 +2,9 @@
 // finite-difference MPOs (App. A carry logic, uploaded once per (n, dx)).
 #include "qtt_internal.h"
 
+#include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <sstream>
 
@@ -11,7 +13,10 @@ namespace qtt {
 void fail(int code, const std::string &msg) { throw Error{code, msg}; }
 
 void hip_check(hipError_t e, const char *what) {
-  if (e != hipSuccess) fail(QTT_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();  // do not leave the runtime's last-error state set
+    fail(QTT_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+  }
 }
 
 double *Ctx::buf(const std::string &name, int64_t ndouble) {
@@ -92,8 +97,45 @@ void Ctx::resolve_events() {
   }
 }
 
+void Ctx::resolve_shapes() {
+  sync();
+  for (size_t i = 0; i < shape_pending.size(); ++i) {
+    float ms = 0.f;
+    HIPC(hipEventElapsedTime(&ms, shape_pending[i].second.first, shape_pending[i].second.second));
+    ShapeRec &r = shapes[shape_pending[i].first];
+    r.calls += 1;
+    r.ms += ms;
+    r.flops += shape_flops_pending[i];
+    kt.pool.push_back(shape_pending[i].second.first);
+    kt.pool.push_back(shape_pending[i].second.second);
+  }
+  shape_pending.clear();
+  shape_flops_pending.clear();
+}
+
 Ctx::~Ctx() {
+  if (shape_stats) {
+    try {
+      resolve_shapes();
+    } catch (...) {
+    }
+    std::vector<std::pair<double, std::string>> v;
+    double tot = 0.0;
+    for (auto &kv : shapes) {
+      v.push_back({kv.second.ms, kv.first});
+      tot += kv.second.ms;
+    }
+    std::sort(v.rbegin(), v.rend());
+    std::fprintf(stderr, "[qtt] GEMM shapes by time (total %.1f ms)\n", tot);
+    for (size_t i = 0; i < v.size() && i < 40; ++i) {
+      const ShapeRec &r = shapes[v[i].second];
+      std::fprintf(stderr, "[qtt] %9.2f ms %7lld calls %8.3f TF/s  %s\n", r.ms, (long long)r.calls,
+                   r.flops / (r.ms * 1e-3) / 1e12, v[i].second.c_str());
+    }
+  }
   hipStreamSynchronize(stream);
+  for (auto &kv : cg_graphs)
+    if (kv.second.exec) hipGraphExecDestroy(kv.second.exec);
   for (int k = 0; k < 2; ++k)
     for (auto &pr : kt.pending[k]) {
       hipEventDestroy(pr.first);
@@ -104,6 +146,7 @@ Ctx::~Ctx() {
     if (kv.second.ptr) hipFree(kv.second.ptr);
   for (void *p : owned) hipFree(p);
   if (pinned) hipHostFree(pinned);
+  if (own_stream) hipStreamDestroy(stream);
 }
 
 Mps from_c(const qtt_mps &m) {
@@ -292,6 +335,44 @@ static std::shared_ptr<Mpo> upload(Ctx &c, const HostMpo &h) {
           }
     perm.insert(perm.end(), p.begin(), p.end());
     rperm.insert(rperm.end(), rp.begin(), rp.end());
+  }
+  // compressed columns of the permuted cores for the streaming MPO kernel
+  for (int which = 0; which < 2; ++which) {
+    const std::vector<double> &src = which == 0 ? perm : rperm;
+    std::vector<int> cp, ri;
+    std::vector<double> vv;
+    MpoCsc &z = m->csc[which];
+    int64_t o = 0;
+    for (int k = 0; k < h.n; ++k) {
+      const int mi = which == 0 ? h.bond[k] : h.bond[k + 1];
+      const int mo = which == 0 ? h.bond[k + 1] : h.bond[k];
+      const int KI = 4 * mi, KO = 4 * mo;
+      z.cp_off.push_back((int64_t)cp.size());
+      z.nz_off.push_back((int64_t)ri.size());
+      const int base = (int)ri.size();
+      for (int oc = 0; oc < KO; ++oc) {
+        cp.push_back((int)ri.size() - base);
+        for (int kk = 0; kk < KI; ++kk) {
+          const double x = src[o + (int64_t)kk * KO + oc];
+          if (x != 0.0) {
+            ri.push_back(kk);
+            vv.push_back(x);
+          }
+        }
+      }
+      cp.push_back((int)ri.size() - base);
+      o += (int64_t)KI * KO;
+    }
+    if (ri.empty()) {
+      ri.push_back(0);
+      vv.push_back(0.0);
+    }
+    z.colptr = (int *)c.alloc_owned(((int64_t)cp.size() + 1) / 2 + 1);
+    z.rowidx = (int *)c.alloc_owned(((int64_t)ri.size() + 1) / 2 + 1);
+    z.val = c.alloc_owned((int64_t)vv.size());
+    HIPC(hipMemcpy(z.colptr, cp.data(), cp.size() * sizeof(int), hipMemcpyHostToDevice));
+    HIPC(hipMemcpy(z.rowidx, ri.data(), ri.size() * sizeof(int), hipMemcpyHostToDevice));
+    HIPC(hipMemcpy(z.val, vv.data(), vv.size() * sizeof(double), hipMemcpyHostToDevice));
   }
   m->fwd = c.alloc_owned(tot);
   m->perm = c.alloc_owned(tot);

@@ -55,12 +55,22 @@ void to_c(const Mps &m, qtt_mps *out);
 // MPO held by the context: forward cores [a][w][w'][b] and, for the
 // contraction kernels, the permuted cores [a][w'][w][b] and reversed
 // permuted cores [b][w'][w][a] (site order unchanged).
+// Compressed-column form of a site core viewed as B[k = (m_in, w_in)][o = (w_out, m_out)]:
+// column o holds its non-zeros (k, value); offsets per site on the host.
+struct MpoCsc {
+  int *colptr = nullptr;   // per site: 4*m_out + 1 entries
+  int *rowidx = nullptr;
+  double *val = nullptr;
+  std::vector<int64_t> cp_off, nz_off;  // per-site offsets into colptr / rowidx,val
+};
+
 struct Mpo {
   int n = 0;
   int bond[QTT_MAX_SITES + 1] = {0};
   double *fwd = nullptr;   // [a][w][w'][b]
   double *perm = nullptr;  // [a][w'][w][b]
   double *rperm = nullptr; // [b][w'][w][a]
+  MpoCsc csc[2];           // 0: perm, 1: rperm
   int64_t off(int k) const {
     int64_t o = 0;
     for (int j = 0; j < k; ++j) o += (int64_t)bond[j] * 16 * bond[j + 1];
@@ -80,10 +90,44 @@ struct KernelTimer {
   std::vector<hipEvent_t> pool;
 };
 
+// captured graph of a chunk of CG iterations
+struct CgGraph {
+  hipGraphExec_t exec = nullptr;
+  std::vector<int64_t> key;
+  int64_t launches[2] = {0, 0};  // GEMM launches per replay (float64, float32)
+};
+
+// ---------------------------------------------------------------- learned preconditioner
+// Shared-weight perceptron applied to every (alpha, beta) position of a centre
+// tensor: PC_IN features -> PC_W -> PC_W -> PC_OUT factor entries of a 4 x 4
+// lower-triangular L; the block of the preconditioner is L L^T.
+constexpr int PC_IN = 16, PC_W = 256, PC_OUT = 10;
+struct PrecondNet {
+  bool ready = false;
+  double *w = nullptr, *g = nullptr, *m = nullptr, *v = nullptr;  // device, nparam each
+  int64_t off[6] = {0, 0, 0, 0, 0, 0};  // W1 b1 W2 b2 W3 b3 (row-major W: out x in)
+  int64_t nparam = 0;
+  int64_t steps = 0;          // Adam steps taken
+  int train_per_solve = 0;    // Adam steps per local system while training
+  double lr = 1e-3;
+  uint64_t seed = 0x5eed;
+  uint64_t probe_ctr = 0;
+  double last_loss = -1.0;    // probe loss of the latest training step
+  double first_loss = -1.0;   // probe loss of the first training step
+  double *loss_dev = nullptr; // device accumulator (1 double)
+  // activations of the latest forward pass with keep = true (act_rows rows)
+  double *Z1 = nullptr, *H1 = nullptr, *Z2 = nullptr, *H2 = nullptr, *Y = nullptr;
+  double *Lf = nullptr, *dY = nullptr;
+  int64_t act_rows = 0;
+  int64_t param_count() const { return (int64_t)PC_W * PC_IN + PC_W + (int64_t)PC_W * PC_W + PC_W +
+                                       (int64_t)PC_OUT * PC_W + PC_OUT; }
+};
+
 // ---------------------------------------------------------------- context
 struct Ctx {
   int device = 0;
   hipStream_t stream = nullptr;
+  bool own_stream = false;            // stream created by the context
   std::string err;
   std::map<std::string, DevBuf> bufs;
   std::vector<void *> owned;          // allocations freed at destroy
@@ -94,6 +138,21 @@ struct Ctx {
   std::map<std::string, std::shared_ptr<Mpo>> mpos;
 
   KernelTimer kt;
+  PrecondNet pc;
+  bool use_graphs = true;             // QTT_GRAPHS=0 disables CG graph capture
+  bool capturing = false;             // a stream capture is open
+  int64_t cap_launches[2] = {0, 0};
+  std::map<std::string, CgGraph> cg_graphs;
+  // per-shape GEMM timing (QTT_GEMM_STATS=1), printed when the context ends
+  bool shape_stats = false;
+  struct ShapeRec {
+    int64_t calls = 0;
+    double ms = 0.0, flops = 0.0;
+  };
+  std::map<std::string, ShapeRec> shapes;
+  std::vector<std::pair<std::string, std::pair<hipEvent_t, hipEvent_t>>> shape_pending;
+  std::vector<double> shape_flops_pending;
+  void resolve_shapes();
   hipEvent_t take_event();
   void resolve_events();
   // caller buffers registered by the entry point (device address ranges)
@@ -136,9 +195,17 @@ struct Gemm {
   double alpha = 1.0, beta = 0.0;
   const int *skip = nullptr;
 };
+constexpr int GEMM_GROUP = 4;
 void gemm(Ctx &c, const Gemm &g);
+// up to GEMM_GROUP problems in one launch; problem i contributes to output
+// group group[i] (a group holds one or two problems sharing C, alpha, beta;
+// two problems are summed); X[group] (nullptr = C) is the beta input.
+void gemm_grouped(Ctx &c, int np, const Gemm *q, int ngroups, const int *group,
+                  const double *const *X, const int *skip, bool f32);
 // float32-MFMA variant with float64 inputs/outputs (mixed precision mode)
 void gemm_f32(Ctx &c, const Gemm &g);
+// bfloat16-MFMA variant (float32 accumulation) with float64 inputs/outputs
+void gemm_bf16(Ctx &c, const Gemm &g);
 
 // ---------------------------------------------------------------- small kernels
 void fill(Ctx &c, double *p, int64_t n, double v);
@@ -155,8 +222,19 @@ void hadamard_core(Ctx &c, double *y, const double *a, int la, int ra, const dou
 void mpo_core(Ctx &c, double *y, const double *W, int wl, int wr, const double *x, int l, int r);
 // one MPO layer of a network chain (sparse, HBM-streaming):
 // Tout[p][w_out][m'][q] = sum W[m][w_in][w_out][m'] T[p][m][w_in][q]
-void mpo_layer(Ctx &c, const double *T, double *Tout, const double *W, int64_t pre, int mi, int mo,
-               int64_t post, const int *skip);
+void mpo_layer(Ctx &c, const double *T, double *Tout, const Mpo &W, int site, bool rev,
+               int64_t pre, int mi, int mo, int64_t post, const int *skip);
+struct MpoJob {
+  const double *T;
+  double *Tout;
+  const Mpo *W;
+  int site;
+  bool rev;
+  int64_t pre, post;
+  int mi, mo;
+};
+// several MPO layers in one launch (at most 4)
+void mpo_layer_grouped(Ctx &c, int nj, const MpoJob *jobs, const int *skip);
 void morton_gather(Ctx &c, double *grid, const double *vec, int n);   // vec (Morton) -> grid
 void morton_scatter(Ctx &c, double *vec, const double *grid, int n);  // grid -> vec (Morton)
 void dot(Ctx &c, const double *x, const double *y, int64_t n, double *out_dev);
@@ -204,5 +282,29 @@ void build_derivative_host(int n, int axis, int order, double dx, std::vector<do
 void project(Ctx &c, const Mps a[2], const Mps b[2], double h, const qtt_params &p, Mps v[2],
              qtt_stats *st, int stage);
 void rk4_step(Ctx &c, Mps u[2], const qtt_params &p, qtt_stats *st);
+
+// ---------------------------------------------------------------- learned preconditioner
+void pc_init(Ctx &c);                   // allocate and draw the weights once
+void pc_reset(Ctx &c, uint64_t seed);   // (re)draw the weights from seed, clear Adam
+// features X (npos x PC_IN) and exact diagonal blocks Bblk (npos x 16) of the
+// local matrix for one component, from its own penalty pair's environments
+void pc_features(Ctx &c, const double *Lenv, const double *Renv, const Mpo &Wii, int d, int la,
+                 int ra, double mu_h2, double pen_scale, int n, int comp, double *X,
+                 double *Bblk);
+// network forward: M blocks (npos x 16); keep = store activations for training
+void pc_forward(Ctx &c, const double *X, int64_t npos, double *M, bool keep);
+void pc_block_inverse(Ctx &c, const double *Bblk, double *M, int64_t npos);
+void pc_apply(Ctx &c, const double *M, const double *r, double *z, int la, int ra,
+              const int *skip);
+void pc_probe(Ctx &c, double *z, int64_t n, uint64_t seed);
+// loss and output gradient for one component's positions (after pc_forward
+// with keep = true); rows [row0, row0 + la*ra) of the stored activations
+void pc_loss_grad(Ctx &c, const double *M, int64_t row0, const double *z, const double *Az,
+                  int la, int ra, const double *zz);
+// backward through the network from the stored output gradient, then Adam
+void pc_backward_adam(Ctx &c, const double *X, int64_t npos);
+// gradient of sum(dY * Y) for given inputs (device pointers): Y and grad out
+void pc_net_grad(Ctx &c, const double *X, int64_t npos, const double *dY, double *Y,
+                 double *grad);
 
 }  // namespace qtt

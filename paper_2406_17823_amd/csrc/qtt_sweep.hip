@@ -29,6 +29,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstring>
 #include <sstream>
 
 namespace qtt {
@@ -36,6 +37,7 @@ namespace qtt {
 namespace {
 
 enum { LAYER_MPO = 0, LAYER_HAD = 1 };
+constexpr int GRAPH_CHUNK = 16;
 
 struct Layer {
   int kind = LAYER_MPO;
@@ -158,7 +160,7 @@ struct Sweep {
       double *dst = bufs[1 - cur];
       const double *core = N.lay[l].core(d, rev);
       if (N.lay[l].kind == LAYER_MPO) {
-        mpo_layer(c, src, dst, core, pre, mi[l], mo[l], post, skip);
+        mpo_layer(c, src, dst, *N.lay[l].mpo, d, rev, pre, mi[l], mo[l], post, skip);
         cur = 1 - cur;
         continue;
       }
@@ -304,20 +306,270 @@ struct Sweep {
 
   int64_t centre_size(int i, int d) const { return v[i].core_size(d); }
 
+  // y = x + mu h^2 sum_j P_i^T D_i^T D_j P_j x_j: the four pair terms go out
+  // as one grouped launch per step (ket contraction, MPO layer, contraction
+  // with the right environment); the last also sums the two j terms of y_i
+  // and adds x_i, so no copy kernel is needed.
+  double *pT[4] = {nullptr, nullptr, nullptr, nullptr}, *pT2[4] = {nullptr, nullptr, nullptr, nullptr};
+
+  void alloc_pen_tmp() {
+    int64_t mx = 1;
+    for (int d = 0; d < n; ++d)
+      for (int k = 0; k < 4; ++k) {
+        const Net &N = pen[k];
+        const int i = k / 2, j = k % 2;
+        const int64_t a = v[i].bond[d], gp = v[j].bond[d + 1];
+        mx = std::max(mx, a * N.lay[0].bond(d) * 4 * gp);
+        mx = std::max(mx, a * N.lay[0].bond(d + 1) * 4 * gp);
+      }
+    for (int k = 0; k < 4; ++k) {
+      pT[k] = c.buf("sw_pT" + std::to_string(k), mx);
+      pT2[k] = c.buf("sw_pT2_" + std::to_string(k), mx);
+    }
+  }
+
   void matvec(int d, const double *x, double *y, const int *skip) {
-    const int64_t s0 = centre_size(0, d), s1 = centre_size(1, d);
-    copy_skip(x, y, s0 + s1, skip);
+    const int64_t s0 = centre_size(0, d);
     const double *xs[2] = {x, x + s0};
     double *ys[2] = {y, y + s0};
-    for (int i = 0; i < 2; ++i)
-      for (int j = 0; j < 2; ++j) {
-        Net &N = pen[2 * i + j];
-        chain(N, d, false, N.env + N.eoff[d], xs[j], Tpen, skip);
-        open_into(N, d, false, Tpen, ys[i], mu_h2, skip);
-      }
+    Gemm kg[4], og[4];
+    MpoJob mj[4];
+    int kgrp[4] = {0, 1, 2, 3}, ogrp[4];
+    const double *kX[4] = {nullptr, nullptr, nullptr, nullptr};
+    const double *oX[2] = {xs[0], xs[1]};
+    for (int k = 0; k < 4; ++k) {
+      const int i = k / 2, j = k % 2;
+      const Net &N = pen[k];
+      const int a = v[i].bond[d], ar = v[i].bond[d + 1];
+      const int g = v[j].bond[d], gp = v[j].bond[d + 1];
+      const int mi = N.lay[0].bond(d), mo = N.lay[0].bond(d + 1);
+      Gemm &q = kg[k];
+      q.M = a * mi;
+      q.N = 4 * gp;
+      q.K = g;
+      q.A = N.env + N.eoff[d];
+      q.sAm = g;
+      q.sAk = 1;
+      q.B = xs[j];
+      q.sBk = 4 * gp;
+      q.sBn = 1;
+      q.C = pT[k];
+      q.sCm = 4 * gp;
+      q.sCn = 1;
+      mj[k] = MpoJob{pT[k], pT2[k], N.lay[0].mpo, d, false, (int64_t)a, (int64_t)gp, mi, mo};
+      const int64_t rest = (int64_t)mo * gp;
+      Gemm &o = og[k];
+      o.M = 4 * a;
+      o.N = ar;
+      o.K = (int)rest;
+      o.A = pT2[k];
+      o.sAm = rest;
+      o.sAk = 1;
+      o.B = N.env + N.eoff[d + 1];
+      o.sBk = 1;
+      o.sBn = rest;
+      o.C = ys[i];
+      o.sCm = ar;
+      o.sCn = 1;
+      o.alpha = mu_h2;
+      o.beta = 1.0;
+      ogrp[k] = i;
+    }
+    gemm_grouped(c, 4, kg, 4, kgrp, kX, skip, false);
+    mpo_layer_grouped(c, 4, mj, skip);
+    gemm_grouped(c, 4, og, 2, ogrp, oX, skip, false);
   }
 
   void copy_skip(const double *x, double *y, int64_t n_, const int *skip);
+
+  // cached graph of GRAPH_CHUNK CG iterations at site d; the key holds every
+  // pointer and shape baked into the captured kernels
+  CgGraph *graph_for(int d, bool rev, bool pre, const double *x, const double *r,
+                     const double *pp, const double *q, const double *rhs) {
+    std::vector<int64_t> key;
+    auto add = [&](const void *ptr) { key.push_back((int64_t)(uintptr_t)ptr); };
+    key.push_back(d);
+    key.push_back(rev ? 1 : 0);
+    int64_t mh;
+    std::memcpy(&mh, &mu_h2, sizeof mh);
+    key.push_back(mh);
+    key.push_back(c.kt.on ? 1 : 0);
+    key.push_back(pre ? 1 : 0);
+    if (pre) {
+      add(pcM);
+      add(pcz);
+      key.push_back(pc_np0);
+    }
+    for (int i = 0; i < 2; ++i) {
+      key.push_back(v[i].bond[d]);
+      key.push_back(v[i].bond[d + 1]);
+    }
+    add(x);
+    add(r);
+    add(pp);
+    add(q);
+    add(rhs);
+    add(st);
+    add(part);
+    add(tmp);
+    add(Tpen);
+    add(c.kt.flop_ctr);
+    for (const Net &N : pen) {
+      add(N.env + N.eoff[d]);
+      add(N.env + N.eoff[d + 1]);
+      add(N.lay[0].mpo->csc[0].colptr);
+      key.push_back(N.lay[0].bond(d));
+      key.push_back(N.lay[0].bond(d + 1));
+    }
+    for (int k = 0; k < 4; ++k) {
+      add(pT[k]);
+      add(pT2[k]);
+    }
+    for (const char *nm : {"gemm_splitk64", "gemm_splitk32"}) {
+      auto it = c.bufs.find(nm);
+      add(it == c.bufs.end() ? nullptr : it->second.ptr);
+    }
+    const std::string k =
+        std::to_string(d) + (rev ? "r" : "f") + (pre ? "p" : "c") + std::to_string(mh);
+    CgGraph &g = c.cg_graphs[k];
+    if (g.exec && g.key != key) {
+      HIPC(hipGraphExecDestroy(g.exec));
+      g.exec = nullptr;
+    }
+    g.key = key;
+    return &g;
+  }
+
+  // ---- preconditioner of the local system at site d (QTT_PC_*)
+  double *pcM = nullptr, *pcz = nullptr;
+  int64_t pc_np0 = 0;
+
+  void apply_pc(const double *r, double *z, int d, const int *skip) {
+    const int64_t s0 = centre_size(0, d);
+    pc_apply(c, pcM, r, z, v[0].bond[d], v[0].bond[d + 1], skip);
+    pc_apply(c, pcM + pc_np0 * 16, r + s0, z + s0, v[1].bond[d], v[1].bond[d + 1], skip);
+  }
+
+  // features of both components, then M from the block inverse (block
+  // Jacobi) or from the network (learned; trained first when enabled)
+  void pc_setup(int d) {
+    const int64_t s0 = centre_size(0, d), ntot = s0 + centre_size(1, d);
+    const int64_t np[2] = {(int64_t)v[0].bond[d] * v[0].bond[d + 1],
+                           (int64_t)v[1].bond[d] * v[1].bond[d + 1]};
+    const int64_t rows = np[0] + np[1];
+    pc_np0 = np[0];
+    double *X = c.buf("pc_X", rows * PC_IN), *B = c.buf("pc_B", rows * 16);
+    pcM = c.buf("pc_M", rows * 16);
+    pcz = c.buf("pc_z", ntot);
+    for (int i = 0; i < 2; ++i) {
+      const Net &N = pen[3 * i];  // pair (i, i)
+      const int64_t r0 = i ? np[0] : 0;
+      pc_features(c, N.env + N.eoff[d], N.env + N.eoff[d + 1], *N.lay[0].mpo, d, v[i].bond[d],
+                  v[i].bond[d + 1], mu_h2, mu_h2 / (p.dx * p.dx), n, i, X + r0 * PC_IN,
+                  B + r0 * 16);
+    }
+    if (p.precond == QTT_PC_BLOCK_JACOBI) {
+      pc_block_inverse(c, B, pcM, rows);
+      return;
+    }
+    PrecondNet &net = c.pc;
+    if (net.train_per_solve > 0) {
+      double *z = c.buf("pc_probe", ntot), *Az = c.buf("pc_Az", ntot);
+      double *zz = c.buf("pc_zz", 1), *Mt = c.buf("pc_Mt", rows * 16);
+      for (int t = 0; t < net.train_per_solve; ++t) {
+        pc_probe(c, z, ntot, net.seed * 0x100000001B3ULL + net.probe_ctr);
+        net.probe_ctr += 2 * (uint64_t)ntot;
+        matvec(d, z, Az, nullptr);
+        dot(c, z, z, ntot, zz);
+        pc_forward(c, X, rows, Mt, true);
+        fill(c, net.loss_dev, 1, 0.0);
+        pc_loss_grad(c, Mt, 0, z, Az, v[0].bond[d], v[0].bond[d + 1], zz);
+        pc_loss_grad(c, Mt, np[0], z + s0, Az + s0, v[1].bond[d], v[1].bond[d + 1], zz);
+        pc_backward_adam(c, X, rows);
+      }
+      double *hl = c.pinned + 2048;
+      HIPC(hipMemcpyAsync(hl, net.loss_dev, sizeof(double), hipMemcpyDeviceToHost, c.stream));
+      c.sync();
+      if (net.first_loss < 0.0) net.first_loss = *hl;
+      net.last_loss = *hl;
+    }
+    pc_forward(c, X, rows, pcM, false);
+  }
+
+  // CG / PCG iterations until the device flag says done: the first chunk
+  // runs eagerly (it also allocates every buffer the iteration needs); later
+  // chunks replay a captured graph of GRAPH_CHUNK iterations, one graph per
+  // (site, direction, mu h^2, preconditioning)
+  void run_cg(int d, bool rev, bool pre, double *x, double *r, double *pp, double *q,
+              const double *rhs, int64_t ntot) {
+    auto enqueue_iters = [&](int k) {
+      for (int i = 0; i < k; ++i) {
+        matvec(d, pp, q, &st->done);
+        cg_alpha(c, pp, q, ntot, st, part);
+        cg_update(c, x, r, pp, q, ntot, st, part);
+        if (pre) {
+          apply_pc(r, pcz, d, &st->done);
+          pcg_next(c, r, pcz, pp, ntot, st, part);
+        } else {
+          cg_pupdate(c, r, pp, ntot, st);
+        }
+      }
+    };
+    const int first_chunk = 8;
+    enqueue_iters(first_chunk);
+    HIPC(hipMemcpyAsync(st_host, st, sizeof(CGState), hipMemcpyDeviceToHost, c.stream));
+    c.sync();
+    while (!st_host->done) {
+      CgGraph *g = c.use_graphs ? graph_for(d, rev, pre, x, r, pp, q, rhs) : nullptr;
+      if (g && !g->exec) {
+        c.capturing = true;
+        c.cap_launches[0] = c.cap_launches[1] = 0;
+        hipGraph_t graph = nullptr;
+        HIPC(hipStreamBeginCapture(c.stream, hipStreamCaptureModeRelaxed));
+        try {
+          enqueue_iters(GRAPH_CHUNK);
+        } catch (...) {
+          c.capturing = false;
+          (void)hipStreamEndCapture(c.stream, &graph);
+          if (graph) (void)hipGraphDestroy(graph);
+          (void)hipGetLastError();
+          throw;
+        }
+        c.capturing = false;
+        HIPC(hipStreamEndCapture(c.stream, &graph));
+        HIPC(hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0));
+        HIPC(hipGraphDestroy(graph));
+        g->launches[0] = c.cap_launches[0];
+        g->launches[1] = c.cap_launches[1];
+      }
+      if (g) {
+        HIPC(hipGraphLaunch(g->exec, c.stream));
+        c.kt.launches[0] += c.kt.on ? g->launches[0] : 0;
+        c.kt.launches[1] += c.kt.on ? g->launches[1] : 0;
+      } else {
+        enqueue_iters(GRAPH_CHUNK);
+      }
+      HIPC(hipMemcpyAsync(st_host, st, sizeof(CGState), hipMemcpyDeviceToHost, c.stream));
+      c.sync();
+    }
+  }
+
+  // r = rhs - A x on the device and the CG state reset (warm start from x)
+  void cg_start(int d, bool pre, double *x, double *r, double *pp, double *q, const double *rhs,
+                int64_t ntot) {
+    st_host->rtol = p.cg_rtol;
+    st_host->maxit = p.cg_maxit;
+    st_host->counter = 0;
+    st_host->done = 0;
+    st_host->precond = pre ? 1 : 0;
+    HIPC(hipMemcpyAsync(st, st_host, sizeof(CGState), hipMemcpyHostToDevice, c.stream));
+    matvec(d, x, q, nullptr);
+    cg_init(c, rhs, q, r, pp, x, ntot, st, part);
+    if (pre) {
+      apply_pc(r, pcz, d, &st->done);
+      pcg_start(c, r, pcz, pp, ntot, st, part);
+    }
+  }
 
   void local_solve(int d, bool rev) {
     const int64_t s0 = centre_size(0, d), s1 = centre_size(1, d), ntot = s0 + s1;
@@ -334,44 +586,51 @@ struct Sweep {
       chain(N, d, rev, E, ket_core(N, d, rev), N.T, nullptr);
       open_into(N, d, rev, N.T, rh[N.bra], N.coef, nullptr);
     }
-    HIPC(hipMemcpyAsync(x, v[0].core(d), s0 * sizeof(double), hipMemcpyDeviceToDevice, c.stream));
-    HIPC(hipMemcpyAsync(x + s0, v[1].core(d), s1 * sizeof(double), hipMemcpyDeviceToDevice,
-                        c.stream));
+    auto load_guess = [&] {
+      HIPC(hipMemcpyAsync(x, v[0].core(d), s0 * sizeof(double), hipMemcpyDeviceToDevice,
+                          c.stream));
+      HIPC(hipMemcpyAsync(x + s0, v[1].core(d), s1 * sizeof(double), hipMemcpyDeviceToDevice,
+                          c.stream));
+    };
+    load_guess();
     if (stats && c.timing) {
       c.sync();
       stats->phase_ms[2] += ms_since(t0);
     }
     t0 = std::chrono::steady_clock::now();
     // CG (Sec. II.C): device-resident scalars, host checks once per chunk
-    st_host->rtol = p.cg_rtol;
-    st_host->maxit = p.cg_maxit;
-    st_host->counter = 0;
-    st_host->done = 0;
-    HIPC(hipMemcpyAsync(st, st_host, sizeof(CGState), hipMemcpyHostToDevice, c.stream));
-    matvec(d, x, q, nullptr);
-    cg_init(c, rhs, q, r, pp, x, ntot, st, part);
-    const int chunk = 8;
-    for (;;) {
-      for (int k = 0; k < chunk; ++k) {
-        matvec(d, pp, q, &st->done);
-        cg_alpha(c, pp, q, ntot, st, part);
-        cg_update(c, x, r, pp, q, ntot, st, part);
-        cg_pupdate(c, r, pp, ntot, st);
-      }
+    const bool pre = p.precond != QTT_PC_NONE;
+    if (pre) pc_setup(d);
+    cg_start(d, pre, x, r, pp, q, rhs, ntot);
+    run_cg(d, rev, pre, x, r, pp, q, rhs, ntot);
+    int iters = st_host->iters;
+    bool converged = st_host->converged;
+    if (pre) {
+      // float64 judge: the true residual of the PCG result decides; plain CG
+      // continues from it (from the guess after a non-finite result) when it
+      // misses the tolerance
+      if (!(st_host->rr_new == st_host->rr_new)) load_guess();
+      cg_start(d, false, x, r, pp, q, rhs, ntot);
       HIPC(hipMemcpyAsync(st_host, st, sizeof(CGState), hipMemcpyDeviceToHost, c.stream));
       c.sync();
-      if (st_host->done) break;
+      if (!st_host->done) {
+        run_cg(d, rev, false, x, r, pp, q, rhs, ntot);
+        if (stats) stats->fallbacks += 1;
+        warn = std::max(warn, (int)QTT_W_PRECOND_FALLBACK);
+      }
+      iters += st_host->iters;
+      converged = st_host->converged;
     }
     if (stats) {
-      stats->cg_iters_total += st_host->iters;
-      stats->cg_iters_max = std::max(stats->cg_iters_max, st_host->iters);
+      stats->cg_iters_total += iters;
+      stats->cg_iters_max = std::max(stats->cg_iters_max, iters);
       stats->cg_solves += 1;
-      if (!st_host->converged) {
+      if (!converged) {
         stats->cg_maxit_hits += 1;
         warn = std::max(warn, (int)QTT_W_CG_MAXIT);
       }
       if (c.timing) stats->phase_ms[3] += ms_since(t0);
-    } else if (!st_host->converged) {
+    } else if (!converged) {
       warn = std::max(warn, (int)QTT_W_CG_MAXIT);
     }
     HIPC(hipMemcpyAsync(v[0].core(d), x, s0 * sizeof(double), hipMemcpyDeviceToDevice, c.stream));
@@ -514,7 +773,10 @@ void project(Ctx &c, const Mps a[2], const Mps b[2], double h, const qtt_params 
   if (n < 2) fail(QTT_E_UNSUPPORTED, "project: n < 2");
   if (p.max_sweeps < 1 || p.cg_maxit < 1) fail(QTT_E_ARG, "project: max_sweeps/cg_maxit < 1");
   if (p.prec != QTT_PREC_F64 && p.prec != QTT_PREC_F32) fail(QTT_E_ARG, "project: prec");
-  if (p.precond != QTT_PC_NONE) fail(QTT_E_UNSUPPORTED, "project: preconditioner not built");
+  if (p.precond != QTT_PC_NONE && p.precond != QTT_PC_BLOCK_JACOBI &&
+      p.precond != QTT_PC_LEARNED)
+    fail(QTT_E_ARG, "project: precond");
+  if (p.precond == QTT_PC_LEARNED) pc_init(c);
 
   auto t0 = std::chrono::steady_clock::now();
   Sweep S(c, p);
@@ -602,13 +864,13 @@ void project(Ctx &c, const Mps a[2], const Mps b[2], double h, const qtt_params 
   // device state: CG scalars, partial sums
   S.st = (CGState *)c.raw("sw_cgstate", sizeof(CGState));
   S.part = c.buf("sw_part", 2048);
-  if (!c.pinned) HIPC(hipHostMalloc((void **)&c.pinned, 4096 * sizeof(double), 0));
   S.st_host = (CGState *)c.pinned;
 
   std::vector<Net *> all;
   for (Net &N : S.rhs) all.push_back(&N);
   for (Net &N : S.pen) all.push_back(&N);
   S.alloc(all);
+  S.alloc_pen_tmp();
 
   // right environments, sites n-1 .. 1
   for (int d = n - 1; d >= 1; --d)

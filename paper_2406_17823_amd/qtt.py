@@ -59,7 +59,8 @@ class c_kstats(ctypes.Structure):
 
 SYMBOLS = ['qtt_kernel_timing', 'qtt_kernel_stats_read', 'qtt_ctx_create', 'qtt_ctx_destroy', 'qtt_last_error', 'qtt_mps_size',
            'qtt_mpo_derivative', 'qtt_add', 'qtt_truncate', 'qtt_apply_mpo', 'qtt_hadamard',
-           'qtt_inner', 'qtt_to_dense', 'qtt_from_dense', 'qtt_project', 'qtt_rk4_step']
+           'qtt_inner', 'qtt_to_dense', 'qtt_from_dense', 'qtt_project', 'qtt_rk4_step',
+           'qtt_precond_config', 'qtt_precond_info', 'qtt_precond_weights', 'qtt_precond_grad']
 
 _lib = None
 
@@ -93,6 +94,10 @@ def lib():
         'qtt_rk4_step': (I32, [P, pm, ctypes.POINTER(c_params), ctypes.POINTER(c_stats)]),
         'qtt_kernel_timing': (I32, [P, I32, I32]),
         'qtt_kernel_stats_read': (I32, [P, I32, ctypes.POINTER(c_kstats)]),
+        'qtt_precond_config': (I32, [P, I32, D, ctypes.c_uint64, I32]),
+        'qtt_precond_info': (I32, [P, ctypes.POINTER(I64), ctypes.POINTER(I64), pd, pd]),
+        'qtt_precond_weights': (I32, [P, I32, pd, I64]),
+        'qtt_precond_grad': (I32, [P, P, I64, P, P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -343,3 +348,50 @@ def kernel_stats(ctx, kernel):
     s = c_kstats()
     ctx.check(lib().qtt_kernel_stats_read(ctx.h, kernel, ctypes.byref(s)), 'kernel_stats_read')
     return dict(launches=s.launches, timed=s.timed, flops=s.flops, timed_ms=s.timed_ms)
+
+
+PC_IN, PC_WIDTH, PC_OUT = 16, 256, 10
+
+
+def precond_config(ctx, train_per_solve=0, lr=1e-3, seed=0x5eed, reset=False):
+    ctx.check(lib().qtt_precond_config(ctx.h, train_per_solve, lr, seed, 1 if reset else 0),
+              'precond_config')
+
+
+def precond_info(ctx):
+    n, s = ctypes.c_int64(), ctypes.c_int64()
+    f, l = ctypes.c_double(), ctypes.c_double()
+    ctx.check(lib().qtt_precond_info(ctx.h, ctypes.byref(n), ctypes.byref(s), ctypes.byref(f),
+                                     ctypes.byref(l)), 'precond_info')
+    return dict(nparam=n.value, steps=s.value, first_loss=f.value, last_loss=l.value)
+
+
+def precond_weights(ctx, w=None):
+    """Return the parameters (float64 numpy array), or set them when w is given."""
+    import numpy as np
+    n = precond_info(ctx)['nparam']
+    if w is None:
+        out = np.zeros(n)
+        ctx.check(lib().qtt_precond_weights(ctx.h, 0, out.ctypes.data_as(
+            ctypes.POINTER(ctypes.c_double)), n), 'precond_weights')
+        return out
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    ctx.check(lib().qtt_precond_weights(ctx.h, 1, w.ctypes.data_as(
+        ctypes.POINTER(ctypes.c_double)), w.size), 'precond_weights')
+    return w
+
+
+def precond_grad(ctx, X, dY):
+    """Network output Y and gradient of sum(dY * Y) for device float64 X, dY."""
+    assert X.dtype == torch.float64 and dY.dtype == torch.float64 and X.is_cuda and dY.is_cuda
+    X, dY = X.contiguous(), dY.contiguous()
+    npos = X.shape[0]
+    assert X.shape == (npos, PC_IN) and dY.shape == (npos, PC_OUT)
+    n = precond_info(ctx)['nparam']
+    Y = torch.empty(npos, PC_OUT, dtype=torch.float64, device=X.device)
+    g = torch.empty(n, dtype=torch.float64, device=X.device)
+    ctx.check(lib().qtt_precond_grad(ctx.h, ctypes.c_void_p(X.data_ptr()), npos,
+                                     ctypes.c_void_p(dY.data_ptr()), ctypes.c_void_p(Y.data_ptr()),
+                                     ctypes.c_void_p(g.data_ptr())), 'precond_grad')
+    return Y, g
+

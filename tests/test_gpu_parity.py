@@ -187,6 +187,27 @@ def test_project_matches_oracle(Q, ctx, flow, n, chi):
     assert abs(st['cg_iters_total'] - ost.cg_iters_total) <= 2 * ost.cg_solves
 
 
+def test_project_matches_oracle_split_k_matvec(Q, ctx):
+    """Bonds [.., 64, 64, 16, ..] make all four penalty-pair GEMMs of the CG
+    matvec at site 4 split their K dimension (four reduced outputs in one
+    grouped launch)."""
+    n, chi = 7, 64
+    dx = 1.0 / (1 << n)
+    u = I.spectrum(n, 2, k0=16.0)
+    b = _mps_pair(u, chi)
+    a = [M.scale(c, 0.25) for c in b]
+    h = 1e-4 / 3
+    prm = Q.params(re=1e3, dt=1e-4, chi=chi, dx=dx, max_sweeps=1)
+    v = [dev(Q, c) for c in a]
+    rc, st = Q.project(ctx, [dev(Q, c) for c in a], [dev(Q, c) for c in b], h, prm, v)
+    assert rc == 0
+    ref = S.project(a, b, h, S.Params(re=1e3, dt=1e-4, chi=chi, dx=dx, max_sweeps=1), a,
+                    S.Stats())
+    for i in range(2):
+        assert v[i].bonds == M.bonds(ref[i])
+        assert M.rel_l2(v[i].cores(), ref[i]) < TOL
+
+
 @pytest.mark.parametrize('flow,n,chi', [('shear', 5, 8), ('jet', 5, 8), ('spectrum', 6, 16)])
 def test_rk4_matches_oracle(Q, ctx, flow, n, chi):
     dx = 1.0 / (1 << n)

@@ -1,0 +1,133 @@
+"""GPU tests of the learned preconditioner of the local CG solves.
+
+* The network's forward and backward kernels (bfloat16 MFMA products) against
+  the float64 oracle network evaluated with the same bfloat16 operand
+  rounding (oracle/mlp.py), through qtt_precond_grad.
+* PCG with the block-Jacobi or the learned preconditioner reaches the same
+  projection as plain CG and as the oracle (the converged solution does not
+  depend on an SPD preconditioner).
+* On-line training lowers the probe loss; the CG iteration counts of the
+  trained network, block Jacobi and no preconditioner are measured and
+  printed (the gain is reported, not assumed).
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import mlp
+from oracle import mps as M
+from oracle import sweep as S
+from paper_2406_17823_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope='module')
+def Q():
+    from paper_2406_17823_amd import qtt
+    return qtt
+
+
+def _relf(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize('npos', [1, 77, 300])
+def test_network_forward_backward_match_oracle(Q, npos):
+    ctx = Q.Context(0)
+    rng = np.random.default_rng(11 + npos)
+    p = mlp.init(seed=3)
+    p['W3'] = rng.standard_normal(p['W3'].shape) * 0.05
+    p['b1'] = rng.standard_normal(256) * 0.1
+    p['b2'] = rng.standard_normal(256) * 0.1
+    p['b3'] = rng.standard_normal(10) * 0.1
+    Q.precond_config(ctx, 0, 1e-3, 1, reset=True)
+    Q.precond_weights(ctx, mlp.flatten(p))
+    assert np.array_equal(Q.precond_weights(ctx), mlp.flatten(p))
+    X = rng.standard_normal((npos, 16))
+    dY = rng.standard_normal((npos, 10))
+    Y, g = Q.precond_grad(ctx, torch.from_numpy(X).cuda(), torch.from_numpy(dY).cuda())
+    Y, g = Y.cpu().numpy(), g.cpu().numpy()
+    yo, cache = mlp.forward(p, X, mlp.bf16)
+    go = mlp.flatten(mlp.backward(p, cache, dY, mlp.bf16))
+    # same bfloat16 operands on both sides; what differs is float32 against
+    # float64 summation inside each 16-deep slice and the rare bfloat16
+    # rounding of an activation that lands on the other side of a tie
+    assert _relf(Y, yo) < 1e-3
+    w = mlp.flatten(p)
+    for k, (a, b) in enumerate(zip(np.split(g, np.cumsum([p[n].size for n in mlp.ORDER])[:-1]),
+                                   np.split(go, np.cumsum([p[n].size for n in mlp.ORDER])[:-1]))):
+        assert _relf(a, b) < 2e-3, mlp.ORDER[k]
+    ctx.close()
+
+
+def _setup(n, chi, seed):
+    dx = 1.0 / (1 << n)
+    u = I.spectrum(n, seed, k0=4.0)
+    b = [M.tt_svd(u[i], chi, 1e-12)[0] for i in range(2)]
+    a = [M.scale(c, 0.25) for c in b]
+    return dx, a, b
+
+
+def _project(Q, ctx, a, b, h, prm):
+    v = [Q.MPS.from_cores(c) for c in a]
+    rc, st = Q.project(ctx, [Q.MPS.from_cores(c) for c in a], [Q.MPS.from_cores(c) for c in b],
+                       h, prm, v)
+    return rc, st, [x.cores() for x in v]
+
+
+def test_pcg_reaches_the_cg_solution(Q):
+    n, chi = 6, 16
+    dx, a, b = _setup(n, chi, 21)
+    h = 2e-3 / 3
+    ctx = Q.Context(0)
+    Q.precond_config(ctx, 2, 1e-3, 5, reset=True)
+    out = {}
+    for pc in (Q.PC_NONE, Q.PC_BLOCK_JACOBI, Q.PC_LEARNED):
+        prm = Q.params(re=1e3, dt=2e-3, chi=chi, dx=dx, max_sweeps=2, cg_rtol=1e-12,
+                       precond=pc)
+        rc, st, v = _project(Q, ctx, a, b, h, prm)
+        assert rc in (0, 3), rc  # 3: the float64 judge ran plain CG after PCG
+        assert st['cg_maxit_hits'] == 0
+        out[pc] = v
+    ref = S.project(a, b, h, S.Params(re=1e3, dt=2e-3, chi=chi, dx=dx, max_sweeps=2), a,
+                    S.Stats())
+    for pc, v in out.items():
+        for i in range(2):
+            assert M.rel_l2(v[i], ref[i]) < 1e-9, (pc, i)
+    info = Q.precond_info(ctx)
+    assert info['steps'] > 0 and np.isfinite(info['last_loss'])
+    ctx.close()
+
+
+def test_training_lowers_loss_and_reports_gain(Q):
+    n, chi = 7, 32
+    ctx = Q.Context(0)
+    Q.precond_config(ctx, 4, 2e-3, 9, reset=True)
+    # train on the systems of a few projections of one flow
+    dx, a, b = _setup(n, chi, 31)
+    for k in range(3):
+        prm = Q.params(re=1e4, dt=1e-3, chi=chi, dx=dx, max_sweeps=1, cg_rtol=1e-10,
+                       precond=Q.PC_LEARNED)
+        _project(Q, ctx, a, b, 1e-3 / (3 if k % 2 else 6), prm)
+    info = Q.precond_info(ctx)
+    assert info['steps'] >= 4 * 2 * (n - 1) * 3
+    assert info['last_loss'] < info['first_loss'], info
+    # evaluate on another flow, training off
+    Q.precond_config(ctx, 0, 2e-3, 9)
+    dx, a, b = _setup(n, chi, 41)
+    iters, sols = {}, {}
+    for name, pc in (('none', Q.PC_NONE), ('block_jacobi', Q.PC_BLOCK_JACOBI),
+                     ('learned', Q.PC_LEARNED)):
+        prm = Q.params(re=1e4, dt=1e-3, chi=chi, dx=dx, max_sweeps=2, cg_rtol=1e-10,
+                       precond=pc)
+        rc, st, v = _project(Q, ctx, a, b, 1e-3 / 3, prm)
+        iters[name] = st['cg_iters_total']
+        sols[name] = v
+        iters[name + '_fallbacks'] = st['fallbacks']
+    for name in ('block_jacobi', 'learned'):
+        for i in range(2):
+            assert M.rel_l2(sols[name][i], sols['none'][i]) < 1e-8
+    print('\n[precond] probe loss first %.4g last %.4g; CG iterations %s' %
+          (info['first_loss'], info['last_loss'], iters), flush=True)
+    ctx.close()
