@@ -26,8 +26,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-PEAK = {0: 78.6, 1: 157.3}          # TFLOP/s: float64 MFMA, float32 MFMA (MI355X)
-KERNEL_NAME = {0: 'k_gemm<double> (float64 MFMA GEMM)', 1: 'k_gemm<float> (float32 MFMA GEMM)'}
+# MI355X dense MFMA peaks, TFLOP/s, by GEMM instantiation (float64 / float32)
+PEAK = {0: 78.6, 1: 157.3, 2: 78.6, 3: 157.3}
 
 
 def parse():
@@ -49,6 +49,11 @@ def parse():
     ap.add_argument('--precond', type=int, default=0)
     ap.add_argument('--sample-every', type=int, default=8)
     ap.add_argument('--cpu-sample', type=int, default=1, help='time the CPU oracle sample')
+    ap.add_argument('--save-state', default='', help='write the state after warm-up (.npz)')
+    ap.add_argument('--load-state', default='', help='start from a saved state (no spin-up)')
+    ap.add_argument('--calib-copy-mib', type=int, default=0,
+                    help='run one device-to-device copy of this many MiB before the timed '
+                         'steps (reference dispatch for hardware byte counters)')
     return ap.parse_args()
 
 
@@ -68,15 +73,13 @@ def rel_l2(Q, ctx, x, y, chi):
     return nd / ny
 
 
-def cpu_sample(n, chi, re, dt, gpu_env_ms):
-    """Oracle right-environment build of one projection stage at the
-    workload's size (all 20 networks, sites n-1..1) on a saturated state."""
-    import numpy as np
+def cpu_sample(uc, chi, re, dt):
+    """Oracle right-environment build of one projection stage (all 20
+    networks, sites n-1..1) on the benchmark's own state uc (two lists of
+    float64 cores), as the first RK4 stage builds it."""
     from oracle import mps as M
     from oracle import sweep as S
-    from paper_2406_17823_amd import inputs as I
-    u = I.spectrum(n, 5, k0=16.0)
-    uc = [M.tt_svd(u[i], chi, 1e-12)[0] for i in range(2)]
+    n = len(uc[0])
     a = [M.scale(c, 0.25) for c in uc]
     prm = S.Params(re=re, dt=dt, chi=chi, dx=1.0 / (1 << n))
     v = [M.right_canonicalize(x) for x in a]
@@ -90,7 +93,7 @@ def cpu_sample(n, chi, re, dt, gpu_env_ms):
     except Exception:
         cores = os.cpu_count()
     threads = int(os.environ.get('OMP_NUM_THREADS', cores))
-    return t, min(threads, cores), [M.bonds(x) for x in uc]
+    return t, min(threads, cores)
 
 
 def main():
@@ -108,9 +111,20 @@ def main():
     ctx = Q.Context(0)
     cap = Q.mps_size(Q.canonical_bonds(n, chi))
     t0 = time.perf_counter()
-    u0 = I.decaying_jet(n)
-    state = [Q.from_dense(ctx, torch.from_numpy(u0[c]).cuda(), chi, 1e-12, capacity=cap)
-             for c in range(2)]
+    if args.load_state:
+        import numpy as np
+        z = np.load(args.load_state)
+        state = []
+        for c in range(2):
+            bonds = [int(b) for b in z[f'bonds{c}']]
+            st_ = Q.MPS.empty(bonds, capacity=cap)
+            st_.data[:z[f'data{c}'].size] = torch.from_numpy(z[f'data{c}']).cuda()
+            state.append(st_)
+        args.spinup = 0
+    else:
+        u0 = I.decaying_jet(n)
+        state = [Q.from_dense(ctx, torch.from_numpy(u0[c]).cuda(), chi, 1e-12, capacity=cap)
+                 for c in range(2)]
     log('initial bonds', state[0].bonds, state[1].bonds, f'{time.perf_counter() - t0:.1f}s')
 
     def prm_for(path):
@@ -140,6 +154,20 @@ def main():
         log(f'warmup {w} {time.perf_counter() - t1:.2f}s bonds', state[0].bonds, state[1].bonds,
             'cg', st['cg_iters_total'], st['cg_iters_max'])
 
+    if args.save_state:
+        import numpy as np
+        sz = [Q.mps_size(x.bonds) for x in state]
+        np.savez(args.save_state, bonds0=np.array(state[0].bonds), bonds1=np.array(state[1].bonds),
+                 data0=state[0].data[:sz[0]].cpu().numpy(), data1=state[1].data[:sz[1]].cpu().numpy())
+    if args.calib_copy_mib > 0:
+        nel = args.calib_copy_mib * (1 << 20) // 8
+        src = torch.ones(nel, dtype=torch.float64, device='cuda')
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f'calibration copy of {args.calib_copy_mib} MiB done')
+        del src, dst
+
     paths = [p for p in args.paths.split(',') if p]
     results, finals, kstats = {}, {}, {}
     for path in paths:
@@ -148,6 +176,7 @@ def main():
         Q.kernel_timing(ctx, True, args.sample_every)
         cg_total, cg_solves = 0, 0
         torch.cuda.synchronize()
+        log(f'{path} timed window start ns {time.monotonic_ns()}')
         t1 = time.perf_counter()
         for s in range(args.steps):
             rc, st = Q.rk4_step(ctx, u, prm)
@@ -156,7 +185,8 @@ def main():
             log(f'{path} step {s} {time.perf_counter() - t1:.2f}s cg {st["cg_iters_total"]}')
         torch.cuda.synchronize()
         el = time.perf_counter() - t1
-        kstats[path] = {k: Q.kernel_stats(ctx, k) for k in (0, 1)}
+        log(f'{path} timed window end ns {time.monotonic_ns()}')
+        kstats[path] = {k: Q.kernel_stats(ctx, k) for k in Q.KERNEL_NAMES}
         Q.kernel_timing(ctx, False)
         results[path] = dict(seconds=el, steps_per_s=args.steps / el,
                              cg_iters_per_solve=cg_total / max(cg_solves, 1))
@@ -175,12 +205,12 @@ def main():
         s = ks[k]
         return (s['timed_ms'] / s['timed'] * s['launches']) if s['timed'] else 0.0
 
-    dom = max((0, 1), key=est_time)
+    dom = max(Q.KERNEL_NAMES, key=est_time)
     s = ks[dom]
     avg_ms = s['timed_ms'] / max(s['timed'], 1)
     flops_per_launch = s['flops'] / max(s['launches'], 1)
     achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
-    roofline = dict(bound='mfma', kernel=KERNEL_NAME[dom], achieved=round(achieved, 3),
+    roofline = dict(bound='mfma', kernel=Q.KERNEL_NAMES[dom], achieved=round(achieved, 3),
                     peak=PEAK[dom], unit='TFLOP/s', frac=round(achieved / PEAK[dom], 4),
                     traffic=None, launches=s['launches'], avg_launch_ms=round(avg_ms, 5),
                     flops_per_launch=flops_per_launch,
@@ -202,15 +232,16 @@ def main():
         rc, st = Q.project(tctx, a, u, args.dt / 6, prm, v)
         gpu_env_ms = st['phase_ms'][1]
         del tctx
-        t_cpu, cores, cpu_bonds = cpu_sample(n, chi, args.re, args.dt, gpu_env_ms)
+        uc = [state[0].cores(), state[1].cores()]
+        t_cpu, cores = cpu_sample(uc, chi, args.re, args.dt)
         step_s = results[main_path]['seconds'] / args.steps
         cpu_step_s = step_s * (t_cpu * 1e3) / max(gpu_env_ms, 1e-9)
         cpu = dict(value=round(1.0 / cpu_step_s, 6), unit='RK4 steps/s', cores=cores,
                    kind='oracle',
-                   sample=(f'oracle right-environment build of one projection stage (20 networks, '
-                           f'sites {n - 1}..1) at {1 << n}^2, chi={chi}, bonds {cpu_bonds[0]}: '
-                           f'{t_cpu:.1f} s on CPU vs {gpu_env_ms:.1f} ms for the same phase on the '
-                           f'GPU; steps/s scaled by that ratio'))
+                   sample=(f'oracle right-environment build of the first RK4 stage (20 networks, '
+                           f'sites {n - 1}..1) on the timed state ({1 << n}^2, chi={chi}): '
+                           f'{t_cpu:.1f} s on {cores} host threads vs {gpu_env_ms:.1f} ms for the '
+                           f'same phase on the GPU; RK4 steps/s scaled by that ratio'))
 
     line = dict(metric='RK4 steps/s, 2^11^2 grid chi=128, mixed vs FP64 plain at <=1e-5 rel L2',
                 value=round(results[main_path]['steps_per_s'], 5), unit='RK4 steps/s',

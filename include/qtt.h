@@ -191,12 +191,17 @@ int qtt_project(qtt_ctx *ctx, const qtt_mps *a, const qtt_mps *b, double h,
 int qtt_rk4_step(qtt_ctx *ctx, qtt_mps *u, const qtt_params *p, qtt_stats *stats);
 
 /* Kernel timing for roofline reporting.  While enabled, every launch of the
- * two GEMM kernels (0 = float64 MFMA, 1 = float32 MFMA) is counted, the
- * kernel adds the flops it executed (2 M N K per batch entry; 0 when it
- * returned early because its CG solve had converged) to a device counter,
- * and every sample_every-th launch is bracketed by HIP events on the
- * context stream.  Enabling starts a new window; reading synchronises the
- * stream. */
+ * GEMM kernel instantiations QTT_KERNEL_GEMM_* is counted, the kernel adds
+ * the flops it executed (2 M N K per batch entry; 0 when it returned early
+ * because its CG solve had converged) to a device counter, and every
+ * sample_every-th launch is bracketed by HIP events on the context stream.
+ * Enabling starts a new window; reading synchronises the stream. */
+enum {
+  QTT_KERNEL_GEMM_F64_T64 = 0,   /* k_gemm<double, 64, 64>   */
+  QTT_KERNEL_GEMM_F32_T64 = 1,   /* k_gemm<float, 64, 64>    */
+  QTT_KERNEL_GEMM_F64_T128 = 2,  /* k_gemm<double, 128, 128> */
+  QTT_KERNEL_GEMM_F32_T128 = 3   /* k_gemm<float, 128, 128>  */
+};
 typedef struct {
   int64_t launches;   /* launches in the window                          */
   int64_t timed;      /* launches bracketed by events                    */

@@ -7,13 +7,17 @@
 // One launch carries up to GEMM_GROUP independent problems (the four penalty
 // pair terms of a CG matvec go out as one launch per step).
 //
-// Tiling: 64 x 64 output tile per 256-thread workgroup (4 wave64s in a 2 x 2
-// arrangement, 32 x 32 per wave = 2 x 2 blocks of 16 x 16), K staged through
-// LDS in slices of 16.  The loader picks the thread-to-element map from the
-// operand's unit-stride dimension so that global loads stay coalesced.
+// Tiling: a 256-thread workgroup (4 wave64s in a 2 x 2 arrangement) owns a
+// BM x BN output tile, 128 x 128 when the launch has at least one such tile
+// per compute unit, else 64 x 64; each wave holds (BM/32) x (BN/32) MFMA
+// blocks of 16 x 16.  K is staged through LDS in slices of KT = 16 with two
+// LDS buffers: the next slice's global loads are issued into registers
+// before the current slice's MFMAs, so one barrier per slice suffices.  The
+// loader picks the thread-to-element map from the operand's unit-stride
+// dimension so that global loads stay coalesced.
 // float64: v_mfma_f64_16x16x4_f64; float32: v_mfma_f32_16x16x4_f32 with
 // float64 operands rounded to float32 on the way into LDS (float64 sums of
-// the float32 16-deep slices).
+// the float32 16-deep slices); bfloat16: v_mfma_f32_16x16x16_bf16.
 // When the output tiles cannot fill the 256 compute units, K is split across
 // workgroups; the partial tiles are summed in split order by a second kernel
 // (deterministic).  That kernel also sums several problems into one output
@@ -30,7 +34,7 @@ typedef __bf16 b4v __attribute__((ext_vector_type(4)));
 
 namespace {
 
-constexpr int MT = 64, NT = 64, KT = 16, PADM = 1;
+constexpr int KT = 16, PADM = 1;
 
 struct Prob {
   int M, N, K, B1, B2, tm, tn, ksplit, kchunk, direct;
@@ -53,89 +57,89 @@ struct GemmK {
   double flops;
 };
 
-template <typename T>
-__device__ inline void mfma_step(const T (*As)[MT + PADM], const T (*Bs)[NT + PADM], int lane,
-                                 int wm, int wn, d4v (&acc)[2][2]);
+// one KT-deep slice of MFMAs for a wave's FM x FN blocks of 16 x 16
+template <typename T, int FM, int FN, int LD>
+struct Mfma;
 
-template <>
-__device__ inline void mfma_step<double>(const double (*As)[MT + PADM],
-                                         const double (*Bs)[NT + PADM], int lane, int wm, int wn,
-                                         d4v (&acc)[2][2]) {
+template <int FM, int FN, int LD>
+struct Mfma<double, FM, FN, LD> {
+  __device__ static void step(const double (*As)[LD], const double (*Bs)[LD], int lane, int m0,
+                              int n0, d4v (&acc)[FM][FN]) {
 #pragma unroll
-  for (int kq = 0; kq < KT / 4; ++kq) {
-    const int kk = kq * 4 + (lane >> 4);
-    double a0 = As[kk][wm * 32 + (lane & 15)];
-    double a1 = As[kk][wm * 32 + 16 + (lane & 15)];
-    double b0 = Bs[kk][wn * 32 + (lane & 15)];
-    double b1 = Bs[kk][wn * 32 + 16 + (lane & 15)];
-    acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-    acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-    acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-    acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+    for (int kq = 0; kq < KT / 4; ++kq) {
+      const int kk = kq * 4 + (lane >> 4);
+      double a[FM], b[FN];
+#pragma unroll
+      for (int i = 0; i < FM; ++i) a[i] = As[kk][m0 + i * 16 + (lane & 15)];
+#pragma unroll
+      for (int j = 0; j < FN; ++j) b[j] = Bs[kk][n0 + j * 16 + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
   }
-}
+};
 
-template <>
-__device__ inline void mfma_step<float>(const float (*As)[MT + PADM], const float (*Bs)[NT + PADM],
-                                        int lane, int wm, int wn, d4v (&acc)[2][2]) {
-  f4v f[2][2];
+template <int FM, int FN, int LD>
+struct Mfma<float, FM, FN, LD> {
+  __device__ static void step(const float (*As)[LD], const float (*Bs)[LD], int lane, int m0,
+                              int n0, d4v (&acc)[FM][FN]) {
+    f4v f[FM][FN];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < FM; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
-      f[i][j] = f4v{0.f, 0.f, 0.f, 0.f};
+      for (int j = 0; j < FN; ++j) f[i][j] = f4v{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-  for (int kq = 0; kq < KT / 4; ++kq) {
-    const int kk = kq * 4 + (lane >> 4);
-    float a0 = As[kk][wm * 32 + (lane & 15)];
-    float a1 = As[kk][wm * 32 + 16 + (lane & 15)];
-    float b0 = Bs[kk][wn * 32 + (lane & 15)];
-    float b1 = Bs[kk][wn * 32 + 16 + (lane & 15)];
-    f[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, f[0][0], 0, 0, 0);
-    f[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, f[0][1], 0, 0, 0);
-    f[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, f[1][0], 0, 0, 0);
-    f[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, f[1][1], 0, 0, 0);
+    for (int kq = 0; kq < KT / 4; ++kq) {
+      const int kk = kq * 4 + (lane >> 4);
+      float a[FM], b[FN];
+#pragma unroll
+      for (int i = 0; i < FM; ++i) a[i] = As[kk][m0 + i * 16 + (lane & 15)];
+#pragma unroll
+      for (int j = 0; j < FN; ++j) b[j] = Bs[kk][n0 + j * 16 + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+          f[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], f[i][j], 0, 0, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[i][j][r] += (double)f[i][j][r];
   }
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) acc[i][j][r] += (double)f[i][j][r];
-}
+};
 
 // bfloat16 operands, float32 accumulation (v_mfma_f32_16x16x16_bf16): lane l
 // holds A[l % 16][4 (l / 16) + 0..3] and B[4 (l / 16) + 0..3][l % 16]
-template <>
-__device__ inline void mfma_step<__bf16>(const __bf16 (*As)[MT + PADM],
-                                         const __bf16 (*Bs)[NT + PADM], int lane, int wm, int wn,
-                                         d4v (&acc)[2][2]) {
-  f4v f[2][2];
+template <int FM, int FN, int LD>
+struct Mfma<__bf16, FM, FN, LD> {
+  __device__ static void step(const __bf16 (*As)[LD], const __bf16 (*Bs)[LD], int lane, int m0,
+                              int n0, d4v (&acc)[FM][FN]) {
+    b4v a[FM], b[FN];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+    for (int e = 0; e < 4; ++e) {
+      const int kk = 4 * (lane >> 4) + e;
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
-      f[i][j] = f4v{0.f, 0.f, 0.f, 0.f};
-  b4v a0, a1, b0, b1;
+      for (int i = 0; i < FM; ++i) a[i][e] = As[kk][m0 + i * 16 + (lane & 15)];
 #pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    const int kk = 4 * (lane >> 4) + e;
-    a0[e] = As[kk][wm * 32 + (lane & 15)];
-    a1[e] = As[kk][wm * 32 + 16 + (lane & 15)];
-    b0[e] = Bs[kk][wn * 32 + (lane & 15)];
-    b1[e] = Bs[kk][wn * 32 + 16 + (lane & 15)];
+      for (int j = 0; j < FN; ++j) b[j][e] = Bs[kk][n0 + j * 16 + (lane & 15)];
+    }
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j) {
+        const f4v f = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], f4v{0.f, 0.f, 0.f, 0.f},
+                                                                0, 0, 0);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[i][j][r] += (double)f[r];
+      }
   }
-  f[0][0] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a0, b0, f[0][0], 0, 0, 0);
-  f[0][1] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a0, b1, f[0][1], 0, 0, 0);
-  f[1][0] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1, b0, f[1][0], 0, 0, 0);
-  f[1][1] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1, b1, f[1][1], 0, 0, 0);
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) acc[i][j][r] += (double)f[i][j][r];
-}
+};
 
 template <typename T>
 __device__ inline T to_op(double v) {
@@ -146,12 +150,16 @@ __device__ inline __bf16 to_op<__bf16>(double v) {
   return (__bf16)(float)v;
 }
 
-template <typename T>
+template <typename T, int BM, int BN>
 __global__ __launch_bounds__(256) void k_gemm(GemmK g) {
   if (g.skip && *g.skip) return;
   if (g.flop_ctr && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(g.flop_ctr, g.flops);
-  __shared__ T As[KT][MT + PADM];
-  __shared__ T Bs[KT][NT + PADM];
+  constexpr int FM = BM / 32, FN = BN / 32;    // 16 x 16 blocks per wave
+  constexpr int AL = BM * KT / 256, BL = BN * KT / 256;  // global loads per thread
+  static_assert(BM == BN, "square tiles: the MFMA step takes one LDS pitch");
+  constexpr int LDA = BM + PADM, LDB = BN + PADM;
+  __shared__ T As[2][KT][LDA];
+  __shared__ T Bs[2][KT][LDB];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -164,7 +172,17 @@ __global__ __launch_bounds__(256) void k_gemm(GemmK g) {
     if (i < g.np && (int64_t)blockIdx.x >= g.p[i].block0) pi = i;
   const Prob &P = g.p[pi];
 
-  const int64_t bid = (int64_t)blockIdx.x - P.block0;
+  int64_t bid = (int64_t)blockIdx.x - P.block0;
+  // single-problem launches: workgroups are dealt round-robin to the 8 XCDs
+  // (each with its own L2), so renumber the blocks such that every XCD walks
+  // a contiguous range of tiles, N-tile fastest: the tiles sharing an A row
+  // panel then run back to back on one XCD and read it from its L2
+  const bool xcd = (g.np == 1) && (P.tn > 1);
+  if (xcd) {
+    const int64_t total = (int64_t)P.tm * P.tn * P.ksplit * P.B1 * P.B2;
+    const int64_t l8 = total & ~(int64_t)7;
+    if (bid < l8) bid = (bid & 7) * (l8 >> 3) + (bid >> 3);
+  }
   const int tiles = P.tm * P.tn;
   const int t = (int)(bid % tiles);
   int64_t bb = bid / tiles;
@@ -174,69 +192,82 @@ __global__ __launch_bounds__(256) void k_gemm(GemmK g) {
   const int b2 = (int)(bb / P.B1);
   const int kbeg = ks * P.kchunk;
   const int kend = min(P.K, kbeg + P.kchunk);
-  const int m0 = (t % P.tm) * MT;
-  const int n0 = (t / P.tm) * NT;
+  const int m0 = (xcd ? (t / P.tn) : (t % P.tm)) * BM;
+  const int n0 = (xcd ? (t % P.tn) : (t / P.tm)) * BN;
 
   const double *A = P.A + b1 * P.sAb1 + b2 * P.sAb2;
   const double *B = P.B + b1 * P.sBb1 + b2 * P.sBb2;
   const bool a_m_unit = (P.sAm == 1);
   const bool b_n_unit = (P.sBn == 1);
 
-  d4v acc[2][2];
+  d4v acc[FM][FN];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < FM; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = d4v{0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < FN; ++j) acc[i][j] = d4v{0.0, 0.0, 0.0, 0.0};
 
-  for (int k0 = kbeg; k0 < kend; k0 += KT) {
+  double ra[AL], rb[BL];
+  auto gload = [&](int k0) {
 #pragma unroll
-    for (int i = 0; i < (MT * KT) / 256; ++i) {
+    for (int i = 0; i < AL; ++i) {
       const int idx = tid + 256 * i;
-      int mm, kk;
-      if (a_m_unit) {
-        mm = idx & (MT - 1);
-        kk = idx / MT;
-      } else {
-        mm = idx / KT;
-        kk = idx & (KT - 1);
-      }
+      const int mm = a_m_unit ? (idx % BM) : (idx / KT);
+      const int kk = a_m_unit ? (idx / BM) : (idx % KT);
       const int gm = m0 + mm, gk = k0 + kk;
-      double v = 0.0;
-      if (gm < P.M && gk < kend) v = A[gm * P.sAm + gk * P.sAk];
-      As[kk][mm] = to_op<T>(v);
+      ra[i] = (gm < P.M && gk < kend) ? A[gm * P.sAm + gk * P.sAk] : 0.0;
     }
 #pragma unroll
-    for (int i = 0; i < (NT * KT) / 256; ++i) {
+    for (int i = 0; i < BL; ++i) {
       const int idx = tid + 256 * i;
-      int nn, kk;
-      if (b_n_unit) {
-        nn = idx & (NT - 1);
-        kk = idx / NT;
-      } else {
-        nn = idx / KT;
-        kk = idx & (KT - 1);
-      }
+      const int nn = b_n_unit ? (idx % BN) : (idx / KT);
+      const int kk = b_n_unit ? (idx / BN) : (idx % KT);
       const int gn = n0 + nn, gk = k0 + kk;
-      double v = 0.0;
-      if (gn < P.N && gk < kend) v = B[gk * P.sBk + gn * P.sBn];
-      Bs[kk][nn] = to_op<T>(v);
+      rb[i] = (gn < P.N && gk < kend) ? B[gk * P.sBk + gn * P.sBn] : 0.0;
     }
-    __syncthreads();
-    mfma_step<T>(As, Bs, lane, wm, wn, acc);
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < AL; ++i) {
+      const int idx = tid + 256 * i;
+      const int mm = a_m_unit ? (idx % BM) : (idx / KT);
+      const int kk = a_m_unit ? (idx / BM) : (idx % KT);
+      As[buf][kk][mm] = to_op<T>(ra[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < BL; ++i) {
+      const int idx = tid + 256 * i;
+      const int nn = b_n_unit ? (idx % BN) : (idx / KT);
+      const int kk = b_n_unit ? (idx / BN) : (idx % KT);
+      Bs[buf][kk][nn] = to_op<T>(rb[i]);
+    }
+  };
+
+  if (kbeg < kend) {
+    gload(kbeg);
+    sstore(0);
     __syncthreads();
   }
+  int buf = 0;
+  for (int k0 = kbeg; k0 < kend; k0 += KT) {
+    const bool more = k0 + KT < kend;
+    if (more) gload(k0 + KT);
+    Mfma<T, FM, FN, LDA>::step(As[buf], Bs[buf], lane, wm * (BM / 2), wn * (BN / 2), acc);
+    if (more) sstore(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
 
-  // D(16x16): lane l holds column l % 16.  float32 16x16x4: register r is row
-  // 4*(l/16) + r; float64 16x16x4: register r is row 4*r + l/16.
+  // D(16x16): lane l holds column l % 16.  float32 / bfloat16: register r is
+  // row 4*(l/16) + r; float64 16x16x4: register r is row 4*r + l/16.
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < FM; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < FN; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = (sizeof(T) == 8) ? (4 * r + (lane >> 4)) : ((lane >> 4) * 4 + r);
-        const int gm = m0 + wm * 32 + i * 16 + row;
-        const int gn = n0 + wn * 32 + j * 16 + (lane & 15);
+        const int gm = m0 + wm * (BM / 2) + i * 16 + row;
+        const int gn = n0 + wn * (BN / 2) + j * 16 + (lane & 15);
         if (gm < P.M && gn < P.N) {
           if (!P.direct) {
             const int64_t bidx = (int64_t)b2 * P.B1 + b1;
@@ -341,6 +372,12 @@ void launch_group(Ctx &c, int np, const Gemm *q, int ngroups, const int *group,
   int64_t part_need = 0;
   int64_t part_off[GEMM_GROUP] = {0};
   int keep[GEMM_GROUP];
+  // 128 x 128 tiles when the launch has one per compute unit, else 64 x 64
+  int64_t tiles128 = 0;
+  for (int i = 0; i < np; ++i)
+    tiles128 += (int64_t)((q[i].M + 127) / 128) * ((q[i].N + 127) / 128) * q[i].B1 * q[i].B2;
+  const bool big = tiles128 >= 256;
+  const int MT = big ? 128 : 64, NT = MT;
   int64_t grp_tiles = 0;
   for (int i = 0; i < np; ++i)
     grp_tiles += (int64_t)((q[i].M + MT - 1) / MT) * ((q[i].N + NT - 1) / NT) * q[i].B1 * q[i].B2;
@@ -410,14 +447,15 @@ void launch_group(Ctx &c, int np, const Gemm *q, int ngroups, const int *group,
 
   bool timed = false;
   std::pair<hipEvent_t, hipEvent_t> ev;
-  if (c.kt.on && kind < 2) g.flop_ctr = c.kt.flop_ctr + kind;
+  const int tk = kind + (big ? 2 : 0);  // timer kind
+  if (c.kt.on && kind < 2) g.flop_ctr = c.kt.flop_ctr + tk;
   if (c.capturing) {
-    if (kind < 2) c.cap_launches[kind] += 1;
+    if (kind < 2) c.cap_launches[tk] += 1;
   } else if (c.kt.on && kind < 2) {
-    timed = (c.kt.launches[kind] % c.kt.every) == 0;
-    c.kt.launches[kind] += 1;
+    timed = (c.kt.launches[tk] % c.kt.every) == 0;
+    c.kt.launches[tk] += 1;
     if (timed) {
-      if (c.kt.pending[kind].size() >= 16384) c.resolve_events();
+      if (c.kt.pending[tk].size() >= 16384) c.resolve_events();
       ev.first = c.take_event();
       ev.second = c.take_event();
       HIPC(hipEventRecord(ev.first, c.stream));
@@ -430,14 +468,17 @@ void launch_group(Ctx &c, int np, const Gemm *q, int ngroups, const int *group,
     sev.second = c.take_event();
     HIPC(hipEventRecord(sev.first, c.stream));
   }
-  hipLaunchKernelGGL(k_gemm<T>, dim3((unsigned)blocks), dim3(256), 0, c.stream, g);
+  if (big)
+    hipLaunchKernelGGL((k_gemm<T, 128, 128>), dim3((unsigned)blocks), dim3(256), 0, c.stream, g);
+  else
+    hipLaunchKernelGGL((k_gemm<T, 64, 64>), dim3((unsigned)blocks), dim3(256), 0, c.stream, g);
   HIPC(hipGetLastError());
   if (shape_rec) {
     HIPC(hipEventRecord(sev.second, c.stream));
     char key[200];
     const Prob &P = g.p[0];
-    std::snprintf(key, sizeof key, "%s x%d M=%d N=%d K=%d B=%dx%d split=%d %s%s",
-                  kind == 0 ? "f64" : (kind == 1 ? "f32" : "bf16"), g.np, P.M, P.N, P.K, P.B1, P.B2, P.ksplit,
+    std::snprintf(key, sizeof key, "%s x%d M=%d N=%d K=%d B=%dx%d split=%d t%d %s%s",
+                  kind == 0 ? "f64" : (kind == 1 ? "f32" : "bf16"), g.np, P.M, P.N, P.K, P.B1, P.B2, P.ksplit, MT,
                   P.sAm == 1 ? "Am" : "Ak", P.sBn == 1 ? "Bn" : "Bk");
     c.shape_pending.push_back({key, sev});
     c.shape_flops_pending.push_back(g.flops);
@@ -445,7 +486,7 @@ void launch_group(Ctx &c, int np, const Gemm *q, int ngroups, const int *group,
   }
   if (timed) {
     HIPC(hipEventRecord(ev.second, c.stream));
-    c.kt.pending[kind].push_back(ev);
+    c.kt.pending[tk].push_back(ev);
   }
   // reduction of split / summed outputs
   if (part_need > 0) {

@@ -4,6 +4,11 @@
 //
 //  * Householder QR with explicit Q and a non-negative diagonal of R: the
 //    centre shifts of the sweep and the left-to-right pass of TT-rounding.
+//    Small matrices take one workgroup each; larger ones (up to the
+//    2048 x 512 unfoldings of a four-term RK4 sum at chi = 128) use the blocked
+//    form: a panel of QR_NB columns is factorised by one workgroup per
+//    matrix, its reflectors are aggregated into I - V T V^T (compact WY), and
+//    the trailing columns and the explicit Q are updated by MFMA GEMMs.
 //  (the SVD of the right-to-left pass of TT-rounding is in k_svd.hip)
 //
 // The working matrix lives column-major in a workspace slice in HBM/L2 so
@@ -130,9 +135,537 @@ __global__ __launch_bounds__(LA_THREADS) void k_qr(QRBatch batch) {
   }
 }
 
+// ---------------------------------------------------------------- blocked QR
+constexpr int QR_NB = 16;
+constexpr int QR_REG_THREADS = 512, QR_REG_WAVES = QR_REG_THREADS / 64;
+constexpr int QR_REG_ROWS = 4;  // rows per thread of the register-resident panel
+
+struct QrbDesc {
+  const double *A;
+  int64_t ars, acs;
+  double *W;    // m x n column-major working matrix (R above, reflectors below)
+  double *V;    // m x k column-major: reflector c in column c (1 at row c, 0 above)
+  double *VT;   // m x k: panel p's columns hold V_p T_p
+  double *VTt;  // m x k: panel p's columns hold V_p T_p^T
+  double *Qw;   // m x k column-major explicit Q (before the sign fix)
+  double *T;    // QR_NB x QR_NB: the current panel's T (upper triangular)
+  double *Q;
+  int64_t qrs, qcs;
+  double *R;
+  int64_t rrs, rcs;
+  int m, n, k;
+};
+struct QrbBatch {
+  int count;
+  QrbDesc d[MAX_BATCH];
+};
+
+__global__ void k_qrb_load(QrbBatch B) {
+  const QrbDesc &D = B.d[blockIdx.y];
+  const int64_t tot = (int64_t)D.m * D.n;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < tot;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(idx % D.m), j = (int)(idx / D.m);
+    D.W[idx] = D.A[i * D.ars + j * D.acs];
+  }
+  const int64_t tq = (int64_t)D.m * D.k;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < tq;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(idx % D.m), j = (int)(idx / D.m);
+    D.Qw[idx] = (i == j) ? 1.0 : 0.0;
+  }
+}
+
+// sum of nv per-thread values over the workgroup; result in red[0..nv)
+// (valid after return in every thread)
+__device__ inline void block_sum_vec(const double (&vals)[QR_NB], int nv,
+                                     double (*sh)[QR_NB + 1], double *red) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int t = 0; t < QR_NB; ++t) {
+    if (t < nv) {
+      const double s = wave_sum(vals[t]);
+      if (lane == 0) sh[wave][t] = s;
+    }
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < nv) {
+    double s = 0.0;
+    for (int w = 0; w < LA_WAVES; ++w) s += sh[w][threadIdx.x];
+    red[threadIdx.x] = s;
+  }
+  __syncthreads();
+}
+
+// factorise columns [j0, j0 + jb) of each matrix (rows j0..m); every thread
+// owns the rows r = tid + LA_THREADS * s throughout, so reflector entries
+// are produced and consumed by the same thread
+__global__ __launch_bounds__(LA_THREADS) void k_qrb_panel(QrbBatch B, int j0) {
+  const QrbDesc &D = B.d[blockIdx.x];
+  const int m = D.m, k = D.k;
+  const int jb = min(QR_NB, k - j0);
+  if (jb <= 0) return;
+  const int tid = threadIdx.x;
+  __shared__ double sh[LA_WAVES][QR_NB + 1];
+  __shared__ double red[QR_NB + 1];
+  __shared__ double T[QR_NB][QR_NB + 1];
+  double *W = D.W, *V = D.V;
+  for (int i = 0; i < jb; ++i) {
+    const int c = j0 + i;
+    double *wc = W + (int64_t)c * m;
+    double part = 0.0;
+    for (int r = tid; r < m; r += LA_THREADS)
+      if (r > c) part += wc[r] * wc[r];
+    part = wave_sum(part);
+    if ((tid & 63) == 0) sh[tid >> 6][0] = part;
+    __syncthreads();
+    if (tid == 0) {
+      double s2 = 0.0;
+      for (int w = 0; w < LA_WAVES; ++w) s2 += sh[w][0];
+      red[QR_NB] = s2;
+    }
+    __syncthreads();
+    const double xnorm2 = red[QR_NB];
+    const double alpha = wc[c];
+    double tau = 0.0, beta = alpha, sc = 0.0;
+    if (xnorm2 > 0.0) {
+      beta = -copysign(sqrt(alpha * alpha + xnorm2), alpha);
+      tau = (beta - alpha) / beta;
+      sc = 1.0 / (alpha - beta);
+    }
+    __syncthreads();  // every thread has read alpha before row c is overwritten
+    // reflector: column c of V (zeros on rows j0..c-1), below-diagonal part of W
+    double d[QR_NB];
+#pragma unroll
+    for (int t = 0; t < QR_NB; ++t) d[t] = 0.0;
+    for (int r = tid; r < m; r += LA_THREADS) {
+      if (r < j0) continue;
+      double v = 0.0;
+      if (r == c) {
+        v = 1.0;
+        wc[r] = beta;
+      } else if (r > c) {
+        v = wc[r] * sc;
+        wc[r] = v;
+      }
+      V[(int64_t)c * m + r] = v;
+      if (r >= c) {
+#pragma unroll
+        for (int t = 0; t < QR_NB; ++t)
+          if (t < jb && t != i) d[t] += v * W[(int64_t)(j0 + t) * m + r];
+      }
+    }
+    block_sum_vec(d, jb, sh, red);
+    // H_c on the panel's trailing columns
+    for (int r = tid; r < m; r += LA_THREADS) {
+      if (r < c) continue;
+      const double v = V[(int64_t)c * m + r];
+      for (int t = i + 1; t < jb; ++t) W[(int64_t)(j0 + t) * m + r] -= tau * red[t] * v;
+    }
+    // T[0:i, i] = -tau T[0:i, 0:i] (V_{0:i}^T v_c), T[i][i] = tau
+    if (tid < i) {
+      double s = 0.0;
+      for (int u = tid; u < i; ++u) s += T[tid][u] * red[u];
+      T[tid][i] = -tau * s;
+    }
+    if (tid == 0) T[i][i] = tau;
+    __syncthreads();
+  }
+  // T_p for the aggregation kernel
+  for (int e = tid; e < QR_NB * QR_NB; e += LA_THREADS) {
+    const int t = e / QR_NB, u = e % QR_NB;
+    D.T[e] = (t < jb && u < jb && u >= t) ? T[t][u] : 0.0;
+  }
+}
+
+// register-resident panel for m <= QR_REG_ROWS * QR_REG_THREADS: thread tid
+// holds rows r = tid + QR_REG_THREADS * s of the panel's columns, so each column
+// step touches HBM/L2 not at all; the column loop is unrolled so that every
+// register index is a compile-time constant
+__global__ __launch_bounds__(QR_REG_THREADS) void k_qrb_panel_reg(QrbBatch B, int j0) {
+  const QrbDesc &D = B.d[blockIdx.x];
+  const int m = D.m, k = D.k;
+  const int jb = min(QR_NB, k - j0);
+  if (jb <= 0 || m > QR_REG_ROWS * QR_REG_THREADS) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  __shared__ double sh[QR_REG_WAVES][QR_NB + 1];
+  __shared__ double red[QR_NB + 2];
+  __shared__ double T[QR_NB][QR_NB + 1];
+  double P[QR_REG_ROWS][QR_NB];
+#pragma unroll
+  for (int s = 0; s < QR_REG_ROWS; ++s) {
+    const int r = tid + QR_REG_THREADS * s;
+#pragma unroll
+    for (int t = 0; t < QR_NB; ++t)
+      P[s][t] = (r >= j0 && r < m && t < jb) ? D.W[(int64_t)(j0 + t) * m + r] : 0.0;
+  }
+  // column loop (not unrolled): register columns are selected with
+  // compile-time indices and a predicate, never indexed by i
+  for (int i = 0; i < jb; ++i) {
+    const int c = j0 + i;
+    double pc[QR_REG_ROWS];
+#pragma unroll
+    for (int s = 0; s < QR_REG_ROWS; ++s) {
+      pc[s] = 0.0;
+#pragma unroll
+      for (int t = 0; t < QR_NB; ++t)
+        if (t == i) pc[s] = P[s][t];
+    }
+    // squared norm below the diagonal; the owner of row c publishes alpha
+    double part = 0.0;
+#pragma unroll
+    for (int s = 0; s < QR_REG_ROWS; ++s) {
+      const int r = tid + QR_REG_THREADS * s;
+      if (r > c && r < m) part += pc[s] * pc[s];
+      if (r == c) red[QR_NB + 1] = pc[s];
+    }
+    part = wave_sum(part);
+    if (lane == 0) sh[wave][QR_NB] = part;
+    __syncthreads();
+    if (tid == 0) {
+      double s2 = 0.0;
+      for (int w = 0; w < QR_REG_WAVES; ++w) s2 += sh[w][QR_NB];
+      red[QR_NB] = s2;
+    }
+    __syncthreads();
+    const double xnorm2 = red[QR_NB];
+    const double alpha = red[QR_NB + 1];
+    double tau = 0.0, beta = alpha, sc = 0.0;
+    if (xnorm2 > 0.0) {
+      beta = -copysign(sqrt(alpha * alpha + xnorm2), alpha);
+      tau = (beta - alpha) / beta;
+      sc = 1.0 / (alpha - beta);
+    }
+    // reflector into column i (beta on the diagonal), dots with the other columns
+    double d[QR_NB];
+#pragma unroll
+    for (int t = 0; t < QR_NB; ++t) d[t] = 0.0;
+    double vr[QR_REG_ROWS];
+#pragma unroll
+    for (int s = 0; s < QR_REG_ROWS; ++s) {
+      const int r = tid + QR_REG_THREADS * s;
+      double v = 0.0, nv = pc[s];
+      if (r == c) {
+        v = 1.0;
+        nv = beta;
+      } else if (r > c && r < m) {
+        v = pc[s] * sc;
+        nv = v;
+      }
+      vr[s] = v;
+#pragma unroll
+      for (int t = 0; t < QR_NB; ++t) {
+        if (t == i) P[s][t] = nv;
+        else d[t] += v * P[s][t];
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < QR_NB; ++t) {
+      if (t < jb) {
+        const double sum = wave_sum(d[t]);
+        if (lane == 0) sh[wave][t] = sum;
+      }
+    }
+    __syncthreads();
+    if (tid < jb) {
+      double s2 = 0.0;
+      for (int w = 0; w < QR_REG_WAVES; ++w) s2 += sh[w][tid];
+      red[tid] = s2;
+    }
+    __syncthreads();
+    // H_c on the panel's trailing columns
+#pragma unroll
+    for (int t = 0; t < QR_NB; ++t) {
+      if (t > i && t < jb) {
+        const double f = tau * red[t];
+#pragma unroll
+        for (int s = 0; s < QR_REG_ROWS; ++s) P[s][t] -= f * vr[s];
+      }
+    }
+    // T[0:i, i] = -tau T[0:i, 0:i] (V_{0:i}^T v_c), T[i][i] = tau
+    if (tid < i) {
+      double s2 = 0.0;
+      for (int u = tid; u < i; ++u) s2 += T[tid][u] * red[u];
+      T[tid][i] = -tau * s2;
+    }
+    if (tid == 0) T[i][i] = tau;
+    __syncthreads();
+  }
+  // write back: W panel (R entries and reflectors), V (unit diagonal, zeros above), T
+#pragma unroll
+  for (int s = 0; s < QR_REG_ROWS; ++s) {
+    const int r = tid + QR_REG_THREADS * s;
+    if (r < j0 || r >= m) continue;
+#pragma unroll
+    for (int t = 0; t < QR_NB; ++t) {
+      if (t < jb) {
+        const int c = j0 + t;
+        D.W[(int64_t)c * m + r] = P[s][t];
+        D.V[(int64_t)c * m + r] = (r < c) ? 0.0 : (r == c ? 1.0 : P[s][t]);
+      }
+    }
+  }
+  for (int e = tid; e < QR_NB * QR_NB; e += QR_REG_THREADS) {
+    const int t = e / QR_NB, u = e % QR_NB;
+    D.T[e] = (t < jb && u < jb && u >= t) ? T[t][u] : 0.0;
+  }
+}
+
+// VT = V_p T_p and VTt = V_p T_p^T on rows j0..m (one thread per row and column)
+__global__ void k_qrb_vt(QrbBatch B, int j0) {
+  const QrbDesc &D = B.d[blockIdx.y];
+  const int m = D.m;
+  const int jb = min(QR_NB, D.k - j0);
+  if (jb <= 0) return;
+  const int64_t tot = (int64_t)(m - j0) * jb;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int r = j0 + (int)(e % (m - j0)), t = (int)(e / (m - j0));
+    double a = 0.0, b = 0.0;
+    for (int s = 0; s < jb; ++s) {
+      const double v = D.V[(int64_t)(j0 + s) * m + r];
+      if (s <= t) a += v * D.T[s * QR_NB + t];
+      if (s >= t) b += v * D.T[t * QR_NB + s];
+    }
+    D.VT[(int64_t)(j0 + t) * m + r] = a;
+    D.VTt[(int64_t)(j0 + t) * m + r] = b;
+  }
+}
+
+// sign convention diag(R) >= 0; Q (m x k) and R (k x n) into the caller views
+__global__ void k_qrb_finish(QrbBatch B) {
+  const QrbDesc &D = B.d[blockIdx.y];
+  const int m = D.m, n = D.n, k = D.k;
+  const int64_t tq = (int64_t)m * k, tr = (int64_t)k * n;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < tq + tr;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    if (idx < tq) {
+      const int i = (int)(idx % m), c = (int)(idx / m);
+      const double s = (D.W[(int64_t)c * m + c] < 0.0) ? -1.0 : 1.0;
+      D.Q[i * D.qrs + c * D.qcs] = s * D.Qw[idx];
+    } else {
+      const int64_t e = idx - tq;
+      const int r = (int)(e % k), c = (int)(e / k);
+      const double s = (D.W[(int64_t)r * m + r] < 0.0) ? -1.0 : 1.0;
+      D.R[r * D.rrs + c * D.rcs] = (c >= r) ? s * D.W[(int64_t)c * m + r] : 0.0;
+    }
+  }
+}
+
+}  // namespace
+
+namespace {
+
+bool qr_use_blocked(int m, int n) {
+  const int k = std::min(m, n);
+  return k > 2 * QR_NB && (int64_t)m * n > 32768;
+}
+
+// blocked Householder QR of cnt matrices (all taking the blocked path)
+void qr_blocked(Ctx &c, int cnt, const ConstMatView *A, const MatView *Q, const MatView *R) {
+  QrbBatch b{};
+  b.count = cnt;
+  int64_t ws = 0;
+  int kmax = 0, nmax = 0;
+  for (int i = 0; i < cnt; ++i) {
+    const int m = A[i].rows, n = A[i].cols, k = std::min(m, n);
+    ws += (int64_t)m * n + 4 * (int64_t)m * k + (int64_t)QR_NB * n + QR_NB * QR_NB;
+    kmax = std::max(kmax, k);
+    nmax = std::max(nmax, n);
+  }
+  double *Wb = c.buf("qrb_work", ws);
+  std::vector<double *> Z(cnt);
+  int64_t o = 0;
+  int64_t elems = 0;
+  for (int i = 0; i < cnt; ++i) {
+    const int m = A[i].rows, n = A[i].cols, k = std::min(m, n);
+    QrbDesc &D = b.d[i];
+    D.A = A[i].p;
+    D.ars = A[i].rs;
+    D.acs = A[i].cs;
+    D.m = m;
+    D.n = n;
+    D.k = k;
+    D.W = Wb + o;
+    o += (int64_t)m * n;
+    D.V = Wb + o;
+    o += (int64_t)m * k;
+    D.VT = Wb + o;
+    o += (int64_t)m * k;
+    D.VTt = Wb + o;
+    o += (int64_t)m * k;
+    D.Qw = Wb + o;
+    o += (int64_t)m * k;
+    Z[i] = Wb + o;
+    o += (int64_t)QR_NB * n;
+    D.T = Wb + o;
+    o += QR_NB * QR_NB;
+    D.Q = Q[i].p;
+    D.qrs = Q[i].rs;
+    D.qcs = Q[i].cs;
+    D.R = R[i].p;
+    D.rrs = R[i].rs;
+    D.rcs = R[i].cs;
+    elems = std::max(elems, (int64_t)m * n + (int64_t)m * k);
+  }
+  const unsigned g = (unsigned)std::min<int64_t>(1024, (elems + 255) / 256);
+  hipLaunchKernelGGL(k_qrb_load, dim3(g, cnt), dim3(256), 0, c.stream, b);
+  HIPC(hipGetLastError());
+  // grouped GEMMs over the matrices (at most GEMM_GROUP per launch)
+  auto grouped = [&](std::vector<Gemm> &qs) {
+    for (size_t s0 = 0; s0 < qs.size(); s0 += GEMM_GROUP) {
+      const int np = (int)std::min<size_t>(GEMM_GROUP, qs.size() - s0);
+      int grp[GEMM_GROUP] = {0, 1, 2, 3};
+      const double *X[GEMM_GROUP] = {nullptr, nullptr, nullptr, nullptr};
+      gemm_grouped(c, np, qs.data() + s0, np, grp, X, nullptr, false);
+    }
+  };
+  for (int j0 = 0; j0 < kmax; j0 += QR_NB) {
+    int mmax = 0;
+    for (int i = 0; i < cnt; ++i) mmax = std::max(mmax, b.d[i].m);
+    if (mmax <= QR_REG_ROWS * QR_REG_THREADS)
+      hipLaunchKernelGGL(k_qrb_panel_reg, dim3(cnt), dim3(QR_REG_THREADS), 0, c.stream, b, j0);
+    else
+      hipLaunchKernelGGL(k_qrb_panel, dim3(cnt), dim3(LA_THREADS), 0, c.stream, b, j0);
+    {
+      int64_t rows = 0;
+      for (int i = 0; i < cnt; ++i) rows = std::max<int64_t>(rows, (int64_t)(b.d[i].m - j0) * QR_NB);
+      const unsigned gv = (unsigned)std::max<int64_t>(1, std::min<int64_t>(2048, (rows + 255) / 256));
+      hipLaunchKernelGGL(k_qrb_vt, dim3(gv, cnt), dim3(256), 0, c.stream, b, j0);
+    }
+    HIPC(hipGetLastError());
+    std::vector<Gemm> z1, z2;
+    for (int i = 0; i < cnt; ++i) {
+      const QrbDesc &D = b.d[i];
+      const int jb = std::min(QR_NB, D.k - j0);
+      const int nt = D.n - j0 - jb;
+      if (jb <= 0 || nt <= 0) continue;
+      Gemm a;  // Z = V_p^T W[j0:m, j0+jb:n]
+      a.M = jb;
+      a.N = nt;
+      a.K = D.m - j0;
+      a.A = D.V + (int64_t)j0 * D.m + j0;
+      a.sAm = D.m;
+      a.sAk = 1;
+      a.B = D.W + (int64_t)(j0 + jb) * D.m + j0;
+      a.sBk = 1;
+      a.sBn = D.m;
+      a.C = Z[i];
+      a.sCm = nt;
+      a.sCn = 1;
+      z1.push_back(a);
+      Gemm u;  // W[j0:m, j0+jb:n] -= (V_p T_p^T) Z
+      u.M = D.m - j0;
+      u.N = nt;
+      u.K = jb;
+      u.A = D.VTt + (int64_t)j0 * D.m + j0;
+      u.sAm = 1;
+      u.sAk = D.m;
+      u.B = Z[i];
+      u.sBk = nt;
+      u.sBn = 1;
+      u.C = D.W + (int64_t)(j0 + jb) * D.m + j0;
+      u.sCm = 1;
+      u.sCn = D.m;
+      u.alpha = -1.0;
+      u.beta = 1.0;
+      z2.push_back(u);
+    }
+    grouped(z1);
+    grouped(z2);
+  }
+  // Q = H_0 ... [I; 0], panels applied last to first
+  for (int j0 = ((kmax - 1) / QR_NB) * QR_NB; j0 >= 0; j0 -= QR_NB) {
+    std::vector<Gemm> z1, z2;
+    for (int i = 0; i < cnt; ++i) {
+      const QrbDesc &D = b.d[i];
+      const int jb = std::min(QR_NB, D.k - j0);
+      if (jb <= 0) continue;
+      const int nq = D.k - j0;
+      Gemm a;  // Z = V_p^T Q[j0:m, j0:k]
+      a.M = jb;
+      a.N = nq;
+      a.K = D.m - j0;
+      a.A = D.V + (int64_t)j0 * D.m + j0;
+      a.sAm = D.m;
+      a.sAk = 1;
+      a.B = D.Qw + (int64_t)j0 * D.m + j0;
+      a.sBk = 1;
+      a.sBn = D.m;
+      a.C = Z[i];
+      a.sCm = nq;
+      a.sCn = 1;
+      z1.push_back(a);
+      Gemm u;  // Q[j0:m, j0:k] -= (V_p T_p) Z
+      u.M = D.m - j0;
+      u.N = nq;
+      u.K = jb;
+      u.A = D.VT + (int64_t)j0 * D.m + j0;
+      u.sAm = 1;
+      u.sAk = D.m;
+      u.B = Z[i];
+      u.sBk = nq;
+      u.sBn = 1;
+      u.C = D.Qw + (int64_t)j0 * D.m + j0;
+      u.sCm = 1;
+      u.sCn = D.m;
+      u.alpha = -1.0;
+      u.beta = 1.0;
+      z2.push_back(u);
+    }
+    grouped(z1);
+    grouped(z2);
+  }
+  hipLaunchKernelGGL(k_qrb_finish, dim3(g, cnt), dim3(256), 0, c.stream, b);
+  HIPC(hipGetLastError());
+}
+
 }  // namespace
 
 void qr_batch(Ctx &c, int count, const ConstMatView *A, const MatView *Q, const MatView *R) {
+  // large matrices: blocked path (after the same shape and range checks)
+  {
+    std::vector<ConstMatView> bA;
+    std::vector<MatView> bQ, bR;
+    std::vector<ConstMatView> sA;
+    std::vector<MatView> sQ, sR;
+    for (int i = 0; i < count; ++i) {
+      const int m = A[i].rows, n = A[i].cols;
+      if (Q[i].rows != m || Q[i].cols != std::min(m, n) || R[i].rows != std::min(m, n) ||
+          R[i].cols != n)
+        fail(QTT_E_SHAPE, "qr_batch: output shapes");
+      int64_t lo = 0, hi = 0;
+      span(lo, hi, A[i].rows, A[i].rs);
+      span(lo, hi, A[i].cols, A[i].cs);
+      c.check_range(A[i].p, lo, hi, 8, "qr A");
+      lo = hi = 0;
+      span(lo, hi, Q[i].rows, Q[i].rs);
+      span(lo, hi, Q[i].cols, Q[i].cs);
+      c.check_range(Q[i].p, lo, hi, 8, "qr Q");
+      lo = hi = 0;
+      span(lo, hi, R[i].rows, R[i].rs);
+      span(lo, hi, R[i].cols, R[i].cs);
+      c.check_range(R[i].p, lo, hi, 8, "qr R");
+      if (qr_use_blocked(m, n)) {
+        bA.push_back(A[i]);
+        bQ.push_back(Q[i]);
+        bR.push_back(R[i]);
+      } else {
+        sA.push_back(A[i]);
+        sQ.push_back(Q[i]);
+        sR.push_back(R[i]);
+      }
+    }
+    for (size_t b0 = 0; b0 < bA.size(); b0 += MAX_BATCH) {
+      const int cnt = (int)std::min<size_t>(MAX_BATCH, bA.size() - b0);
+      qr_blocked(c, cnt, bA.data() + b0, bQ.data() + b0, bR.data() + b0);
+    }
+    if (sA.empty()) return;
+    if ((int)sA.size() != count) {
+      qr_batch(c, (int)sA.size(), sA.data(), sQ.data(), sR.data());
+      return;
+    }
+  }
   for (int base = 0; base < count; base += MAX_BATCH) {
     const int cnt = std::min(MAX_BATCH, count - base);
     QRBatch b{};

@@ -24,7 +24,11 @@ namespace {
 constexpr int SV_THREADS = 1024;
 constexpr int SV_WAVES = SV_THREADS / 64;
 constexpr int SV_MAXB = 8;
-constexpr double SV_TOL = 1e-15;
+// rotation threshold on the cosine between two columns: sqrt(m) units of
+// roundoff (the level at which computed column products stop carrying
+// information, as in the one-sided Jacobi literature); a fixed tighter
+// threshold sits below the noise of m-term sums and never stops rotating
+constexpr double SV_EPS = 1.1102230246251565e-16;
 
 __device__ inline double wave_sum(double v) {
 #pragma unroll
@@ -39,6 +43,7 @@ struct SvMat {
   double *W;   // m x n column-major
   double *V;   // n x n column-major
   int *count;  // rotations of the current sweep
+  double *fro2;  // squared Frobenius norm of A (invariant under the rotations)
   int b;       // block width
   int nb;      // blocks
   int single;  // n <= 2b: whole matrix is one block pair
@@ -56,9 +61,21 @@ struct SvBatch {
 
 __global__ __launch_bounds__(SV_THREADS) void k_sv_init(SvBatch B) {
   const SvMat &D = B.d[blockIdx.x];
+  __shared__ double part[SV_WAVES];
+  double ss = 0.0;
   for (int64_t idx = threadIdx.x; idx < (int64_t)D.m * D.n; idx += SV_THREADS) {
     const int i = (int)(idx % D.m), j = (int)(idx / D.m);
-    D.W[idx] = D.A[i * D.ars + j * D.acs];
+    const double a = D.A[i * D.ars + j * D.acs];
+    D.W[idx] = a;
+    ss += a * a;
+  }
+  ss = wave_sum(ss);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = ss;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < SV_WAVES; ++w) t += part[w];
+    *D.fro2 = t;
   }
   for (int64_t idx = threadIdx.x; idx < (int64_t)D.n * D.n; idx += SV_THREADS) {
     const int i = (int)(idx % D.n), j = (int)(idx / D.n);
@@ -69,7 +86,11 @@ __global__ __launch_bounds__(SV_THREADS) void k_sv_init(SvBatch B) {
 
 // one Jacobi sweep over the column pairs of the nc LDS columns; returns the
 // number of rotations (valid in every thread after the final barrier)
-__device__ int inner_sweep(double *cols, int m, int nc, double *Wacc, int *rot) {
+// columns whose squared norm is below floor2 are numerically zero (pure
+// roundoff); rotating them against each other never converges and changes
+// nothing above the noise, so such pairs are skipped
+__device__ int inner_sweep(double *cols, int m, int nc, double *Wacc, int *rot, double floor2) {
+  const double tol = sqrt((double)m) * SV_EPS;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int np = nc + (nc & 1);
   if (threadIdx.x == 0) *rot = 0;
@@ -102,7 +123,7 @@ __device__ int inner_sweep(double *cols, int m, int nc, double *Wacc, int *rot) 
       al = wave_sum(al);
       be = wave_sum(be);
       ga = wave_sum(ga);
-      if (ga != 0.0 && fabs(ga) > SV_TOL * sqrt(al * be)) {
+      if (ga != 0.0 && al > floor2 && be > floor2 && fabs(ga) > tol * sqrt(al * be)) {
         const double zeta = (be - al) / (2.0 * ga);
         const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
         const double cs = 1.0 / sqrt(1.0 + t * t);
@@ -183,6 +204,9 @@ __global__ __launch_bounds__(SV_THREADS) void k_sv_round(SvBatch B, int round) {
   }
   double *cols = lds;
   double *Wacc = lds + (int64_t)nc * m;
+  // numerically zero columns: norm below 4 sqrt(m) eps ||A||_F
+  const double fl = 4.0 * sqrt((double)m) * SV_EPS;
+  const double floor2 = fl * fl * *D.fro2;
   __syncthreads();
   for (int64_t idx = threadIdx.x; idx < (int64_t)nc * m; idx += SV_THREADS) {
     const int k = (int)(idx / m), i = (int)(idx % m);
@@ -196,13 +220,13 @@ __global__ __launch_bounds__(SV_THREADS) void k_sv_round(SvBatch B, int round) {
   if (D.single) {
     int last = 1;
     for (int s = 0; s < 60 && last > 0; ++s) {
-      last = inner_sweep(cols, m, nc, Wacc, &rot);
+      last = inner_sweep(cols, m, nc, Wacc, &rot, floor2);
       any += last;
       __syncthreads();
     }
     total = last;
   } else {
-    total = inner_sweep(cols, m, nc, Wacc, &rot);
+    total = inner_sweep(cols, m, nc, Wacc, &rot, floor2);
     any = total;
   }
   __syncthreads();
@@ -299,10 +323,127 @@ size_t sv_lds_limit(Ctx &c) {
   return lim;
 }
 
+bool sv_verbose() {
+  static const bool v = [] {
+    const char *e = std::getenv("QTT_VERBOSE");
+    return e && e[0] == '1';
+  }();
+  return v;
+}
+
 }  // namespace
+
+namespace {
+
+// dst view <- src (rows x cols, row-major packed)
+__global__ void k_sv_copy_view(double *dst, int64_t drs, int64_t dcs, const double *src, int rows,
+                               int cols) {
+  const int64_t tot = (int64_t)rows * cols;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e / cols), j = (int)(e % cols);
+    dst[i * drs + j * dcs] = src[e];
+  }
+}
+
+void svd_jacobi(Ctx &c, int count, const ConstMatView *A, const MatView *U, double *const *S,
+                const MatView *V);
+
+}  // namespace
+
+// Matrices with more than SVQ_MIN columns are first factorised A = Q R
+// (blocked Householder); the one-sided Jacobi then runs on X = R^T, whose
+// columns start much closer to orthogonal than those of A (about half the
+// sweeps on truncation unfoldings) and, for tall A, are also shorter.
+// X = U_X S V_X^T gives A = (Q V_X) S U_X^T.
+constexpr int SVQ_MIN = 32;
 
 void svd_batch(Ctx &c, int count, const ConstMatView *A, const MatView *U, double *const *S,
                const MatView *V) {
+  std::vector<int> qi, di;
+  for (int i = 0; i < count; ++i) {
+    if (A[i].rows < A[i].cols) fail(QTT_E_SHAPE, "svd_batch: needs rows >= cols");
+    if (U[i].rows != A[i].rows || U[i].cols != A[i].cols || V[i].rows != A[i].cols ||
+        V[i].cols != A[i].cols)
+      fail(QTT_E_SHAPE, "svd_batch: output shapes");
+    (A[i].cols > SVQ_MIN ? qi : di).push_back(i);
+  }
+  if (!di.empty()) {
+    std::vector<ConstMatView> a;
+    std::vector<MatView> u, v;
+    std::vector<double *> s;
+    for (int i : di) {
+      a.push_back(A[i]);
+      u.push_back(U[i]);
+      v.push_back(V[i]);
+      s.push_back(S[i]);
+    }
+    svd_jacobi(c, (int)di.size(), a.data(), u.data(), s.data(), v.data());
+  }
+  if (qi.empty()) return;
+  int64_t qs = 0, ns = 0;
+  for (int i : qi) {
+    qs += (int64_t)A[i].rows * A[i].cols;
+    ns += (int64_t)A[i].cols * A[i].cols;
+  }
+  double *Qb = c.buf("svq_Q", qs);
+  double *Rb = c.buf("svq_R", ns);
+  double *UXb = c.buf("svq_UX", ns);
+  double *VXb = c.buf("svq_VX", ns);
+  std::vector<ConstMatView> a, x;
+  std::vector<MatView> q, r, ux, vx;
+  std::vector<double *> s;
+  int64_t qo = 0, no = 0;
+  for (int i : qi) {
+    const int m = A[i].rows, n = A[i].cols;
+    a.push_back(A[i]);
+    q.push_back(MatView{Qb + qo, m, n, n, 1});
+    r.push_back(MatView{Rb + no, n, n, n, 1});
+    x.push_back(ConstMatView{Rb + no, n, n, 1, n});  // R^T
+    ux.push_back(MatView{UXb + no, n, n, n, 1});
+    vx.push_back(MatView{VXb + no, n, n, n, 1});
+    s.push_back(S[i]);
+    qo += (int64_t)m * n;
+    no += (int64_t)n * n;
+  }
+  const int cnt = (int)qi.size();
+  qr_batch(c, cnt, a.data(), q.data(), r.data());
+  svd_jacobi(c, cnt, x.data(), ux.data(), s.data(), vx.data());
+  for (int k = 0; k < cnt; ++k) {
+    const int i = qi[k];
+    const int m = A[i].rows, n = A[i].cols;
+    {
+      int64_t lo = 0, hi = 0;
+      span(lo, hi, n, V[i].rs);
+      span(lo, hi, n, V[i].cs);
+      c.check_range(V[i].p, lo, hi, 8, "svd V");
+      c.check_range(ux[k].p, 0, (int64_t)n * n - 1, 8, "svd UX");
+      const unsigned g = (unsigned)std::min<int64_t>(1024, ((int64_t)n * n + 255) / 256);
+      hipLaunchKernelGGL(k_sv_copy_view, dim3(g), dim3(256), 0, c.stream, V[i].p, V[i].rs,
+                         V[i].cs, (const double *)ux[k].p, n, n);
+      HIPC(hipGetLastError());
+    }
+    Gemm gq;  // U = Q V_X
+    gq.M = m;
+    gq.N = n;
+    gq.K = n;
+    gq.A = q[k].p;
+    gq.sAm = n;
+    gq.sAk = 1;
+    gq.B = vx[k].p;
+    gq.sBk = n;
+    gq.sBn = 1;
+    gq.C = U[i].p;
+    gq.sCm = U[i].rs;
+    gq.sCn = U[i].cs;
+    gemm(c, gq);
+  }
+}
+
+namespace {
+
+void svd_jacobi(Ctx &c, int count, const ConstMatView *A, const MatView *U, double *const *S,
+                const MatView *V) {
   const size_t SV_LDS_LIMIT = sv_lds_limit(c);
   for (int base = 0; base < count; base += SV_MAXB) {
     const int cnt = std::min(SV_MAXB, count - base);
@@ -362,6 +503,7 @@ void svd_batch(Ctx &c, int count, const ConstMatView *A, const MatView *U, doubl
     double *Wb = c.buf("svd_work", ws);
     int *cnt_host = (int *)(c.pinned + 2048);
     int *cnt_dev = (int *)c.raw("svd_counts", SV_MAXB * sizeof(int));
+    double *fro2_dev = c.buf("svd_fro2", SV_MAXB);
     int64_t o = 0;
     for (int i = 0; i < cnt; ++i) {
       SvMat &d = B.d[i];
@@ -370,6 +512,7 @@ void svd_batch(Ctx &c, int count, const ConstMatView *A, const MatView *U, doubl
       d.V = Wb + o;
       o += (int64_t)d.n * d.n + 1;
       d.count = cnt_dev + i;
+      d.fro2 = fro2_dev + i;
     }
     hipLaunchKernelGGL(k_sv_init, dim3(cnt), dim3(SV_THREADS), 0, c.stream, B);
     HIPC(hipGetLastError());
@@ -377,7 +520,9 @@ void svd_batch(Ctx &c, int count, const ConstMatView *A, const MatView *U, doubl
     int rounds = 1;
     for (int i = 0; i < cnt; ++i)
       if (!B.d[i].single) rounds = std::max(rounds, B.d[i].nb + (B.d[i].nb & 1) - 1);
+    int sweeps_run = 0;
     for (int sweep = 0; sweep < 40; ++sweep) {
+      ++sweeps_run;
       for (int r = 0; r < rounds; ++r) {
         // workgroups of this round per matrix
         SvBatch R = B;
@@ -404,9 +549,14 @@ void svd_batch(Ctx &c, int count, const ConstMatView *A, const MatView *U, doubl
       if (done) break;
       HIPC(hipMemsetAsync(cnt_dev, 0, cnt * sizeof(int), c.stream));
     }
+    if (sv_verbose())
+      std::fprintf(stderr, "[qtt] svd %dx%d (+%d) sweeps %d rounds/sweep %d\n", B.d[0].m, B.d[0].n,
+                   cnt - 1, sweeps_run, rounds);
     hipLaunchKernelGGL(k_sv_finish, dim3(cnt), dim3(SV_THREADS), lds_fin, c.stream, B);
     HIPC(hipGetLastError());
   }
 }
+
+}  // namespace
 
 }  // namespace qtt

@@ -304,7 +304,7 @@ int qtt_kernel_timing(qtt_ctx *ctx, int32_t enable, int32_t sample_every) {
   return guard(ctx, [&] {
     qtt::Ctx &c = ctx->c;
     c.resolve_events();
-    for (int k = 0; k < 2; ++k) {
+    for (int k = 0; k < qtt::KT_KINDS; ++k) {
       c.kt.launches[k] = 0;
       c.kt.timed[k] = 0;
       c.kt.timed_ms[k] = 0.0;
@@ -312,8 +312,8 @@ int qtt_kernel_timing(qtt_ctx *ctx, int32_t enable, int32_t sample_every) {
     c.kt.every = sample_every < 1 ? 1 : sample_every;
     c.kt.on = enable != 0;
     if (c.kt.on) {
-      c.kt.flop_ctr = (double *)c.raw("kt_flops", 2 * sizeof(double));
-      HIPC(hipMemsetAsync(c.kt.flop_ctr, 0, 2 * sizeof(double), c.stream));
+      c.kt.flop_ctr = (double *)c.raw("kt_flops", qtt::KT_KINDS * sizeof(double));
+      HIPC(hipMemsetAsync(c.kt.flop_ctr, 0, qtt::KT_KINDS * sizeof(double), c.stream));
       c.sync();
     }
   });
@@ -321,12 +321,13 @@ int qtt_kernel_timing(qtt_ctx *ctx, int32_t enable, int32_t sample_every) {
 
 int qtt_kernel_stats_read(qtt_ctx *ctx, int32_t kernel, qtt_kernel_stats *out) {
   return guard(ctx, [&] {
-    if (!out || kernel < 0 || kernel > 1) qtt::fail(QTT_E_ARG, "kernel_stats_read: bad arguments");
+    if (!out || kernel < 0 || kernel >= qtt::KT_KINDS)
+      qtt::fail(QTT_E_ARG, "kernel_stats_read: bad arguments");
     qtt::Ctx &c = ctx->c;
     c.resolve_events();
-    double fl[2] = {0.0, 0.0};
+    double fl[qtt::KT_KINDS] = {0.0, 0.0, 0.0, 0.0};
     if (c.kt.flop_ctr)
-      HIPC(hipMemcpy(fl, c.kt.flop_ctr, 2 * sizeof(double), hipMemcpyDeviceToHost));
+      HIPC(hipMemcpy(fl, c.kt.flop_ctr, qtt::KT_KINDS * sizeof(double), hipMemcpyDeviceToHost));
     out->launches = c.kt.launches[kernel];
     out->timed = c.kt.timed[kernel];
     out->flops = fl[kernel];

@@ -84,7 +84,7 @@ hipEvent_t Ctx::take_event() {
 
 void Ctx::resolve_events() {
   sync();
-  for (int k = 0; k < 2; ++k) {
+  for (int k = 0; k < KT_KINDS; ++k) {
     for (auto &pr : kt.pending[k]) {
       float ms = 0.f;
       HIPC(hipEventElapsedTime(&ms, pr.first, pr.second));
@@ -136,7 +136,7 @@ Ctx::~Ctx() {
   hipStreamSynchronize(stream);
   for (auto &kv : cg_graphs)
     if (kv.second.exec) hipGraphExecDestroy(kv.second.exec);
-  for (int k = 0; k < 2; ++k)
+  for (int k = 0; k < KT_KINDS; ++k)
     for (auto &pr : kt.pending[k]) {
       hipEventDestroy(pr.first);
       hipEventDestroy(pr.second);

@@ -79,14 +79,17 @@ struct Mpo {
 };
 
 // ---------------------------------------------------------------- kernel timing
+// GEMM kernel instantiations told apart by the timer (QTT_KERNEL_GEMM_*):
+// 0 float64 64x64 tiles, 1 float32 64x64, 2 float64 128x128, 3 float32 128x128
+constexpr int KT_KINDS = 4;
 struct KernelTimer {
   bool on = false;
   int every = 1;
-  int64_t launches[2] = {0, 0};
-  int64_t timed[2] = {0, 0};
-  double timed_ms[2] = {0.0, 0.0};
-  double *flop_ctr = nullptr;  // device, 2 doubles
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[2];
+  int64_t launches[KT_KINDS] = {0, 0, 0, 0};
+  int64_t timed[KT_KINDS] = {0, 0, 0, 0};
+  double timed_ms[KT_KINDS] = {0.0, 0.0, 0.0, 0.0};
+  double *flop_ctr = nullptr;  // device, KT_KINDS doubles
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[KT_KINDS];
   std::vector<hipEvent_t> pool;
 };
 
@@ -94,7 +97,7 @@ struct KernelTimer {
 struct CgGraph {
   hipGraphExec_t exec = nullptr;
   std::vector<int64_t> key;
-  int64_t launches[2] = {0, 0};  // GEMM launches per replay (float64, float32)
+  int64_t launches[KT_KINDS] = {0, 0, 0, 0};  // GEMM launches per replay, by timer kind
 };
 
 // ---------------------------------------------------------------- learned preconditioner
@@ -141,7 +144,7 @@ struct Ctx {
   PrecondNet pc;
   bool use_graphs = true;             // QTT_GRAPHS=0 disables CG graph capture
   bool capturing = false;             // a stream capture is open
-  int64_t cap_launches[2] = {0, 0};
+  int64_t cap_launches[KT_KINDS] = {0, 0, 0, 0};
   std::map<std::string, CgGraph> cg_graphs;
   // per-shape GEMM timing (QTT_GEMM_STATS=1), printed when the context ends
   bool shape_stats = false;

@@ -523,7 +523,7 @@ struct Sweep {
       CgGraph *g = c.use_graphs ? graph_for(d, rev, pre, x, r, pp, q, rhs) : nullptr;
       if (g && !g->exec) {
         c.capturing = true;
-        c.cap_launches[0] = c.cap_launches[1] = 0;
+        for (int k = 0; k < KT_KINDS; ++k) c.cap_launches[k] = 0;
         hipGraph_t graph = nullptr;
         HIPC(hipStreamBeginCapture(c.stream, hipStreamCaptureModeRelaxed));
         try {
@@ -539,13 +539,11 @@ struct Sweep {
         HIPC(hipStreamEndCapture(c.stream, &graph));
         HIPC(hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0));
         HIPC(hipGraphDestroy(graph));
-        g->launches[0] = c.cap_launches[0];
-        g->launches[1] = c.cap_launches[1];
+        for (int k = 0; k < KT_KINDS; ++k) g->launches[k] = c.cap_launches[k];
       }
       if (g) {
         HIPC(hipGraphLaunch(g->exec, c.stream));
-        c.kt.launches[0] += c.kt.on ? g->launches[0] : 0;
-        c.kt.launches[1] += c.kt.on ? g->launches[1] : 0;
+        for (int k = 0; k < KT_KINDS; ++k) c.kt.launches[k] += c.kt.on ? g->launches[k] : 0;
       } else {
         enqueue_iters(GRAPH_CHUNK);
       }

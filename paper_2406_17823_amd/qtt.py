@@ -343,8 +343,14 @@ def kernel_timing(ctx, enable=True, sample_every=1):
     ctx.check(lib().qtt_kernel_timing(ctx.h, 1 if enable else 0, sample_every), 'kernel_timing')
 
 
+KERNEL_GEMM_F64_T64, KERNEL_GEMM_F32_T64, KERNEL_GEMM_F64_T128, KERNEL_GEMM_F32_T128 = 0, 1, 2, 3
+KERNEL_NAMES = {0: 'k_gemm<double, 64, 64>', 1: 'k_gemm<float, 64, 64>',
+                2: 'k_gemm<double, 128, 128>', 3: 'k_gemm<float, 128, 128>'}
+
+
 def kernel_stats(ctx, kernel):
-    """kernel 0: float64 GEMM, 1: float32 GEMM."""
+    """Launch count, timed launches, executed flops and event time of one GEMM
+    instantiation (KERNEL_GEMM_*) in the current timing window."""
     s = c_kstats()
     ctx.check(lib().qtt_kernel_stats_read(ctx.h, kernel, ctypes.byref(s)), 'kernel_stats_read')
     return dict(launches=s.launches, timed=s.timed, flops=s.flops, timed_ms=s.timed_ms)

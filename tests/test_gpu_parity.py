@@ -135,6 +135,21 @@ def test_truncate_ragged_and_rank_cutoff(Q, ctx):
     assert M.rel_l2(d.cores(), x) < TOL
 
 
+@pytest.mark.parametrize('chi_in,chi', [(37, 48), (37, 20)])
+def test_truncate_four_term_sum_blocked_qr(Q, ctx, chi_in, chi):
+    """Sum bonds 148 give unfoldings of 256 x 148 and 592 x 148: the blocked
+    QR path with four full panels of 32 and a ragged one of 20."""
+    n = 8
+    xs = [rand(I.canonical_bonds(n, chi_in), 40 + t) for t in range(4)]
+    y = M.add([1.0, -0.5, 0.25, 2.0], xs)
+    d = dev(Q, y)
+    disc = Q.truncate(ctx, d, chi, 1e-12)
+    ref, disc_ref = M.truncate(y, chi, 1e-12)
+    assert d.bonds == M.bonds(ref)
+    assert M.rel_l2(d.cores(), ref) < TOL
+    assert abs(disc - disc_ref) <= 1e-9 * max(disc_ref, 1e-30) + 1e-28
+
+
 # ---------------------------------------------------------------- input compression
 def test_from_dense_matches_tt_svd(Q, ctx):
     n, chi = 6, 12
