@@ -57,6 +57,25 @@ def parse():
     return ap.parse_args()
 
 
+def measured_traffic(kernel):
+    """HBM bytes per dispatch of `kernel` from the committed byte-counter
+    profile, or None when there is none or the kernel source has changed
+    since the counters were taken."""
+    import glob
+    import hashlib
+    src = os.path.join(ROOT, 'paper_2406_17823_amd', 'csrc', 'k_gemm.hip')
+    sha = hashlib.sha256(open(src, 'rb').read()).hexdigest()[:16]
+    for f in glob.glob(os.path.join(ROOT, 'profiles', '*_traffic.txt')):
+        kv = {}
+        for line in open(f):
+            if ':' in line and not line.startswith(' '):
+                k, v = line.split(':', 1)
+                kv[k.strip()] = v.strip()
+        if kv.get('kernel') == kernel and kv.get('source', '').endswith(sha):
+            return float(kv['traffic_bytes_per_dispatch'])
+    return None
+
+
 def log(*a):
     print('[bench]', *a, file=sys.stderr, flush=True)
 
@@ -210,9 +229,10 @@ def main():
     avg_ms = s['timed_ms'] / max(s['timed'], 1)
     flops_per_launch = s['flops'] / max(s['launches'], 1)
     achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
+    traffic = measured_traffic(Q.KERNEL_NAMES[dom])
     roofline = dict(bound='mfma', kernel=Q.KERNEL_NAMES[dom], achieved=round(achieved, 3),
                     peak=PEAK[dom], unit='TFLOP/s', frac=round(achieved / PEAK[dom], 4),
-                    traffic=None, launches=s['launches'], avg_launch_ms=round(avg_ms, 5),
+                    traffic=traffic, launches=s['launches'], avg_launch_ms=round(avg_ms, 5),
                     flops_per_launch=flops_per_launch,
                     kernel_share=round(est_time(dom) / (results[main_path]['seconds'] * 1e3), 3))
 
