@@ -190,6 +190,18 @@ int qtt_project(qtt_ctx *ctx, const qtt_mps *a, const qtt_mps *b, double h,
  * bonds min(chi, 4^k, 4^(n-k)). */
 int qtt_rk4_step(qtt_ctx *ctx, qtt_mps *u, const qtt_params *p, qtt_stats *stats);
 
+/* One RK4 step (as qtt_rk4_step) of each of nflows independent flows, for
+ * many flows of uneven size at once.  u holds 2 * nflows MPS (flow f:
+ * u[2f], u[2f+1]), p and stats (may be NULL) nflows entries.  The flows are
+ * dealt round-robin to `workers` worker contexts (0 = 4, at most 8), each
+ * with its own stream and workspace, and advanced concurrently after the
+ * work already enqueued on the context's stream; the call returns when all
+ * flows are done.  Each flow's result is bit-identical to qtt_rk4_step on it
+ * alone.  Returns the most negative error over the flows (the message names
+ * the flow), else the largest warning. */
+int qtt_rk4_step_batched(qtt_ctx *ctx, int32_t nflows, qtt_mps *u, const qtt_params *p,
+                         qtt_stats *stats, int32_t workers);
+
 /* Kernel timing for roofline reporting.  While enabled, every launch of the
  * GEMM kernel instantiations QTT_KERNEL_GEMM_* is counted, the kernel adds
  * the flops it executed (2 M N K per batch entry; 0 when it returned early
@@ -197,10 +209,10 @@ int qtt_rk4_step(qtt_ctx *ctx, qtt_mps *u, const qtt_params *p, qtt_stats *stats
  * sample_every-th launch is bracketed by HIP events on the context stream.
  * Enabling starts a new window; reading synchronises the stream. */
 enum {
-  QTT_KERNEL_GEMM_F64_T64 = 0,   /* k_gemm<double, 64, 64>   */
-  QTT_KERNEL_GEMM_F32_T64 = 1,   /* k_gemm<float, 64, 64>    */
-  QTT_KERNEL_GEMM_F64_T128 = 2,  /* k_gemm<double, 128, 128> */
-  QTT_KERNEL_GEMM_F32_T128 = 3   /* k_gemm<float, 128, 128>  */
+  QTT_KERNEL_GEMM_F64_T64 = 0,   /* k_gemm<double, 64, 64, 2, 2>   */
+  QTT_KERNEL_GEMM_F32_T64 = 1,   /* k_gemm<float, 64, 64, 2, 2>    */
+  QTT_KERNEL_GEMM_F64_T128 = 2,  /* k_gemm<double, 128, 128, 2, 4> */
+  QTT_KERNEL_GEMM_F32_T128 = 3   /* k_gemm<float, 128, 128, 2, 4>  */
 };
 typedef struct {
   int64_t launches;   /* launches in the window                          */

@@ -32,7 +32,7 @@ __device__ inline double block_sum(double v, double *sh) {
   return s;
 }
 
-// returns true in thread 0 of the last block to arrive
+// true in every thread of the last block to arrive (block-uniform)
 __device__ inline bool arrive_last(CGState *st, double *part, int slot, double s0, double s1) {
   __shared__ bool last;
   if (threadIdx.x == 0) {
@@ -43,21 +43,29 @@ __device__ inline bool arrive_last(CGState *st, double *part, int slot, double s
     last = (prev == gridDim.x - 1);
   }
   __syncthreads();
-  if (last && threadIdx.x == 0) {
-    __threadfence();
-    return true;
-  }
-  return false;
+  if (last) __threadfence();
+  return last;
 }
 
+// fixed-order sum of the np partial pairs by the whole (last) block; the
+// result is valid in every thread
 __device__ inline void sum_parts(const double *part, int np, double &s0, double &s1) {
+  __shared__ double sh[2][CG_THREADS / 64];
   const volatile double *vp = part;
-  s0 = 0.0;
-  s1 = 0.0;
-  for (int i = 0; i < np; ++i) {
-    s0 += vp[2 * i];
-    s1 += vp[2 * i + 1];
+  double a = 0.0, b = 0.0;
+  for (int i = threadIdx.x; i < np; i += CG_THREADS) {
+    a += vp[2 * i];
+    b += vp[2 * i + 1];
   }
+  a = wave_sum(a);
+  b = wave_sum(b);
+  if ((threadIdx.x & 63) == 0) {
+    sh[0][threadIdx.x >> 6] = a;
+    sh[1][threadIdx.x >> 6] = b;
+  }
+  __syncthreads();
+  s0 = (sh[0][0] + sh[0][1]) + (sh[0][2] + sh[0][3]);
+  s1 = (sh[1][0] + sh[1][1]) + (sh[1][2] + sh[1][3]);
 }
 
 // r = rhs - q (q = A x0), p = z = M r (M = I here), rr = r.r, bnorm2 = rhs.rhs
@@ -80,17 +88,19 @@ __global__ __launch_bounds__(CG_THREADS) void k_cg_init(const double *rhs, const
   if (arrive_last(st, part, blockIdx.x, sa, sb)) {
     double rr, bn;
     sum_parts(part, gridDim.x, rr, bn);
-    st->rr = rr;
-    st->rz = rr;
-    st->rr_new = rr;
-    st->bnorm2 = bn;
-    st->tol2 = st->rtol * st->rtol * bn;
-    st->iters = 0;
-    st->converged = 0;
-    st->zero_x = (bn == 0.0) ? 1 : 0;
-    st->done = (bn == 0.0 || rr <= st->tol2) ? 1 : 0;
-    if (st->done) st->converged = 1;
-    st->counter = 0;
+    if (threadIdx.x == 0) {
+      st->rr = rr;
+      st->rz = rr;
+      st->rr_new = rr;
+      st->bnorm2 = bn;
+      st->tol2 = st->rtol * st->rtol * bn;
+      st->iters = 0;
+      st->converged = 0;
+      st->zero_x = (bn == 0.0) ? 1 : 0;
+      st->done = (bn == 0.0 || rr <= st->tol2) ? 1 : 0;
+      if (st->done) st->converged = 1;
+      st->counter = 0;
+    }
   }
 }
 
@@ -114,9 +124,11 @@ __global__ __launch_bounds__(CG_THREADS) void k_cg_alpha(const double *p, const 
   if (arrive_last(st, part, blockIdx.x, sa, 0.0)) {
     double pq, dummy;
     sum_parts(part, gridDim.x, pq, dummy);
-    st->pq = pq;
-    st->alpha = st->rz / pq;
-    st->counter = 0;
+    if (threadIdx.x == 0) {
+      st->pq = pq;
+      st->alpha = st->rz / pq;
+      st->counter = 0;
+    }
   }
 }
 
@@ -139,23 +151,25 @@ __global__ __launch_bounds__(CG_THREADS) void k_cg_update(double *x, double *r, 
   if (arrive_last(st, part, blockIdx.x, sa, 0.0)) {
     double rr, dummy;
     sum_parts(part, gridDim.x, rr, dummy);
-    st->iters += 1;
-    // plain CG: rr <- previous r.r (for beta), rr_new = rz <- new r.r (for
-    // beta and the next alpha); PCG keeps rz = r.z for pcg_next
-    if (!st->precond) {
-      st->rr = st->rz;
-      st->rz = rr;
+    if (threadIdx.x == 0) {
+      st->iters += 1;
+      // plain CG: rr <- previous r.r (for beta), rr_new = rz <- new r.r (for
+      // beta and the next alpha); PCG keeps rz = r.z for pcg_next
+      if (!st->precond) {
+        st->rr = st->rz;
+        st->rz = rr;
+      }
+      st->rr_new = rr;
+      if (!(rr == rr)) {
+        st->done = 1;  // NaN: stop, not converged
+      } else if (rr <= st->tol2) {
+        st->done = 1;
+        st->converged = 1;
+      } else if (st->iters >= st->maxit) {
+        st->done = 1;
+      }
+      st->counter = 0;
     }
-    st->rr_new = rr;
-    if (!(rr == rr)) {
-      st->done = 1;  // NaN: stop, not converged
-    } else if (rr <= st->tol2) {
-      st->done = 1;
-      st->converged = 1;
-    } else if (st->iters >= st->maxit) {
-      st->done = 1;
-    }
-    st->counter = 0;
   }
 }
 
@@ -182,10 +196,12 @@ __global__ __launch_bounds__(CG_THREADS) void k_pcg_rz(const double *r, const do
   if (arrive_last(st, part, blockIdx.x, sa, 0.0)) {
     double rz, dummy;
     sum_parts(part, gridDim.x, rz, dummy);
-    st->beta = rz / st->rz;
-    st->rz = rz;
-    st->rr = st->rr_new;
-    st->counter = 0;
+    if (threadIdx.x == 0) {
+      st->beta = rz / st->rz;
+      st->rz = rz;
+      st->rr = st->rr_new;
+      st->counter = 0;
+    }
   }
 }
 
@@ -214,8 +230,10 @@ __global__ __launch_bounds__(CG_THREADS) void k_pcg_start(const double *r, const
   if (arrive_last(st, part, blockIdx.x, sa, 0.0)) {
     double rz, dummy;
     sum_parts(part, gridDim.x, rz, dummy);
-    st->rz = rz;
-    st->counter = 0;
+    if (threadIdx.x == 0) {
+      st->rz = rz;
+      st->counter = 0;
+    }
   }
 }
 

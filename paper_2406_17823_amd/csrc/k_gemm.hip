@@ -150,13 +150,17 @@ __device__ inline __bf16 to_op<__bf16>(double v) {
   return (__bf16)(float)v;
 }
 
-template <typename T, int BM, int BN>
-__global__ __launch_bounds__(256) void k_gemm(GemmK g) {
+// WGM x WGN waves per workgroup, each owning (BM / WGM) x (BN / WGN) outputs
+template <typename T, int BM, int BN, int WGM, int WGN>
+__global__ __launch_bounds__(64 * WGM * WGN) void k_gemm(GemmK g) {
   if (g.skip && *g.skip) return;
   if (g.flop_ctr && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(g.flop_ctr, g.flops);
-  constexpr int FM = BM / 32, FN = BN / 32;    // 16 x 16 blocks per wave
-  constexpr int AL = BM * KT / 256, BL = BN * KT / 256;  // global loads per thread
+  constexpr int NTHR = 64 * WGM * WGN;
+  constexpr int WTM = BM / WGM, WTN = BN / WGN;  // wave tile
+  constexpr int FM = WTM / 16, FN = WTN / 16;    // 16 x 16 blocks per wave
+  constexpr int AL = BM * KT / NTHR, BL = BN * KT / NTHR;  // global loads per thread
   static_assert(BM == BN, "square tiles: the MFMA step takes one LDS pitch");
+  static_assert(AL * NTHR == BM * KT && BL * NTHR == BN * KT, "tile / thread mismatch");
   constexpr int LDA = BM + PADM, LDB = BN + PADM;
   __shared__ T As[2][KT][LDA];
   __shared__ T Bs[2][KT][LDB];
@@ -164,7 +168,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmK g) {
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
+  const int wm = wave / WGN, wn = wave % WGN;
 
   int pi = 0;
 #pragma unroll
@@ -210,7 +214,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmK g) {
   auto gload = [&](int k0) {
 #pragma unroll
     for (int i = 0; i < AL; ++i) {
-      const int idx = tid + 256 * i;
+      const int idx = tid + NTHR * i;
       const int mm = a_m_unit ? (idx % BM) : (idx / KT);
       const int kk = a_m_unit ? (idx / BM) : (idx % KT);
       const int gm = m0 + mm, gk = k0 + kk;
@@ -218,7 +222,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmK g) {
     }
 #pragma unroll
     for (int i = 0; i < BL; ++i) {
-      const int idx = tid + 256 * i;
+      const int idx = tid + NTHR * i;
       const int nn = b_n_unit ? (idx % BN) : (idx / KT);
       const int kk = b_n_unit ? (idx / BN) : (idx % KT);
       const int gn = n0 + nn, gk = k0 + kk;
@@ -228,14 +232,14 @@ __global__ __launch_bounds__(256) void k_gemm(GemmK g) {
   auto sstore = [&](int buf) {
 #pragma unroll
     for (int i = 0; i < AL; ++i) {
-      const int idx = tid + 256 * i;
+      const int idx = tid + NTHR * i;
       const int mm = a_m_unit ? (idx % BM) : (idx / KT);
       const int kk = a_m_unit ? (idx / BM) : (idx % KT);
       As[buf][kk][mm] = to_op<T>(ra[i]);
     }
 #pragma unroll
     for (int i = 0; i < BL; ++i) {
-      const int idx = tid + 256 * i;
+      const int idx = tid + NTHR * i;
       const int nn = b_n_unit ? (idx % BN) : (idx / KT);
       const int kk = b_n_unit ? (idx / BN) : (idx % KT);
       Bs[buf][kk][nn] = to_op<T>(rb[i]);
@@ -251,7 +255,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmK g) {
   for (int k0 = kbeg; k0 < kend; k0 += KT) {
     const bool more = k0 + KT < kend;
     if (more) gload(k0 + KT);
-    Mfma<T, FM, FN, LDA>::step(As[buf], Bs[buf], lane, wm * (BM / 2), wn * (BN / 2), acc);
+    Mfma<T, FM, FN, LDA>::step(As[buf], Bs[buf], lane, wm * WTM, wn * WTN, acc);
     if (more) sstore(buf ^ 1);
     __syncthreads();
     buf ^= 1;
@@ -266,8 +270,8 @@ __global__ __launch_bounds__(256) void k_gemm(GemmK g) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = (sizeof(T) == 8) ? (4 * r + (lane >> 4)) : ((lane >> 4) * 4 + r);
-        const int gm = m0 + wm * (BM / 2) + i * 16 + row;
-        const int gn = n0 + wn * (BN / 2) + j * 16 + (lane & 15);
+        const int gm = m0 + wm * WTM + i * 16 + row;
+        const int gn = n0 + wn * WTN + j * 16 + (lane & 15);
         if (gm < P.M && gn < P.N) {
           if (!P.direct) {
             const int64_t bidx = (int64_t)b2 * P.B1 + b1;
@@ -469,9 +473,10 @@ void launch_group(Ctx &c, int np, const Gemm *q, int ngroups, const int *group,
     HIPC(hipEventRecord(sev.first, c.stream));
   }
   if (big)
-    hipLaunchKernelGGL((k_gemm<T, 128, 128>), dim3((unsigned)blocks), dim3(256), 0, c.stream, g);
+    hipLaunchKernelGGL((k_gemm<T, 128, 128, 2, 4>), dim3((unsigned)blocks), dim3(512), 0, c.stream,
+                       g);
   else
-    hipLaunchKernelGGL((k_gemm<T, 64, 64>), dim3((unsigned)blocks), dim3(256), 0, c.stream, g);
+    hipLaunchKernelGGL((k_gemm<T, 64, 64, 2, 2>), dim3((unsigned)blocks), dim3(256), 0, c.stream, g);
   HIPC(hipGetLastError());
   if (shape_rec) {
     HIPC(hipEventRecord(sev.second, c.stream));

@@ -458,7 +458,7 @@ namespace {
 
 bool qr_use_blocked(int m, int n) {
   const int k = std::min(m, n);
-  return k > 2 * QR_NB && (int64_t)m * n > 32768;
+  return k > 2 * QR_NB;
 }
 
 // blocked Householder QR of cnt matrices (all taking the blocked path)

@@ -16,6 +16,7 @@
 
 #include <cstdio>
 #include <cstdlib>
+#include <mutex>
 
 namespace qtt {
 
@@ -23,6 +24,9 @@ namespace {
 
 constexpr int SV_THREADS = 1024;
 constexpr int SV_WAVES = SV_THREADS / 64;
+// larger matrices: blocks of SV_BQ columns, a block pair per SVB_THREADS-thread
+// workgroup; matrices with at most SV_SINGLE columns are one block pair
+constexpr int SV_BQ = 8, SVB_THREADS = 512, SV_SINGLE = 64;
 constexpr int SV_MAXB = 8;
 // rotation threshold on the cosine between two columns: sqrt(m) units of
 // roundoff (the level at which computed column products stop carrying
@@ -44,6 +48,7 @@ struct SvMat {
   double *V;   // n x n column-major
   int *count;  // rotations of the current sweep
   double *fro2;  // squared Frobenius norm of A (invariant under the rotations)
+  int accumulate;  // accumulate the rotations into V (0: V is not wanted)
   int b;       // block width
   int nb;      // blocks
   int single;  // n <= 2b: whole matrix is one block pair
@@ -84,19 +89,30 @@ __global__ __launch_bounds__(SV_THREADS) void k_sv_init(SvBatch B) {
   if (threadIdx.x == 0) *D.count = 0;
 }
 
+// sum over a 16-lane group of a wave
+__device__ inline double grp16_sum(double v) {
+#pragma unroll
+  for (int o = 8; o > 0; o >>= 1) v += __shfl_xor(v, o, 16);
+  return v;
+}
+
 // one Jacobi sweep over the column pairs of the nc LDS columns; returns the
-// number of rotations (valid in every thread after the final barrier)
-// columns whose squared norm is below floor2 are numerically zero (pure
+// number of rotations (valid in every thread after the final barrier).  A
+// pair is handled by a group of 16 lanes (NT / 16 pairs at once), so its
+// three column products need four exchange steps, not six.
+// Columns whose squared norm is below floor2 are numerically zero (pure
 // roundoff); rotating them against each other never converges and changes
-// nothing above the noise, so such pairs are skipped
+// nothing above the noise, so such pairs are skipped.
+template <int NT>
 __device__ int inner_sweep(double *cols, int m, int nc, double *Wacc, int *rot, double floor2) {
   const double tol = sqrt((double)m) * SV_EPS;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  constexpr int NG = NT / 16;
+  const int gl = threadIdx.x & 15, grp = threadIdx.x >> 4;
   const int np = nc + (nc & 1);
   if (threadIdx.x == 0) *rot = 0;
   __syncthreads();
   for (int r = 0; r < np - 1; ++r) {
-    for (int pr = wave; pr < np / 2; pr += SV_WAVES) {
+    for (int pr = grp; pr < np / 2; pr += NG) {
       int p, q;
       if (pr == 0) {
         p = np - 1;
@@ -114,32 +130,32 @@ __device__ int inner_sweep(double *cols, int m, int nc, double *Wacc, int *rot, 
       double *cp = cols + (int64_t)p * m;
       double *cq = cols + (int64_t)q * m;
       double al = 0.0, be = 0.0, ga = 0.0;
-      for (int i = lane; i < m; i += 64) {
+      for (int i = gl; i < m; i += 16) {
         const double x = cp[i], y = cq[i];
         al += x * x;
         be += y * y;
         ga += x * y;
       }
-      al = wave_sum(al);
-      be = wave_sum(be);
-      ga = wave_sum(ga);
+      al = grp16_sum(al);
+      be = grp16_sum(be);
+      ga = grp16_sum(ga);
       if (ga != 0.0 && al > floor2 && be > floor2 && fabs(ga) > tol * sqrt(al * be)) {
         const double zeta = (be - al) / (2.0 * ga);
         const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
         const double cs = 1.0 / sqrt(1.0 + t * t);
         const double sn = cs * t;
-        for (int i = lane; i < m; i += 64) {
+        for (int i = gl; i < m; i += 16) {
           const double x = cp[i], y = cq[i];
           cp[i] = cs * x - sn * y;
           cq[i] = sn * x + cs * y;
         }
         double *wp = Wacc + p * nc, *wq = Wacc + q * nc;
-        for (int i = lane; i < nc; i += 64) {
+        for (int i = gl; i < nc; i += 16) {
           const double x = wp[i], y = wq[i];
           wp[i] = cs * x - sn * y;
           wq[i] = sn * x + cs * y;
         }
-        if (lane == 0) atomicAdd(rot, 1);
+        if (gl == 0) atomicAdd(rot, 1);
       }
     }
     __syncthreads();
@@ -148,7 +164,10 @@ __device__ int inner_sweep(double *cols, int m, int nc, double *Wacc, int *rot, 
 }
 
 // LDS: cols[nc][m], Wacc[nc][nc] (column-major: Wacc[c * nc + k]), colidx[nc], rot
-__global__ __launch_bounds__(SV_THREADS) void k_sv_round(SvBatch B, int round) {
+// NT = 1024 for matrices that are one block pair (the sweep repeats inside
+// the launch), NT = SVB_THREADS for block pairs of 2 SV_BQ columns
+template <int NT>
+__global__ __launch_bounds__(NT) void k_sv_round(SvBatch B, int round) {
   extern __shared__ double lds[];
   // which matrix and which pair
   int mi = 0;
@@ -208,11 +227,11 @@ __global__ __launch_bounds__(SV_THREADS) void k_sv_round(SvBatch B, int round) {
   const double fl = 4.0 * sqrt((double)m) * SV_EPS;
   const double floor2 = fl * fl * *D.fro2;
   __syncthreads();
-  for (int64_t idx = threadIdx.x; idx < (int64_t)nc * m; idx += SV_THREADS) {
+  for (int64_t idx = threadIdx.x; idx < (int64_t)nc * m; idx += NT) {
     const int k = (int)(idx / m), i = (int)(idx % m);
     cols[idx] = D.W[(int64_t)colidx[k] * m + i];
   }
-  for (int idx = threadIdx.x; idx < nc * nc; idx += SV_THREADS)
+  for (int idx = threadIdx.x; idx < nc * nc; idx += NT)
     Wacc[idx] = ((idx / nc) == (idx % nc)) ? 1.0 : 0.0;
   __syncthreads();
 
@@ -220,32 +239,32 @@ __global__ __launch_bounds__(SV_THREADS) void k_sv_round(SvBatch B, int round) {
   if (D.single) {
     int last = 1;
     for (int s = 0; s < 60 && last > 0; ++s) {
-      last = inner_sweep(cols, m, nc, Wacc, &rot, floor2);
+      last = inner_sweep<NT>(cols, m, nc, Wacc, &rot, floor2);
       any += last;
       __syncthreads();
     }
     total = last;
   } else {
-    total = inner_sweep(cols, m, nc, Wacc, &rot, floor2);
+    total = inner_sweep<NT>(cols, m, nc, Wacc, &rot, floor2);
     any = total;
   }
   __syncthreads();
   // columns back to HBM
-  for (int64_t idx = threadIdx.x; idx < (int64_t)nc * m; idx += SV_THREADS) {
+  for (int64_t idx = threadIdx.x; idx < (int64_t)nc * m; idx += NT) {
     const int k = (int)(idx / m), i = (int)(idx % m);
     D.W[(int64_t)colidx[k] * m + i] = cols[idx];
   }
   // V[:, cols] <- V[:, cols] Wacc, staged through the LDS the columns used
   // (n <= m, so the n x nc slice fits)
-  if (any > 0) {
+  if (any > 0 && D.accumulate) {
     __syncthreads();
     double *Vl = cols;
-    for (int64_t idx = threadIdx.x; idx < (int64_t)nc * n; idx += SV_THREADS) {
+    for (int64_t idx = threadIdx.x; idx < (int64_t)nc * n; idx += NT) {
       const int k = (int)(idx / n), i = (int)(idx % n);
       Vl[idx] = D.V[(int64_t)colidx[k] * n + i];
     }
     __syncthreads();
-    for (int64_t idx = threadIdx.x; idx < (int64_t)nc * n; idx += SV_THREADS) {
+    for (int64_t idx = threadIdx.x; idx < (int64_t)nc * n; idx += NT) {
       const int cc = (int)(idx / n), i = (int)(idx % n);
       double s = 0.0;
       for (int k = 0; k < nc; ++k) s += Vl[(int64_t)k * n + i] * Wacc[cc * nc + k];
@@ -290,36 +309,45 @@ __global__ __launch_bounds__(SV_THREADS) void k_sv_finish(SvBatch B) {
     const double s = sig[j];
     D.U[i * D.urs + rank[j] * D.ucs] = (s > 0.0) ? D.W[idx] / s : 0.0;
   }
-  for (int64_t idx = threadIdx.x; idx < (int64_t)n * n; idx += SV_THREADS) {
-    const int i = (int)(idx % n), j = (int)(idx / n);
-    D.Vout[i * D.vrs + rank[j] * D.vcs] = D.V[idx];
-  }
+  if (D.accumulate)
+    for (int64_t idx = threadIdx.x; idx < (int64_t)n * n; idx += SV_THREADS) {
+      const int i = (int)(idx % n), j = (int)(idx / n);
+      D.Vout[i * D.vrs + rank[j] * D.vcs] = D.V[idx];
+    }
 }
 
 // dynamic LDS available to k_sv_round: the device's per-workgroup maximum
 // minus the kernel's static LDS (opted in once per process)
 size_t g_lds_limit = 0;
 
+std::mutex g_lds_mutex;
+
 size_t sv_lds_limit(Ctx &c) {
+  std::lock_guard<std::mutex> lock(g_lds_mutex);
   if (g_lds_limit) return g_lds_limit;
   int maxsh = 0;
   HIPC(hipDeviceGetAttribute(&maxsh, hipDeviceAttributeMaxSharedMemoryPerBlock, c.device));
-  hipFuncAttributes fa;
-  HIPC(hipFuncGetAttributes(&fa, (const void *)k_sv_round));
-  size_t lim = (size_t)maxsh > fa.sharedSizeBytes + 256 ? (size_t)maxsh - fa.sharedSizeBytes - 256
-                                                        : 32768;
-  if (lim > 65536 - fa.sharedSizeBytes - 256) {
-    if (hipFuncSetAttribute((const void *)k_sv_round, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)lim) != hipSuccess) {
-      (void)hipGetLastError();
-      lim = 65536 - fa.sharedSizeBytes - 256;
-    }
+  size_t stat = 0;
+  const void *kerns[2] = {(const void *)k_sv_round<SV_THREADS>, (const void *)k_sv_round<SVB_THREADS>};
+  for (const void *k : kerns) {
+    hipFuncAttributes fa;
+    HIPC(hipFuncGetAttributes(&fa, k));
+    stat = std::max(stat, (size_t)fa.sharedSizeBytes);
+  }
+  size_t lim = (size_t)maxsh > stat + 256 ? (size_t)maxsh - stat - 256 : 32768;
+  if (lim > 65536 - stat - 256) {
+    for (const void *k : kerns)
+      if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lim) !=
+          hipSuccess) {
+        (void)hipGetLastError();
+        lim = 65536 - stat - 256;
+      }
   }
   g_lds_limit = lim;
   const char *vb = std::getenv("QTT_VERBOSE");
   if (vb && vb[0] == '1')
     std::fprintf(stderr, "[qtt] svd: device LDS per workgroup %d, static %zu, dynamic limit %zu\n",
-                 maxsh, (size_t)fa.sharedSizeBytes, lim);
+                 maxsh, stat, lim);
   return lim;
 }
 
@@ -355,7 +383,8 @@ void svd_jacobi(Ctx &c, int count, const ConstMatView *A, const MatView *U, doub
 // (blocked Householder); the one-sided Jacobi then runs on X = R^T, whose
 // columns start much closer to orthogonal than those of A (about half the
 // sweeps on truncation unfoldings) and, for tall A, are also shorter.
-// X = U_X S V_X^T gives A = (Q V_X) S U_X^T.
+// X = U_X S V_X^T gives A = (Q V_X) S U_X^T.  A null U (U[i].p == nullptr)
+// asks for S and V only: the Jacobi rotations are then not accumulated.
 constexpr int SVQ_MIN = 32;
 
 void svd_batch(Ctx &c, int count, const ConstMatView *A, const MatView *U, double *const *S,
@@ -372,9 +401,18 @@ void svd_batch(Ctx &c, int count, const ConstMatView *A, const MatView *U, doubl
     std::vector<ConstMatView> a;
     std::vector<MatView> u, v;
     std::vector<double *> s;
+    int64_t scratch = 0;
+    for (int i : di)
+      if (!U[i].p) scratch += (int64_t)A[i].rows * A[i].cols;
+    double *Us = scratch ? c.buf("svd_Uscratch", scratch) : nullptr;
     for (int i : di) {
       a.push_back(A[i]);
-      u.push_back(U[i]);
+      if (U[i].p) {
+        u.push_back(U[i]);
+      } else {
+        u.push_back(MatView{Us, A[i].rows, A[i].cols, A[i].cols, 1});
+        Us += (int64_t)A[i].rows * A[i].cols;
+      }
       v.push_back(V[i]);
       s.push_back(S[i]);
     }
@@ -401,7 +439,8 @@ void svd_batch(Ctx &c, int count, const ConstMatView *A, const MatView *U, doubl
     r.push_back(MatView{Rb + no, n, n, n, 1});
     x.push_back(ConstMatView{Rb + no, n, n, 1, n});  // R^T
     ux.push_back(MatView{UXb + no, n, n, n, 1});
-    vx.push_back(MatView{VXb + no, n, n, n, 1});
+    // without U the rotations need not be accumulated: V = U_X alone
+    vx.push_back(MatView{U[i].p ? VXb + no : nullptr, n, n, n, 1});
     s.push_back(S[i]);
     qo += (int64_t)m * n;
     no += (int64_t)n * n;
@@ -423,6 +462,7 @@ void svd_batch(Ctx &c, int count, const ConstMatView *A, const MatView *U, doubl
                          V[i].cs, (const double *)ux[k].p, n, n);
       HIPC(hipGetLastError());
     }
+    if (!U[i].p) continue;
     Gemm gq;  // U = Q V_X
     gq.M = m;
     gq.N = n;
@@ -442,8 +482,8 @@ void svd_batch(Ctx &c, int count, const ConstMatView *A, const MatView *U, doubl
 
 namespace {
 
-void svd_jacobi(Ctx &c, int count, const ConstMatView *A, const MatView *U, double *const *S,
-                const MatView *V) {
+void svd_jacobi_group(Ctx &c, int count, const ConstMatView *A, const MatView *U,
+                      double *const *S, const MatView *V, bool single_group) {
   const size_t SV_LDS_LIMIT = sv_lds_limit(c);
   for (int base = 0; base < count; base += SV_MAXB) {
     const int cnt = std::min(SV_MAXB, count - base);
@@ -467,16 +507,19 @@ void svd_jacobi(Ctx &c, int count, const ConstMatView *A, const MatView *U, doub
         span(lo, hi, U[base + i].rows, U[base + i].rs);
         span(lo, hi, U[base + i].cols, U[base + i].cs);
         c.check_range(U[base + i].p, lo, hi, 8, "svd U");
-        lo = hi = 0;
-        span(lo, hi, V[base + i].rows, V[base + i].rs);
-        span(lo, hi, V[base + i].cols, V[base + i].cs);
-        c.check_range(V[base + i].p, lo, hi, 8, "svd V");
+        if (V[base + i].p) {
+          lo = hi = 0;
+          span(lo, hi, V[base + i].rows, V[base + i].rs);
+          span(lo, hi, V[base + i].cols, V[base + i].cs);
+          c.check_range(V[base + i].p, lo, hi, 8, "svd V");
+        }
         c.check_range(S[base + i], 0, n - 1, 8, "svd S");
       }
-      // block width: 2b columns of m rows (plus the rotation) must fit in LDS
-      int b = 32;
-      while (b > 1 && (size_t)(2 * b) * (m + 2 * b) * 8 > SV_LDS_LIMIT) b /= 2;
-      if ((size_t)(2 * b) * (m + 2 * b) * 8 > SV_LDS_LIMIT)
+      // one block pair when the whole matrix fits LDS, else blocks of SV_BQ
+      const bool one = n <= SV_SINGLE && (size_t)n * (m + n) * 8 <= SV_LDS_LIMIT;
+      if (one != single_group) fail(QTT_E_ARG, "svd_batch: block-pair grouping");
+      int b = one ? (n + 1) / 2 : SV_BQ;
+      if (!one && (size_t)(2 * b) * (m + 2 * b) * 8 > SV_LDS_LIMIT)
         fail(QTT_E_UNSUPPORTED, "svd_batch: matrix too tall");
       SvMat &d = B.d[i];
       d.A = a.p;
@@ -493,6 +536,7 @@ void svd_jacobi(Ctx &c, int count, const ConstMatView *A, const MatView *U, doub
       d.ucs = U[base + i].cs;
       d.S = S[base + i];
       d.Vout = V[base + i].p;
+      d.accumulate = V[base + i].p ? 1 : 0;
       d.vrs = V[base + i].rs;
       d.vcs = V[base + i].cs;
       ws += (int64_t)m * n + (int64_t)n * n + 1;
@@ -539,7 +583,12 @@ void svd_jacobi(Ctx &c, int count, const ConstMatView *A, const MatView *U, doub
         }
         if (active == 0) continue;
         // matrices with no work this round keep first = wg (no workgroup maps to them)
-        hipLaunchKernelGGL(k_sv_round, dim3(wg), dim3(SV_THREADS), lds_round, c.stream, R, r);
+        if (single_group)
+          hipLaunchKernelGGL(k_sv_round<SV_THREADS>, dim3(wg), dim3(SV_THREADS), lds_round,
+                             c.stream, R, r);
+        else
+          hipLaunchKernelGGL(k_sv_round<SVB_THREADS>, dim3(wg), dim3(SVB_THREADS), lds_round,
+                             c.stream, R, r);
         HIPC(hipGetLastError());
       }
       HIPC(hipMemcpyAsync(cnt_host, cnt_dev, cnt * sizeof(int), hipMemcpyDeviceToHost, c.stream));
@@ -554,6 +603,32 @@ void svd_jacobi(Ctx &c, int count, const ConstMatView *A, const MatView *U, doub
                    cnt - 1, sweeps_run, rounds);
     hipLaunchKernelGGL(k_sv_finish, dim3(cnt), dim3(SV_THREADS), lds_fin, c.stream, B);
     HIPC(hipGetLastError());
+  }
+}
+
+// matrices that are one block pair and those split into blocks take different
+// round kernels: run them as two groups
+void svd_jacobi(Ctx &c, int count, const ConstMatView *A, const MatView *U, double *const *S,
+                const MatView *V) {
+  const size_t lim = sv_lds_limit(c);
+  std::vector<int> ids[2];
+  for (int i = 0; i < count; ++i) {
+    const int m = A[i].rows, n = A[i].cols;
+    const bool one = n <= SV_SINGLE && (size_t)n * (m + n) * 8 <= lim;
+    ids[one ? 0 : 1].push_back(i);
+  }
+  for (int g = 0; g < 2; ++g) {
+    if (ids[g].empty()) continue;
+    std::vector<ConstMatView> a;
+    std::vector<MatView> u, v;
+    std::vector<double *> s;
+    for (int i : ids[g]) {
+      a.push_back(A[i]);
+      u.push_back(U[i]);
+      v.push_back(V[i]);
+      s.push_back(S[i]);
+    }
+    svd_jacobi_group(c, (int)a.size(), a.data(), u.data(), s.data(), v.data(), g == 0);
   }
 }
 

@@ -6,6 +6,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <sstream>
+#include <thread>
 
 static_assert(qtt::PC_IN == QTT_PC_IN && qtt::PC_W == QTT_PC_WIDTH && qtt::PC_OUT == QTT_PC_OUT,
               "preconditioner sizes");
@@ -297,6 +298,74 @@ int qtt_rk4_step(qtt_ctx *ctx, qtt_mps *u, const qtt_params *p, qtt_stats *stats
     qtt::to_c(um[0], &u[0]);
     qtt::to_c(um[1], &u[1]);
     if (warn) throw qtt::Error{warn, "rk4_step: warning"};
+  });
+}
+
+int qtt_rk4_step_batched(qtt_ctx *ctx, int32_t nflows, qtt_mps *u, const qtt_params *p,
+                         qtt_stats *stats, int32_t workers) {
+  return guard(ctx, [&] {
+    if (nflows < 0 || (nflows > 0 && (!u || !p)) || workers < 0)
+      qtt::fail(QTT_E_ARG, "rk4_step_batched: bad arguments");
+    if (nflows == 0) return;
+    for (int f = 0; f < nflows; ++f) check_params(&p[f]);
+    qtt::Ctx &c = ctx->c;
+    const int W = std::max(1, std::min({workers == 0 ? 4 : (int)workers, (int)nflows, 8}));
+    while ((int)c.workers.size() < W) c.workers.push_back(qtt::make_worker(c));
+    // the workers' streams start after the work already on the caller's stream
+    hipEvent_t ev;
+    HIPC(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    HIPC(hipEventRecord(ev, c.stream));
+    for (int w = 0; w < W; ++w) HIPC(hipStreamWaitEvent(c.workers[w]->stream, ev, 0));
+    std::vector<int> codes(nflows, 0);
+    std::vector<std::string> msgs(nflows);
+    std::vector<std::thread> th;
+    for (int w = 0; w < W; ++w)
+      th.emplace_back([&, w] {
+        (void)hipSetDevice(c.device);
+        qtt::Ctx &wc = *c.workers[w];
+        for (int f = w; f < nflows; f += W) {
+          wc.err.clear();
+          wc.user_ranges.clear();
+          try {
+            reg(wc, u[2 * f]);
+            reg(wc, u[2 * f + 1]);
+            qtt::Mps um[2] = {qtt::from_c(u[2 * f]), qtt::from_c(u[2 * f + 1])};
+            for (int i = 0; i < 2; ++i) check_finite(wc, um[i], "rk4_step_batched: state");
+            qtt_stats *sf = stats ? &stats[f] : nullptr;
+            if (sf) std::memset(sf, 0, sizeof(qtt_stats));
+            try {
+              qtt::rk4_step(wc, um, p[f], sf);
+            } catch (qtt::Error &e) {
+              if (e.code <= 0) throw;
+              codes[f] = e.code;
+            }
+            qtt::to_c(um[0], &u[2 * f]);
+            qtt::to_c(um[1], &u[2 * f + 1]);
+          } catch (qtt::Error &e) {
+            codes[f] = e.code;
+            msgs[f] = e.msg;
+            (void)hipGetLastError();
+            (void)hipStreamSynchronize(wc.stream);
+          } catch (std::exception &e) {
+            codes[f] = QTT_E_HIP;
+            msgs[f] = e.what();
+          }
+        }
+      });
+    for (auto &t : th) t.join();
+    (void)hipEventDestroy(ev);
+    int err = 0, warn = 0;
+    std::string msg;
+    for (int f = 0; f < nflows; ++f) {
+      if (codes[f] < 0 && (err == 0 || codes[f] < err)) {
+        err = codes[f];
+        msg = "rk4_step_batched: flow " + std::to_string(f) + ": " + msgs[f];
+      } else if (codes[f] > 0) {
+        warn = std::max(warn, codes[f]);
+      }
+    }
+    if (err < 0) qtt::fail(err, msg);
+    if (warn) throw qtt::Error{warn, "rk4_step_batched: warning"};
   });
 }
 

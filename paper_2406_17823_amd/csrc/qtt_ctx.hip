@@ -113,6 +113,17 @@ void Ctx::resolve_shapes() {
   shape_flops_pending.clear();
 }
 
+std::unique_ptr<Ctx> make_worker(const Ctx &parent) {
+  std::unique_ptr<Ctx> w(new Ctx());
+  w->device = parent.device;
+  HIPC(hipSetDevice(parent.device));
+  HIPC(hipStreamCreateWithFlags(&w->stream, hipStreamNonBlocking));
+  w->own_stream = true;
+  HIPC(hipHostMalloc((void **)&w->pinned, 4096 * sizeof(double), 0));
+  w->use_graphs = parent.use_graphs;
+  return w;
+}
+
 Ctx::~Ctx() {
   if (shape_stats) {
     try {

@@ -166,6 +166,8 @@ struct Ctx {
   void sync();
   double *alloc_owned(int64_t ndouble);
   void register_user(const void *p, size_t bytes);
+  // worker contexts (own stream and workspace) for concurrent independent flows
+  std::vector<std::unique_ptr<Ctx>> workers;
   // every kernel launch checks that the element range [lo, hi] of each
   // operand lies inside one known allocation; a violation is an error, not
   // a launch
@@ -173,6 +175,10 @@ struct Ctx {
                    const char *what) const;
   ~Ctx();
 };
+
+// a worker context on the parent's device: own non-blocking stream (default
+// priority), own pinned scratch and workspace, the parent's graph setting
+std::unique_ptr<Ctx> make_worker(const Ctx &parent);
 
 // element offsets touched by a strided access with the given extents
 inline void span(int64_t &lo, int64_t &hi, int64_t ext, int64_t stride) {
@@ -259,8 +265,8 @@ struct ConstMatView {
 // k = min(m, n), diag(R) >= 0.  Outputs may alias nothing.
 void qr_batch(Ctx &c, int count, const ConstMatView *A, const MatView *Q, const MatView *R);
 // Batched one-sided Jacobi SVD of m x n (m >= n) matrices: A = U diag(S) V^T,
-// singular values descending.  U is m x n (zero columns for zero sigma),
-// V is n x n, S has n entries (device).
+// singular values descending.  U is m x n, V is n x n, S has n entries
+// (device).  A view with a null pointer in U asks for S and V only.
 void svd_batch(Ctx &c, int count, const ConstMatView *A, const MatView *U, double *const *S,
                const MatView *V);
 

@@ -399,7 +399,8 @@ void mps_truncate(Ctx &c, std::vector<Mps *> ys, int chi, double rtol, double *d
         A[i] = ConstMatView{src, l, 4 * r, 4 * (int64_t)r, 1};
       else
         A[i] = ConstMatView{src, 4 * r, l, 1, 4 * (int64_t)r};
-      U[i] = MatView{Ub + uo, m[i], nn[i], nn[i], 1};
+      // tall: only S and V are needed (G = A V[:, :keep] below)
+      U[i] = MatView{tall[i] ? nullptr : Ub + uo, m[i], nn[i], nn[i], 1};
       V[i] = MatView{Vb + vo, nn[i], nn[i], nn[i], 1};
       S[i] = Sdev + (int64_t)i * maxn;
       uo += (int64_t)m[i] * nn[i];
@@ -426,9 +427,22 @@ void mps_truncate(Ctx &c, std::vector<Mps *> ys, int chi, double rtol, double *d
       for (int j = keep; j < ns; ++j) disc[i] += s[j] * s[j];
       // right factor rows -> new core k (keep x 4r); left factor * S -> G (l x keep)
       if (tall[i]) {
-        // M = U S V^T: core rows = V^T[:keep] ; G = U[:, :keep] S
+        // M = U S V^T: core rows = V^T[:keep] ; G = U[:, :keep] S = M V[:, :keep]
         permute3(c, WC + slot[i][k], Vb + vo, keep, 1, 4 * r, 1, 0, ns);
-        scale_cols(c, Gb + uo, Ub + uo, l, keep, ns, 1, S[i]);
+        Gemm gm;
+        gm.M = l;
+        gm.N = keep;
+        gm.K = 4 * r;
+        gm.A = A[i].p;
+        gm.sAm = A[i].rs;
+        gm.sAk = A[i].cs;
+        gm.B = Vb + vo;
+        gm.sBk = ns;
+        gm.sBn = 1;
+        gm.C = Gb + uo;
+        gm.sCm = keep;
+        gm.sCn = 1;
+        gemm(c, gm);
       } else {
         // M^T = U' S V'^T: core rows = U'^T[:keep] ; G = V'[:, :keep] S
         permute3(c, WC + slot[i][k], Ub + uo, keep, 1, 4 * r, 1, 0, ns);

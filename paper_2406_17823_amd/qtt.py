@@ -60,7 +60,8 @@ class c_kstats(ctypes.Structure):
 SYMBOLS = ['qtt_kernel_timing', 'qtt_kernel_stats_read', 'qtt_ctx_create', 'qtt_ctx_destroy', 'qtt_last_error', 'qtt_mps_size',
            'qtt_mpo_derivative', 'qtt_add', 'qtt_truncate', 'qtt_apply_mpo', 'qtt_hadamard',
            'qtt_inner', 'qtt_to_dense', 'qtt_from_dense', 'qtt_project', 'qtt_rk4_step',
-           'qtt_precond_config', 'qtt_precond_info', 'qtt_precond_weights', 'qtt_precond_grad']
+           'qtt_precond_config', 'qtt_precond_info', 'qtt_precond_weights', 'qtt_precond_grad',
+           'qtt_rk4_step_batched']
 
 _lib = None
 
@@ -98,6 +99,8 @@ def lib():
         'qtt_precond_info': (I32, [P, ctypes.POINTER(I64), ctypes.POINTER(I64), pd, pd]),
         'qtt_precond_weights': (I32, [P, I32, pd, I64]),
         'qtt_precond_grad': (I32, [P, P, I64, P, P, P]),
+        'qtt_rk4_step_batched': (I32, [P, I32, pm, ctypes.POINTER(c_params),
+                                       ctypes.POINTER(c_stats), I32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -339,13 +342,27 @@ def rk4_step(ctx, u, prm):
     return rc, st.as_dict()
 
 
+def rk4_step_batched(ctx, flows, prms, workers=0):
+    """One RK4 step of every flow (a list of [u1, u2] MPS pairs, updated in
+    place) with its own parameters; returns (code, list of stats dicts)."""
+    nf = len(flows)
+    U = (c_mps * (2 * nf))(*[x.struct() for f in flows for x in f])
+    Pp = (c_params * nf)(*prms)
+    St = (c_stats * nf)()
+    rc = ctx.check(lib().qtt_rk4_step_batched(ctx.h, nf, U, Pp, St, workers), 'rk4_step_batched')
+    for f in range(nf):
+        flows[f][0].take(U[2 * f])
+        flows[f][1].take(U[2 * f + 1])
+    return rc, [St[f].as_dict() for f in range(nf)]
+
+
 def kernel_timing(ctx, enable=True, sample_every=1):
     ctx.check(lib().qtt_kernel_timing(ctx.h, 1 if enable else 0, sample_every), 'kernel_timing')
 
 
 KERNEL_GEMM_F64_T64, KERNEL_GEMM_F32_T64, KERNEL_GEMM_F64_T128, KERNEL_GEMM_F32_T128 = 0, 1, 2, 3
-KERNEL_NAMES = {0: 'k_gemm<double, 64, 64>', 1: 'k_gemm<float, 64, 64>',
-                2: 'k_gemm<double, 128, 128>', 3: 'k_gemm<float, 128, 128>'}
+KERNEL_NAMES = {0: 'k_gemm<double, 64, 64, 2, 2>', 1: 'k_gemm<float, 64, 64, 2, 2>',
+                2: 'k_gemm<double, 128, 128, 2, 4>', 3: 'k_gemm<float, 128, 128, 2, 4>'}
 
 
 def kernel_stats(ctx, kernel):
