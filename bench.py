@@ -45,7 +45,9 @@ def parse():
     ap.add_argument('--sweeps', type=int, default=2)
     ap.add_argument('--cg-rtol', type=float, default=1e-10)
     ap.add_argument('--cg-maxit', type=int, default=1000)
-    ap.add_argument('--paths', default='mixed,f64')
+    ap.add_argument('--paths', default='mixed,f64,bf16x3',
+                    help='mixed: float32 convection networks; bf16x3: compensated split '
+                         'bfloat16 convection networks; f64: all float64')
     ap.add_argument('--precond', type=int, default=0)
     ap.add_argument('--sample-every', type=int, default=8)
     ap.add_argument('--cpu-sample', type=int, default=1, help='time the CPU oracle sample')
@@ -149,8 +151,8 @@ def main():
     def prm_for(path):
         return Q.params(re=args.re, dt=args.dt, chi=chi, dx=dx, cg_rtol=args.cg_rtol,
                         cg_maxit=args.cg_maxit, max_sweeps=args.sweeps, svd_rtol=1e-12,
-                        prec=Q.PREC_F32 if path == 'mixed' else Q.PREC_F64,
-                        precond=args.precond if path == 'mixed' else Q.PC_NONE)
+                        prec={'mixed': Q.PREC_F32, 'bf16x3': Q.PREC_BF16X3}.get(path, Q.PREC_F64),
+                        precond=args.precond if path != 'f64' else Q.PC_NONE)
 
     # spin-up: the jet starts with low QTT rank; the workload is the developed
     # flow whose bonds have reached chi (the paper times steps from t = 1)
@@ -190,8 +192,14 @@ def main():
     paths = [p for p in args.paths.split(',') if p]
     results, finals, kstats = {}, {}, {}
     for path in paths:
-        u = [clone(Q, state[0]), clone(Q, state[1])]
         prm = prm_for(path)
+        # one untimed step of this path (its GEMM tile tuning, graph capture
+        # and workspace growth happen here), then the timed steps from the
+        # common state
+        w = [clone(Q, state[0]), clone(Q, state[1])]
+        Q.rk4_step(ctx, w, prm)
+        del w
+        u = [clone(Q, state[0]), clone(Q, state[1])]
         Q.kernel_timing(ctx, True, args.sample_every)
         cg_total, cg_solves = 0, 0
         torch.cuda.synchronize()
@@ -216,6 +224,10 @@ def main():
     rel = None
     if 'mixed' in finals and 'f64' in finals:
         rel = max(rel_l2(Q, ctx, finals['mixed'][i], finals['f64'][i], chi) for i in range(2))
+    for p_ in results:
+        if p_ != 'f64' and 'f64' in finals:
+            results[p_]['rel_l2_vs_f64'] = max(
+                rel_l2(Q, ctx, finals[p_][i], finals['f64'][i], chi) for i in range(2))
 
     # roofline of the dominant kernel of the timed (value) path
     ks = kstats[main_path]

@@ -57,9 +57,12 @@ enum {
   QTT_E_UNSUPPORTED = -6
 };
 
-/* contraction precision of the expensive networks (the QR / SVD, the CG
- * residual and the overlap term always stay float64) */
-enum { QTT_PREC_F64 = 0, QTT_PREC_F32 = 1 };
+/* contraction precision of the 8 convection networks, the only ones whose
+ * contributions are scaled by the stage step h (the overlap, diffusion and
+ * penalty networks, the CG, the QR and the SVD always stay float64):
+ * float64 MFMA, float32 MFMA, or compensated split bfloat16 MFMA (each
+ * operand as a sum of two bfloat16, three products) */
+enum { QTT_PREC_F64 = 0, QTT_PREC_F32 = 1, QTT_PREC_BF16X3 = 2 };
 
 /* preconditioner of the local CG solves */
 enum { QTT_PC_NONE = 0, QTT_PC_BLOCK_JACOBI = 1, QTT_PC_LEARNED = 2 };
@@ -194,9 +197,10 @@ int qtt_rk4_step(qtt_ctx *ctx, qtt_mps *u, const qtt_params *p, qtt_stats *stats
  * many flows of uneven size at once.  u holds 2 * nflows MPS (flow f:
  * u[2f], u[2f+1]), p and stats (may be NULL) nflows entries.  The flows are
  * dealt round-robin to `workers` worker contexts (0 = 4, at most 8), each
- * with its own stream and workspace, and advanced concurrently after the
- * work already enqueued on the context's stream; the call returns when all
- * flows are done.  Each flow's result is bit-identical to qtt_rk4_step on it
+ * with its own stream and workspace (CG chunks are launched directly, not
+ * replayed from graphs), and advanced concurrently after the work already
+ * enqueued on the context's stream; the call returns when all flows are
+ * done.  Each flow's result is bit-identical to qtt_rk4_step on it
  * alone.  Returns the most negative error over the flows (the message names
  * the flow), else the largest warning. */
 int qtt_rk4_step_batched(qtt_ctx *ctx, int32_t nflows, qtt_mps *u, const qtt_params *p,

@@ -17,7 +17,9 @@
 // dimension so that global loads stay coalesced.
 // float64: v_mfma_f64_16x16x4_f64; float32: v_mfma_f32_16x16x4_f32 with
 // float64 operands rounded to float32 on the way into LDS (float64 sums of
-// the float32 16-deep slices); bfloat16: v_mfma_f32_16x16x16_bf16.
+// the float32 16-deep slices); bfloat16: v_mfma_f32_16x16x16_bf16;
+// compensated split bfloat16 (each operand as hi + lo bfloat16, three MFMAs
+// per block dropping lo*lo, float32 within a slice, float64 across slices).
 // When the output tiles cannot fill the 256 compute units, K is split across
 // workgroups; the partial tiles are summed in split order by a second kernel
 // (deterministic).  That kernel also sums several problems into one output
@@ -31,6 +33,18 @@ namespace qtt {
 typedef double d4v __attribute__((ext_vector_type(4)));
 typedef float f4v __attribute__((ext_vector_type(4)));
 typedef __bf16 b4v __attribute__((ext_vector_type(4)));
+
+// compensated split bfloat16 operand: v ~ hi + lo, both bfloat16 (16
+// significant bits in all); products take hi*hi + hi*lo + lo*hi
+struct bf3 {
+  __bf16 hi, lo;
+};
+
+template <typename T> struct GemmKind;
+template <> struct GemmKind<double> { static constexpr int value = 0; };
+template <> struct GemmKind<float> { static constexpr int value = 1; };
+template <> struct GemmKind<__bf16> { static constexpr int value = 2; };
+template <> struct GemmKind<bf3> { static constexpr int value = 3; };
 
 namespace {
 
@@ -141,6 +155,42 @@ struct Mfma<__bf16, FM, FN, LD> {
   }
 };
 
+// compensated split bfloat16: three v_mfma_f32_16x16x16_bf16 per block
+template <int FM, int FN, int LD>
+struct Mfma<bf3, FM, FN, LD> {
+  __device__ static void step(const bf3 (*As)[LD], const bf3 (*Bs)[LD], int lane, int m0, int n0,
+                              d4v (&acc)[FM][FN]) {
+    b4v ah[FM], al[FM], bh[FN], bl[FN];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int kk = 4 * (lane >> 4) + e;
+#pragma unroll
+      for (int i = 0; i < FM; ++i) {
+        const bf3 v = As[kk][m0 + i * 16 + (lane & 15)];
+        ah[i][e] = v.hi;
+        al[i][e] = v.lo;
+      }
+#pragma unroll
+      for (int j = 0; j < FN; ++j) {
+        const bf3 v = Bs[kk][n0 + j * 16 + (lane & 15)];
+        bh[j][e] = v.hi;
+        bl[j][e] = v.lo;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j) {
+        f4v f = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al[i], bh[j], f4v{0.f, 0.f, 0.f, 0.f},
+                                                          0, 0, 0);
+        f = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[i], bl[j], f, 0, 0, 0);
+        f = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[i], bh[j], f, 0, 0, 0);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[i][j][r] += (double)f[r];
+      }
+  }
+};
+
 template <typename T>
 __device__ inline T to_op(double v) {
   return (T)v;
@@ -148,6 +198,13 @@ __device__ inline T to_op(double v) {
 template <>
 __device__ inline __bf16 to_op<__bf16>(double v) {
   return (__bf16)(float)v;
+}
+template <>
+__device__ inline bf3 to_op<bf3>(double v) {
+  bf3 r;
+  r.hi = (__bf16)(float)v;
+  r.lo = (__bf16)(float)(v - (double)(float)r.hi);
+  return r;
 }
 
 // WGM x WGN waves per workgroup, each owning (BM / WGM) x (BN / WGN) outputs
@@ -269,7 +326,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_gemm(GemmK g) {
     for (int j = 0; j < FN; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = (sizeof(T) == 8) ? (4 * r + (lane >> 4)) : ((lane >> 4) * 4 + r);
+        const int row = (GemmKind<T>::value == 0) ? (4 * r + (lane >> 4)) : ((lane >> 4) * 4 + r);
         const int gm = m0 + wm * WTM + i * 16 + row;
         const int gn = n0 + wn * WTN + j * 16 + (lane & 15);
         if (gm < P.M && gn < P.N) {
@@ -356,6 +413,60 @@ void check_operands(Ctx &c, const Gemm &q) {
   c.check_range(q.C, lo, hi, sizeof(double), "gemm C");
 }
 
+// Result-invariant tile autotuning.  For a launch without split-K, whose
+// problems all write C = alpha A B (beta = 0, no summed or extra inputs),
+// running it twice is harmless and every tile size gives bitwise the same C;
+// the first time such a shape appears (outside graph capture) the tile sizes
+// run interleaved three times each, timed with events, and the one with the
+// fastest run is remembered for the shape.  QTT_AUTOTUNE=0 keeps the
+// heuristic choice.
+template <typename T, typename Build>
+int tuned_tile(Ctx &c, int np, const Gemm *q, int ngroups, const double *const *X,
+               int heuristic, Build &build, GemmK &g, int64_t &blocks, int64_t &part_need) {
+  if (!c.autotune || c.capturing || ngroups != np) return heuristic;
+  for (int i = 0; i < np; ++i)
+    if (q[i].beta != 0.0 || X[i] != nullptr) return heuristic;
+  char key[256];
+  int o = std::snprintf(key, sizeof key, "%d:%d", GemmKind<T>::value, np);
+  for (int i = 0; i < np && o < (int)sizeof key - 48; ++i)
+    o += std::snprintf(key + o, sizeof key - o, "|%d,%d,%d,%d,%d,%d%d", q[i].M, q[i].N, q[i].K,
+                       q[i].B1, q[i].B2, q[i].sAm == 1, q[i].sBn == 1);
+  auto it = c.gemm_tune.find(key);
+  if (it != c.gemm_tune.end()) return it->second;
+  // candidates interleaved, three rounds, fastest single run of each
+  const int cand[2] = {64, 128};
+  float best[2] = {3.0e38f, 3.0e38f};
+  hipEvent_t e0 = c.take_event(), e1 = c.take_event();
+  for (int rep = 0; rep < 3; ++rep)
+    for (int ci = 0; ci < 2; ++ci) {
+      const int MT = cand[ci];
+      build(MT);
+      if (g.np == 0 || part_need > 0) {
+        c.kt.pool.push_back(e0);
+        c.kt.pool.push_back(e1);
+        return heuristic;
+      }
+      HIPC(hipEventRecord(e0, c.stream));
+      if (MT == 128)
+        hipLaunchKernelGGL((k_gemm<T, 128, 128, 2, 4>), dim3((unsigned)blocks), dim3(512), 0,
+                           c.stream, g);
+      else
+        hipLaunchKernelGGL((k_gemm<T, 64, 64, 2, 2>), dim3((unsigned)blocks), dim3(256), 0,
+                           c.stream, g);
+      HIPC(hipGetLastError());
+      HIPC(hipEventRecord(e1, c.stream));
+      HIPC(hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIPC(hipEventElapsedTime(&ms, e0, e1));
+      best[ci] = std::min(best[ci], ms);
+    }
+  const int choice = best[1] < best[0] ? 128 : 64;
+  c.kt.pool.push_back(e0);
+  c.kt.pool.push_back(e1);
+  c.gemm_tune[key] = choice;
+  return choice;
+}
+
 // np problems; problem i belongs to output group group[i] (a group holds
 // one or two problems that share C; X[group] is the beta input, nullptr = C).
 template <typename T>
@@ -365,7 +476,7 @@ void launch_group(Ctx &c, int np, const Gemm *q, int ngroups, const int *group,
   g.np = 0;
   g.skip = skip;
   g.flops = 0.0;
-  const int kind = (sizeof(T) == 8) ? 0 : (sizeof(T) == 4 ? 1 : 2);
+  const int kind = GemmKind<T>::value;
   int64_t blocks = 0;
   int nsrc[GEMM_GROUP] = {0};
   for (int i = 0; i < np; ++i) {
@@ -376,81 +487,96 @@ void launch_group(Ctx &c, int np, const Gemm *q, int ngroups, const int *group,
   int64_t part_need = 0;
   int64_t part_off[GEMM_GROUP] = {0};
   int keep[GEMM_GROUP];
-  // 128 x 128 tiles when the launch has one per compute unit, else 64 x 64
-  int64_t tiles128 = 0;
-  for (int i = 0; i < np; ++i)
-    tiles128 += (int64_t)((q[i].M + 127) / 128) * ((q[i].N + 127) / 128) * q[i].B1 * q[i].B2;
-  const bool big = tiles128 >= 256;
-  const int MT = big ? 128 : 64, NT = MT;
-  int64_t grp_tiles = 0;
-  for (int i = 0; i < np; ++i)
-    grp_tiles += (int64_t)((q[i].M + MT - 1) / MT) * ((q[i].N + NT - 1) / NT) * q[i].B1 * q[i].B2;
+  // split-K is decided on the 64 x 64 tiling alone, so the tile size never
+  // changes the summation order: every tile choice gives identical results
+  int64_t tiles64 = 0, tiles128 = 0;
   for (int i = 0; i < np; ++i) {
-    const Gemm &s = q[i];
-    keep[i] = -1;
-    if (s.M <= 0 || s.N <= 0 || s.B1 <= 0 || s.B2 <= 0) continue;
-    check_operands(c, s);
-    Prob &P = g.p[g.np];
-    keep[i] = g.np++;
-    P.M = s.M;
-    P.N = s.N;
-    P.K = s.K;
-    P.B1 = s.B1;
-    P.B2 = s.B2;
-    P.tm = (s.M + MT - 1) / MT;
-    P.tn = (s.N + NT - 1) / NT;
-    P.A = s.A;
-    P.sAm = s.sAm;
-    P.sAk = s.sAk;
-    P.sAb1 = s.sAb1;
-    P.sAb2 = s.sAb2;
-    P.B = s.B;
-    P.sBk = s.sBk;
-    P.sBn = s.sBn;
-    P.sBb1 = s.sBb1;
-    P.sBb2 = s.sBb2;
-    P.C = s.C;
-    P.sCm = s.sCm;
-    P.sCn = s.sCn;
-    P.sCb1 = s.sCb1;
-    P.sCb2 = s.sCb2;
-    P.alpha = s.alpha;
-    P.beta = s.beta;
-    P.part = nullptr;
-    g.flops += 2.0 * s.M * (double)s.N * s.K * s.B1 * s.B2;
-    const int64_t out_tiles = (int64_t)P.tm * P.tn * P.B1 * P.B2;
-    P.ksplit = 1;
-    P.kchunk = std::max(s.K, 1);
-    // split K when the group's output tiles cannot fill the compute units
-    if (grp_tiles < 256 && s.K >= 4 * KT) {
-      const int64_t want = (512 + grp_tiles - 1) / grp_tiles;
-      const int64_t maxs = s.K / (2 * KT);
-      int ks = (int)std::max<int64_t>(1, std::min<int64_t>(want, maxs));
-      if (ks > 1) {
-        int chunk = (s.K + ks - 1) / ks;
-        chunk = ((chunk + KT - 1) / KT) * KT;
-        ks = (s.K + chunk - 1) / chunk;
-        P.ksplit = ks;
-        P.kchunk = chunk;
-      }
-    }
-    P.direct = (P.ksplit == 1 && nsrc[group[i]] == 1 && X[group[i]] == nullptr) ? 1 : 0;
-    part_off[g.np - 1] = part_need;
-    if (!P.direct) part_need += (int64_t)P.ksplit * P.M * P.N * P.B1 * P.B2;
-    P.block0 = blocks;
-    blocks += out_tiles * P.ksplit;
+    tiles64 += (int64_t)((q[i].M + 63) / 64) * ((q[i].N + 63) / 64) * q[i].B1 * q[i].B2;
+    tiles128 += (int64_t)((q[i].M + 127) / 128) * ((q[i].N + 127) / 128) * q[i].B1 * q[i].B2;
   }
+  const bool may_split = tiles64 < 256;
+  auto build = [&](int MT) {
+    const int NT = MT;
+    g.np = 0;
+    g.flops = 0.0;
+    blocks = 0;
+    part_need = 0;
+    for (int i = 0; i < np; ++i) {
+      const Gemm &s = q[i];
+      keep[i] = -1;
+      if (s.M <= 0 || s.N <= 0 || s.B1 <= 0 || s.B2 <= 0) continue;
+      Prob &P = g.p[g.np];
+      keep[i] = g.np++;
+      P.M = s.M;
+      P.N = s.N;
+      P.K = s.K;
+      P.B1 = s.B1;
+      P.B2 = s.B2;
+      P.tm = (s.M + MT - 1) / MT;
+      P.tn = (s.N + NT - 1) / NT;
+      P.A = s.A;
+      P.sAm = s.sAm;
+      P.sAk = s.sAk;
+      P.sAb1 = s.sAb1;
+      P.sAb2 = s.sAb2;
+      P.B = s.B;
+      P.sBk = s.sBk;
+      P.sBn = s.sBn;
+      P.sBb1 = s.sBb1;
+      P.sBb2 = s.sBb2;
+      P.C = s.C;
+      P.sCm = s.sCm;
+      P.sCn = s.sCn;
+      P.sCb1 = s.sCb1;
+      P.sCb2 = s.sCb2;
+      P.alpha = s.alpha;
+      P.beta = s.beta;
+      P.part = nullptr;
+      g.flops += 2.0 * s.M * (double)s.N * s.K * s.B1 * s.B2;
+      const int64_t out_tiles = (int64_t)P.tm * P.tn * P.B1 * P.B2;
+      P.ksplit = 1;
+      P.kchunk = std::max(s.K, 1);
+      // split K when the group's output tiles cannot fill the compute units
+      if (may_split && s.K >= 4 * KT) {
+        const int64_t want = (512 + tiles64 - 1) / tiles64;
+        const int64_t maxs = s.K / (2 * KT);
+        int ks = (int)std::max<int64_t>(1, std::min<int64_t>(want, maxs));
+        if (ks > 1) {
+          int chunk = (s.K + ks - 1) / ks;
+          chunk = ((chunk + KT - 1) / KT) * KT;
+          ks = (s.K + chunk - 1) / chunk;
+          P.ksplit = ks;
+          P.kchunk = chunk;
+        }
+      }
+      P.direct = (P.ksplit == 1 && nsrc[group[i]] == 1 && X[group[i]] == nullptr) ? 1 : 0;
+      part_off[g.np - 1] = part_need;
+      if (!P.direct) part_need += (int64_t)P.ksplit * P.M * P.N * P.B1 * P.B2;
+      P.block0 = blocks;
+      blocks += out_tiles * P.ksplit;
+    }
+  };
+  for (int i = 0; i < np; ++i)
+    if (q[i].M > 0 && q[i].N > 0 && q[i].B1 > 0 && q[i].B2 > 0) check_operands(c, q[i]);
+  // tile size: 64 x 64 while split-K may be needed; otherwise the tuned
+  // choice for this shape, or 128 x 128 when there is one such tile per CU
+  int MT = (!may_split && tiles128 >= 256) ? 128 : 64;
+  if (!may_split) MT = tuned_tile<T>(c, np, q, ngroups, X, MT, build, g, blocks, part_need);
+  build(MT);
   if (g.np == 0) return;
   if (blocks > 0x7fffffffLL) fail(QTT_E_UNSUPPORTED, "gemm grid too large");
   if (part_need > ((int64_t)64 << 20)) fail(QTT_E_UNSUPPORTED, "gemm split-K buffer too large");
   if (part_need > 0) {
-    double *part = c.buf(kind == 0 ? "gemm_splitk64" : (kind == 1 ? "gemm_splitk32" : "gemm_splitk16"), part_need);
+    static const char *const names[4] = {"gemm_splitk64", "gemm_splitk32", "gemm_splitk16",
+                                         "gemm_splitk16x3"};
+    double *part = c.buf(names[kind], part_need);
     for (int i = 0; i < g.np; ++i)
       if (!g.p[i].direct) g.p[i].part = part + part_off[i];
   }
 
   bool timed = false;
   std::pair<hipEvent_t, hipEvent_t> ev;
+  const bool big = (MT == 128);
   const int tk = kind + (big ? 2 : 0);  // timer kind
   if (c.kt.on && kind < 2) g.flop_ctr = c.kt.flop_ctr + tk;
   if (c.capturing) {
@@ -483,7 +609,8 @@ void launch_group(Ctx &c, int np, const Gemm *q, int ngroups, const int *group,
     char key[200];
     const Prob &P = g.p[0];
     std::snprintf(key, sizeof key, "%s x%d M=%d N=%d K=%d B=%dx%d split=%d t%d %s%s",
-                  kind == 0 ? "f64" : (kind == 1 ? "f32" : "bf16"), g.np, P.M, P.N, P.K, P.B1, P.B2, P.ksplit, MT,
+                  kind == 0 ? "f64" : (kind == 1 ? "f32" : (kind == 2 ? "bf16" : "bf16x3")), g.np,
+                  P.M, P.N, P.K, P.B1, P.B2, P.ksplit, MT,
                   P.sAm == 1 ? "Am" : "Ak", P.sBn == 1 ? "Bn" : "Bk");
     c.shape_pending.push_back({key, sev});
     c.shape_flops_pending.push_back(g.flops);
@@ -574,6 +701,12 @@ void gemm_bf16(Ctx &c, const Gemm &g) {
   const int grp = 0;
   const double *X = nullptr;
   launch_group<__bf16>(c, 1, &g, 1, &grp, &X, g.skip);
+}
+
+void gemm_bf16x3(Ctx &c, const Gemm &g) {
+  const int grp = 0;
+  const double *X = nullptr;
+  launch_group<bf3>(c, 1, &g, 1, &grp, &X, g.skip);
 }
 
 void gemm_grouped(Ctx &c, int np, const Gemm *q, int ngroups, const int *group,

@@ -278,6 +278,33 @@ __global__ __launch_bounds__(LA_THREADS) void k_qrb_panel(QrbBatch B, int j0) {
   }
 }
 
+// sum over the 64 lanes of a wave of 16 values at once: four butterfly
+// steps halve the values each lane holds (17 exchanges instead of 16 x 6);
+// on return lane l holds the total of value (l >> 2) & 15
+__device__ inline double wave_sum16(const double (&v)[16], int lane) {
+  double a[8], b[4], c[2];
+  const bool h5 = (lane >> 5) & 1, h4 = (lane >> 4) & 1, h3 = (lane >> 3) & 1, h2 = (lane >> 2) & 1;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const double keep = h5 ? v[j + 8] : v[j], send = h5 ? v[j] : v[j + 8];
+    a[j] = keep + __shfl_xor(send, 32, 64);
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const double keep = h4 ? a[j + 4] : a[j], send = h4 ? a[j] : a[j + 4];
+    b[j] = keep + __shfl_xor(send, 16, 64);
+  }
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const double keep = h3 ? b[j + 2] : b[j], send = h3 ? b[j] : b[j + 2];
+    c[j] = keep + __shfl_xor(send, 8, 64);
+  }
+  double d = (h2 ? c[1] : c[0]) + __shfl_xor(h2 ? c[0] : c[1], 4, 64);
+  d += __shfl_xor(d, 2, 64);
+  d += __shfl_xor(d, 1, 64);
+  return d;
+}
+
 // register-resident panel for m <= QR_REG_ROWS * QR_REG_THREADS: thread tid
 // holds rows r = tid + QR_REG_THREADS * s of the panel's columns, so each column
 // step touches HBM/L2 not at all; the column loop is unrolled so that every
@@ -359,12 +386,10 @@ __global__ __launch_bounds__(QR_REG_THREADS) void k_qrb_panel_reg(QrbBatch B, in
         else d[t] += v * P[s][t];
       }
     }
-#pragma unroll
-    for (int t = 0; t < QR_NB; ++t) {
-      if (t < jb) {
-        const double sum = wave_sum(d[t]);
-        if (lane == 0) sh[wave][t] = sum;
-      }
+    static_assert(QR_NB == 16, "wave_sum16 reduces 16 columns");
+    {
+      const double sum = wave_sum16(d, lane);
+      if ((lane & 3) == 0) sh[wave][lane >> 2] = sum;
     }
     __syncthreads();
     if (tid < jb) {

@@ -24,9 +24,10 @@ namespace {
 
 constexpr int SV_THREADS = 1024;
 constexpr int SV_WAVES = SV_THREADS / 64;
-// larger matrices: blocks of SV_BQ columns, a block pair per SVB_THREADS-thread
+// larger matrices: blocks of SV_BQ columns (halved when a block pair of m rows
+// does not fit LDS), a block pair per SVB_THREADS-thread
 // workgroup; matrices with at most SV_SINGLE columns are one block pair
-constexpr int SV_BQ = 8, SVB_THREADS = 512, SV_SINGLE = 64;
+constexpr int SV_BQ = 16, SVB_THREADS = 512, SV_SINGLE = 64;
 constexpr int SV_MAXB = 8;
 // rotation threshold on the cosine between two columns: sqrt(m) units of
 // roundoff (the level at which computed column products stop carrying
@@ -519,6 +520,7 @@ void svd_jacobi_group(Ctx &c, int count, const ConstMatView *A, const MatView *U
       const bool one = n <= SV_SINGLE && (size_t)n * (m + n) * 8 <= SV_LDS_LIMIT;
       if (one != single_group) fail(QTT_E_ARG, "svd_batch: block-pair grouping");
       int b = one ? (n + 1) / 2 : SV_BQ;
+      while (!one && b > 4 && (size_t)(2 * b) * (m + 2 * b) * 8 > SV_LDS_LIMIT) b /= 2;
       if (!one && (size_t)(2 * b) * (m + 2 * b) * 8 > SV_LDS_LIMIT)
         fail(QTT_E_UNSUPPORTED, "svd_batch: matrix too tall");
       SvMat &d = B.d[i];

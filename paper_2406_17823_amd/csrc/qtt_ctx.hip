@@ -120,7 +120,11 @@ std::unique_ptr<Ctx> make_worker(const Ctx &parent) {
   HIPC(hipStreamCreateWithFlags(&w->stream, hipStreamNonBlocking));
   w->own_stream = true;
   HIPC(hipHostMalloc((void **)&w->pinned, 4096 * sizeof(double), 0));
-  w->use_graphs = parent.use_graphs;
+  // no stream capture in workers: an allocation or a synchronous copy made by
+  // another worker while one captures would invalidate the capture (device-
+  // wide synchronisation); eager CG chunks give the same results
+  w->use_graphs = false;
+  w->autotune = parent.autotune;
   return w;
 }
 

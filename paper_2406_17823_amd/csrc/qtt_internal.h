@@ -143,6 +143,8 @@ struct Ctx {
   KernelTimer kt;
   PrecondNet pc;
   bool use_graphs = true;             // QTT_GRAPHS=0 disables CG graph capture
+  bool autotune = true;               // QTT_AUTOTUNE=0 keeps heuristic GEMM tiles
+  std::map<std::string, int> gemm_tune;  // tuned tile size per GEMM shape
   bool capturing = false;             // a stream capture is open
   int64_t cap_launches[KT_KINDS] = {0, 0, 0, 0};
   std::map<std::string, CgGraph> cg_graphs;
@@ -177,7 +179,7 @@ struct Ctx {
 };
 
 // a worker context on the parent's device: own non-blocking stream (default
-// priority), own pinned scratch and workspace, the parent's graph setting
+// priority), own pinned scratch and workspace, no graph capture
 std::unique_ptr<Ctx> make_worker(const Ctx &parent);
 
 // element offsets touched by a strided access with the given extents
@@ -215,6 +217,9 @@ void gemm_grouped(Ctx &c, int np, const Gemm *q, int ngroups, const int *group,
 void gemm_f32(Ctx &c, const Gemm &g);
 // bfloat16-MFMA variant (float32 accumulation) with float64 inputs/outputs
 void gemm_bf16(Ctx &c, const Gemm &g);
+// compensated split-bfloat16 variant: hi*hi + hi*lo + lo*hi on bfloat16 MFMA
+// (about 16 significant bits per operand), float64 inputs/outputs
+void gemm_bf16x3(Ctx &c, const Gemm &g);
 
 // ---------------------------------------------------------------- small kernels
 void fill(Ctx &c, double *p, int64_t n, double v);

@@ -60,7 +60,7 @@ struct Net {
   const Mps *ket = nullptr;
   const double *ket_rev = nullptr;
   double coef = 1.0;
-  bool f32 = false;
+  int prec = QTT_PREC_F64;  // contraction precision of this network
   double *env = nullptr;
   std::vector<int64_t> eoff;
   double *T = nullptr;
@@ -114,7 +114,8 @@ struct Sweep {
   }
 
   void gemm_for(const Net &N, const Gemm &g) {
-    if (N.f32) gemm_f32(c, g);
+    if (N.prec == QTT_PREC_F32) gemm_f32(c, g);
+    else if (N.prec == QTT_PREC_BF16X3) gemm_bf16x3(c, g);
     else gemm(c, g);
   }
 
@@ -770,7 +771,8 @@ void project(Ctx &c, const Mps a[2], const Mps b[2], double h, const qtt_params 
   }
   if (n < 2) fail(QTT_E_UNSUPPORTED, "project: n < 2");
   if (p.max_sweeps < 1 || p.cg_maxit < 1) fail(QTT_E_ARG, "project: max_sweeps/cg_maxit < 1");
-  if (p.prec != QTT_PREC_F64 && p.prec != QTT_PREC_F32) fail(QTT_E_ARG, "project: prec");
+  if (p.prec != QTT_PREC_F64 && p.prec != QTT_PREC_F32 && p.prec != QTT_PREC_BF16X3)
+    fail(QTT_E_ARG, "project: prec");
   if (p.precond != QTT_PC_NONE && p.precond != QTT_PC_BLOCK_JACOBI &&
       p.precond != QTT_PC_LEARNED)
     fail(QTT_E_ARG, "project: precond");
@@ -800,7 +802,7 @@ void project(Ctx &c, const Mps a[2], const Mps b[2], double h, const qtt_params 
   auto D1 = get_mpo(c, n, "D1", p.dx, 0), D2 = get_mpo(c, n, "D2", p.dx, 0);
   auto LAP = get_mpo(c, n, "LAP", p.dx, p.lap_mode);
   const Mpo *D[2] = {D1.get(), D2.get()};
-  const bool f32 = (p.prec == QTT_PREC_F32);
+  const int conv_prec = p.prec;  // precision of the 8 convection networks
 
   for (int i = 0; i < 2; ++i) {
     Net ov;
@@ -828,7 +830,7 @@ void project(Ctx &c, const Mps a[2], const Mps b[2], double h, const qtt_params 
         N.ket = &b[i];
         N.ket_rev = brev[i];
         N.coef = -0.5 * h;
-        N.f32 = f32;
+        N.prec = conv_prec;
         S.rhs.push_back(N);
       }
     Net df;
