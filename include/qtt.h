@@ -27,6 +27,13 @@
  *   and device outputs are valid on return.  Inner CG iterations are
  *   replayed from captured HIP graphs (QTT_GRAPHS=0 disables this).
  *
+ * Environment (read when a context is created)
+ *   QTT_GRAPHS=0    no graph capture of CG iterations
+ *   QTT_AUTOTUNE=1  time both GEMM tile sizes on the first use of each
+ *                   shape and keep the faster (results are unchanged)
+ *   QTT_TIMING=1    host-timed phase statistics in qtt_stats.phase_ms
+ *   QTT_VERBOSE=1   per-call diagnostics on stderr
+ *
  * Errors
  *   0 = success, > 0 = warning (result valid), < 0 = error (outputs
  *   undefined).  No C++ exception crosses this interface.  One context per

@@ -418,8 +418,7 @@ void check_operands(Ctx &c, const Gemm &q) {
 // running it twice is harmless and every tile size gives bitwise the same C;
 // the first time such a shape appears (outside graph capture) the tile sizes
 // run interleaved three times each, timed with events, and the one with the
-// fastest run is remembered for the shape.  QTT_AUTOTUNE=0 keeps the
-// heuristic choice.
+// fastest run is remembered for the shape (enabled by QTT_AUTOTUNE=1).
 template <typename T, typename Build>
 int tuned_tile(Ctx &c, int np, const Gemm *q, int ngroups, const double *const *X,
                int heuristic, Build &build, GemmK &g, int64_t &blocks, int64_t &part_need) {

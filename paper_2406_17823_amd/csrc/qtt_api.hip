@@ -90,7 +90,7 @@ int qtt_ctx_create(qtt_ctx **out, int device, void *hip_stream) {
   const char *gr = std::getenv("QTT_GRAPHS");
   c->c.use_graphs = !(gr && gr[0] == '0');
   const char *at = std::getenv("QTT_AUTOTUNE");
-  c->c.autotune = !(at && at[0] == '0');
+  c->c.autotune = (at && at[0] == '1');
   const char *gs = std::getenv("QTT_GEMM_STATS");
   c->c.shape_stats = (gs && gs[0] == '1');
   *out = c;

@@ -143,7 +143,7 @@ struct Ctx {
   KernelTimer kt;
   PrecondNet pc;
   bool use_graphs = true;             // QTT_GRAPHS=0 disables CG graph capture
-  bool autotune = true;               // QTT_AUTOTUNE=0 keeps heuristic GEMM tiles
+  bool autotune = false;              // QTT_AUTOTUNE=1 tunes GEMM tile sizes per shape
   std::map<std::string, int> gemm_tune;  // tuned tile size per GEMM shape
   bool capturing = false;             // a stream capture is open
   int64_t cap_launches[KT_KINDS] = {0, 0, 0, 0};
@@ -293,8 +293,16 @@ void build_derivative_host(int n, int axis, int order, double dx, std::vector<do
                            int *bond);
 
 // ---------------------------------------------------------------- sweep / RK4
+// What the four stages of one RK4 step share: the stages start from the same
+// guess a = u/4, so its right-canonical form and the initial right
+// environments of the networks that do not involve b (overlap and penalty
+// pairs) are computed by the first stage and copied by the others.
+struct StageCache {
+  bool valid = false;
+  int bond[2][QTT_MAX_SITES + 1];
+};
 void project(Ctx &c, const Mps a[2], const Mps b[2], double h, const qtt_params &p, Mps v[2],
-             qtt_stats *st, int stage);
+             qtt_stats *st, int stage, StageCache *cache = nullptr);
 void rk4_step(Ctx &c, Mps u[2], const qtt_params &p, qtt_stats *st);
 
 // ---------------------------------------------------------------- learned preconditioner

@@ -763,7 +763,7 @@ void check_profile(const Mps &x, const char *what) {
 }  // namespace
 
 void project(Ctx &c, const Mps a[2], const Mps b[2], double h, const qtt_params &p, Mps v[2],
-             qtt_stats *st, int stage) {
+             qtt_stats *st, int stage, StageCache *cache) {
   const int n = v[0].n;
   for (int i = 0; i < 2; ++i) {
     if (a[i].n != n || b[i].n != n || v[i].n != n) fail(QTT_E_SHAPE, "project: site counts differ");
@@ -785,7 +785,18 @@ void project(Ctx &c, const Mps a[2], const Mps b[2], double h, const qtt_params 
   S.stats = st;
   S.mu_h2 = p.mu * h * h;
 
-  mps_right_canonicalize(c, {&v[0], &v[1]});
+  const bool reuse = cache && cache->valid;
+  if (reuse) {
+    // the canonical guess of the first stage (same a, same canonical form)
+    for (int i = 0; i < 2; ++i) {
+      for (int k = 0; k <= n; ++k) v[i].bond[k] = cache->bond[i][k];
+      if (v[i].size() > v[i].capacity) fail(QTT_E_CAPACITY, "project: guess capacity");
+      HIPC(hipMemcpyAsync(v[i].data, c.buf("rk4c_v" + std::to_string(i), v[i].size()),
+                          v[i].size() * sizeof(double), hipMemcpyDeviceToDevice, c.stream));
+    }
+  } else {
+    mps_right_canonicalize(c, {&v[0], &v[1]});
+  }
 
   // site-reversed copies of the fixed MPS and the trial MPS
   double *arev[2], *brev[2];
@@ -872,12 +883,34 @@ void project(Ctx &c, const Mps a[2], const Mps b[2], double h, const qtt_params 
   S.alloc(all);
   S.alloc_pen_tmp();
 
-  // right environments, sites n-1 .. 1
+  // right environments, sites n-1 .. 1; the overlap and penalty networks do
+  // not involve b and are copied from the first stage when it is cached
+  auto b_free = [](const Net &N) { return N.nl == 0 || N.trial_ket; };
+  auto env_total = [&](const Net &N) { return N.eoff[n] + 1; };
   for (int d = n - 1; d >= 1; --d)
     for (Net *N : all) {
+      if (reuse && b_free(*N)) continue;
       S.chain(*N, d, true, N->env + N->eoff[d + 1], S.ket_core(*N, d, true), S.Tpen, nullptr);
       S.env_from_T(*N, d, true, S.Tpen);
     }
+  for (size_t idx = 0; idx < all.size(); ++idx) {
+    if (!cache || !b_free(*all[idx])) continue;
+    double *saved = c.buf("rk4c_env" + std::to_string(idx), env_total(*all[idx]));
+    if (reuse)
+      HIPC(hipMemcpyAsync(all[idx]->env, saved, env_total(*all[idx]) * sizeof(double),
+                          hipMemcpyDeviceToDevice, c.stream));
+    else
+      HIPC(hipMemcpyAsync(saved, all[idx]->env, env_total(*all[idx]) * sizeof(double),
+                          hipMemcpyDeviceToDevice, c.stream));
+  }
+  if (cache && !reuse) {
+    for (int i = 0; i < 2; ++i) {
+      for (int k = 0; k <= n; ++k) cache->bond[i][k] = v[i].bond[k];
+      HIPC(hipMemcpyAsync(c.buf("rk4c_v" + std::to_string(i), v[i].size()), v[i].data,
+                          v[i].size() * sizeof(double), hipMemcpyDeviceToDevice, c.stream));
+    }
+    cache->valid = true;
+  }
   if (st && c.timing) {
     c.sync();
     st->phase_ms[1] += Sweep::ms_since(t0);
@@ -938,6 +971,7 @@ void rk4_step(Ctx &c, Mps u[2], const qtt_params &p, qtt_stats *st) {
     }
   }
   static const double hs[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
+  StageCache cache;
   static const double bc[3][2] = {{3.0, 0.25}, {1.5, 0.625}, {3.0, 0.25}};
   int warn = 0;
   Mps a[2], U[4][2], bb[2], sum[2];
@@ -991,7 +1025,7 @@ void rk4_step(Ctx &c, Mps u[2], const qtt_params &p, qtt_stats *st) {
       b = bb;
     }
     for (int i = 0; i < 2; ++i) mps_copy(c, a[i], U[k][i]);
-    run([&] { project(c, a, b, hs[k] * p.dt, p, U[k], st, k); });
+    run([&] { project(c, a, b, hs[k] * p.dt, p, U[k], st, k, &cache); });
   }
   auto t0 = std::chrono::steady_clock::now();
   for (int i = 0; i < 2; ++i) {

@@ -14,7 +14,7 @@ pytestmark = pytest.mark.gpu
 
 
 def _step(Q, tune, n, chi):
-    os.environ['QTT_AUTOTUNE'] = '1' if tune else '0'
+    os.environ['QTT_AUTOTUNE'] = '1' if tune else '0'  # read when the context is created
     try:
         ctx = Q.Context(0)
     finally:
