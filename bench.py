@@ -44,6 +44,11 @@ def parse():
     ap.add_argument('--dt', type=float, default=5e-5)
     ap.add_argument('--sweeps', type=int, default=2)
     ap.add_argument('--cg-rtol', type=float, default=1e-10)
+    ap.add_argument('--mixed-cg-rtol', type=float, default=1e-9,
+                    help='CG tolerance of the reduced-precision paths: their right-hand '
+                         'sides carry float32 rounding of the convection terms (about 1e-10 '
+                         'of the norm on this workload, the derivative MPO entries scale as '
+                         '1/dx), so a tighter solve mostly fits that rounding')
     ap.add_argument('--cg-maxit', type=int, default=1000)
     ap.add_argument('--paths', default='mixed,f64,bf16x3',
                     help='mixed: float32 convection networks; bf16x3: compensated split '
@@ -149,7 +154,8 @@ def main():
     log('initial bonds', state[0].bonds, state[1].bonds, f'{time.perf_counter() - t0:.1f}s')
 
     def prm_for(path):
-        return Q.params(re=args.re, dt=args.dt, chi=chi, dx=dx, cg_rtol=args.cg_rtol,
+        return Q.params(re=args.re, dt=args.dt, chi=chi, dx=dx,
+                        cg_rtol=args.cg_rtol if path == 'f64' else args.mixed_cg_rtol,
                         cg_maxit=args.cg_maxit, max_sweeps=args.sweeps, svd_rtol=1e-12,
                         prec={'mixed': Q.PREC_F32, 'bf16x3': Q.PREC_BF16X3}.get(path, Q.PREC_F64),
                         precond=args.precond if path != 'f64' else Q.PC_NONE)
@@ -216,7 +222,8 @@ def main():
         kstats[path] = {k: Q.kernel_stats(ctx, k) for k in Q.KERNEL_NAMES}
         Q.kernel_timing(ctx, False)
         results[path] = dict(seconds=el, steps_per_s=args.steps / el,
-                             cg_iters_per_solve=cg_total / max(cg_solves, 1))
+                             cg_iters_per_solve=cg_total / max(cg_solves, 1),
+                             cg_rtol=prm.cg_rtol)
         finals[path] = u
         log(path, results[path])
 

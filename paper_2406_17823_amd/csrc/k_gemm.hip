@@ -7,12 +7,14 @@
 // One launch carries up to GEMM_GROUP independent problems (the four penalty
 // pair terms of a CG matvec go out as one launch per step).
 //
-// Tiling: a 256-thread workgroup (4 wave64s in a 2 x 2 arrangement) owns a
-// BM x BN output tile, 128 x 128 when the launch has at least one such tile
-// per compute unit, else 64 x 64; each wave holds (BM/32) x (BN/32) MFMA
-// blocks of 16 x 16.  K is staged through LDS in slices of KT = 16 with two
-// LDS buffers: the next slice's global loads are issued into registers
-// before the current slice's MFMAs, so one barrier per slice suffices.  The
+// Tiling: a workgroup owns a BM x BN output tile, 128 x 128 (512 threads,
+// 2 x 4 wave64s) when the launch has at least one such tile per compute
+// unit, else 64 x 64 (256 threads, 2 x 2); each wave holds 16 x 16 MFMA
+// blocks.  K is staged through LDS in slices of KD = 32 (128-tiles) or 16
+// (64-tiles) rows with two LDS buffers: the next slice's global loads are
+// issued into registers before the current slice's MFMAs, so one barrier per
+// slice suffices, and the deeper slice gives the loads of the large tiles
+// twice the MFMA time to arrive.  The
 // loader picks the thread-to-element map from the operand's unit-stride
 // dimension so that global loads stay coalesced.
 // float64: v_mfma_f64_16x16x4_f64; float32: v_mfma_f32_16x16x4_f32 with
@@ -207,20 +209,24 @@ __device__ inline bf3 to_op<bf3>(double v) {
   return r;
 }
 
-// WGM x WGN waves per workgroup, each owning (BM / WGM) x (BN / WGN) outputs
-template <typename T, int BM, int BN, int WGM, int WGN>
+// WGM x WGN waves per workgroup, each owning (BM / WGM) x (BN / WGN) outputs;
+// K goes through LDS in slices of KD (16 or 32) rows, each consumed as
+// KD / 16 MFMA steps of 16: the float32 / bfloat16 partial sums stay 16 deep
+// and float64 MFMAs accumulate in k order, so KD changes no result bit
+template <typename T, int BM, int BN, int WGM, int WGN, int KD>
 __global__ __launch_bounds__(64 * WGM * WGN) void k_gemm(GemmK g) {
   if (g.skip && *g.skip) return;
   if (g.flop_ctr && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(g.flop_ctr, g.flops);
   constexpr int NTHR = 64 * WGM * WGN;
   constexpr int WTM = BM / WGM, WTN = BN / WGN;  // wave tile
   constexpr int FM = WTM / 16, FN = WTN / 16;    // 16 x 16 blocks per wave
-  constexpr int AL = BM * KT / NTHR, BL = BN * KT / NTHR;  // global loads per thread
+  constexpr int AL = BM * KD / NTHR, BL = BN * KD / NTHR;  // global loads per thread
   static_assert(BM == BN, "square tiles: the MFMA step takes one LDS pitch");
-  static_assert(AL * NTHR == BM * KT && BL * NTHR == BN * KT, "tile / thread mismatch");
+  static_assert(KD % KT == 0, "slices of whole MFMA steps");
+  static_assert(AL * NTHR == BM * KD && BL * NTHR == BN * KD, "tile / thread mismatch");
   constexpr int LDA = BM + PADM, LDB = BN + PADM;
-  __shared__ T As[2][KT][LDA];
-  __shared__ T Bs[2][KT][LDB];
+  __shared__ T As[2][KD][LDA];
+  __shared__ T Bs[2][KD][LDB];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -272,16 +278,16 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_gemm(GemmK g) {
 #pragma unroll
     for (int i = 0; i < AL; ++i) {
       const int idx = tid + NTHR * i;
-      const int mm = a_m_unit ? (idx % BM) : (idx / KT);
-      const int kk = a_m_unit ? (idx / BM) : (idx % KT);
+      const int mm = a_m_unit ? (idx % BM) : (idx / KD);
+      const int kk = a_m_unit ? (idx / BM) : (idx % KD);
       const int gm = m0 + mm, gk = k0 + kk;
       ra[i] = (gm < P.M && gk < kend) ? A[gm * P.sAm + gk * P.sAk] : 0.0;
     }
 #pragma unroll
     for (int i = 0; i < BL; ++i) {
       const int idx = tid + NTHR * i;
-      const int nn = b_n_unit ? (idx % BN) : (idx / KT);
-      const int kk = b_n_unit ? (idx / BN) : (idx % KT);
+      const int nn = b_n_unit ? (idx % BN) : (idx / KD);
+      const int kk = b_n_unit ? (idx / BN) : (idx % KD);
       const int gn = n0 + nn, gk = k0 + kk;
       rb[i] = (gn < P.N && gk < kend) ? B[gk * P.sBk + gn * P.sBn] : 0.0;
     }
@@ -290,15 +296,15 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_gemm(GemmK g) {
 #pragma unroll
     for (int i = 0; i < AL; ++i) {
       const int idx = tid + NTHR * i;
-      const int mm = a_m_unit ? (idx % BM) : (idx / KT);
-      const int kk = a_m_unit ? (idx / BM) : (idx % KT);
+      const int mm = a_m_unit ? (idx % BM) : (idx / KD);
+      const int kk = a_m_unit ? (idx / BM) : (idx % KD);
       As[buf][kk][mm] = to_op<T>(ra[i]);
     }
 #pragma unroll
     for (int i = 0; i < BL; ++i) {
       const int idx = tid + NTHR * i;
-      const int nn = b_n_unit ? (idx % BN) : (idx / KT);
-      const int kk = b_n_unit ? (idx / BN) : (idx % KT);
+      const int nn = b_n_unit ? (idx % BN) : (idx / KD);
+      const int kk = b_n_unit ? (idx / BN) : (idx % KD);
       Bs[buf][kk][nn] = to_op<T>(rb[i]);
     }
   };
@@ -309,10 +315,13 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_gemm(GemmK g) {
     __syncthreads();
   }
   int buf = 0;
-  for (int k0 = kbeg; k0 < kend; k0 += KT) {
-    const bool more = k0 + KT < kend;
-    if (more) gload(k0 + KT);
-    Mfma<T, FM, FN, LDA>::step(As[buf], Bs[buf], lane, wm * WTM, wn * WTN, acc);
+  for (int k0 = kbeg; k0 < kend; k0 += KD) {
+    const bool more = k0 + KD < kend;
+    if (more) gload(k0 + KD);
+#pragma unroll
+    for (int h = 0; h < KD / KT; ++h)
+      Mfma<T, FM, FN, LDA>::step(As[buf] + h * KT, Bs[buf] + h * KT, lane, wm * WTM, wn * WTN,
+                                 acc);
     if (more) sstore(buf ^ 1);
     __syncthreads();
     buf ^= 1;
@@ -447,10 +456,10 @@ int tuned_tile(Ctx &c, int np, const Gemm *q, int ngroups, const double *const *
       }
       HIPC(hipEventRecord(e0, c.stream));
       if (MT == 128)
-        hipLaunchKernelGGL((k_gemm<T, 128, 128, 2, 4>), dim3((unsigned)blocks), dim3(512), 0,
+        hipLaunchKernelGGL((k_gemm<T, 128, 128, 2, 4, 32>), dim3((unsigned)blocks), dim3(512), 0,
                            c.stream, g);
       else
-        hipLaunchKernelGGL((k_gemm<T, 64, 64, 2, 2>), dim3((unsigned)blocks), dim3(256), 0,
+        hipLaunchKernelGGL((k_gemm<T, 64, 64, 2, 2, 16>), dim3((unsigned)blocks), dim3(256), 0,
                            c.stream, g);
       HIPC(hipGetLastError());
       HIPC(hipEventRecord(e1, c.stream));
@@ -598,10 +607,11 @@ void launch_group(Ctx &c, int np, const Gemm *q, int ngroups, const int *group,
     HIPC(hipEventRecord(sev.first, c.stream));
   }
   if (big)
-    hipLaunchKernelGGL((k_gemm<T, 128, 128, 2, 4>), dim3((unsigned)blocks), dim3(512), 0, c.stream,
+    hipLaunchKernelGGL((k_gemm<T, 128, 128, 2, 4, 32>), dim3((unsigned)blocks), dim3(512), 0, c.stream,
                        g);
   else
-    hipLaunchKernelGGL((k_gemm<T, 64, 64, 2, 2>), dim3((unsigned)blocks), dim3(256), 0, c.stream, g);
+    hipLaunchKernelGGL((k_gemm<T, 64, 64, 2, 2, 16>), dim3((unsigned)blocks), dim3(256), 0, c.stream,
+                       g);
   HIPC(hipGetLastError());
   if (shape_rec) {
     HIPC(hipEventRecord(sev.second, c.stream));

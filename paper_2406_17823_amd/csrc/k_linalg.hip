@@ -137,7 +137,6 @@ __global__ __launch_bounds__(LA_THREADS) void k_qr(QRBatch batch) {
 
 // ---------------------------------------------------------------- blocked QR
 constexpr int QR_NB = 16;
-constexpr int QR_REG_THREADS = 512, QR_REG_WAVES = QR_REG_THREADS / 64;
 constexpr int QR_REG_ROWS = 4;  // rows per thread of the register-resident panel
 
 struct QrbDesc {
@@ -305,31 +304,40 @@ __device__ inline double wave_sum16(const double (&v)[16], int lane) {
   return d;
 }
 
-// register-resident panel for m <= QR_REG_ROWS * QR_REG_THREADS: thread tid
-// holds rows r = tid + QR_REG_THREADS * s of the panel's columns, so each column
-// step touches HBM/L2 not at all; the column loop is unrolled so that every
-// register index is a compile-time constant
-__global__ __launch_bounds__(QR_REG_THREADS) void k_qrb_panel_reg(QrbBatch B, int j0) {
+// register-resident panel for m <= QR_REG_ROWS * 64 NW: thread tid holds
+// rows r = tid + 64 NW s of the panel's columns, so a column step touches
+// HBM/L2 not at all.  One reduction per column: with x the entries of
+// column i below row c = j0 + i, the sums S[t] = sum_{r > c} x_r P[r][t]
+// over all 16 panel columns give |x|^2 (t = i), the products of the new
+// reflector v = (1, x / (alpha - beta)) with the trailing columns
+// (P[c][t] + S[t] / (alpha - beta), t > i) and with the earlier reflectors
+// (the same expression, t < i, for the next column of T); row c itself is
+// published through LDS by its owner.  Two barriers per column; the LDS
+// words read after the second are double-buffered by column parity.
+// Register columns are selected with compile-time indices and a predicate,
+// never indexed by i.
+template <int NW>
+__global__ __launch_bounds__(64 * NW) void k_qrb_panel_reg(QrbBatch B, int j0) {
+  constexpr int NT = 64 * NW;
   const QrbDesc &D = B.d[blockIdx.x];
   const int m = D.m, k = D.k;
   const int jb = min(QR_NB, k - j0);
-  if (jb <= 0 || m > QR_REG_ROWS * QR_REG_THREADS) return;
+  if (jb <= 0 || m > QR_REG_ROWS * NT) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  __shared__ double sh[QR_REG_WAVES][QR_NB + 1];
-  __shared__ double red[QR_NB + 2];
+  __shared__ double sh[NW][QR_NB];
+  __shared__ double red[2][QR_NB];
+  __shared__ double rowc[2][QR_NB];
   __shared__ double T[QR_NB][QR_NB + 1];
   double P[QR_REG_ROWS][QR_NB];
 #pragma unroll
   for (int s = 0; s < QR_REG_ROWS; ++s) {
-    const int r = tid + QR_REG_THREADS * s;
+    const int r = tid + NT * s;
 #pragma unroll
     for (int t = 0; t < QR_NB; ++t)
       P[s][t] = (r >= j0 && r < m && t < jb) ? D.W[(int64_t)(j0 + t) * m + r] : 0.0;
   }
-  // column loop (not unrolled): register columns are selected with
-  // compile-time indices and a predicate, never indexed by i
   for (int i = 0; i < jb; ++i) {
-    const int c = j0 + i;
+    const int c = j0 + i, bf = i & 1;
     double pc[QR_REG_ROWS];
 #pragma unroll
     for (int s = 0; s < QR_REG_ROWS; ++s) {
@@ -338,52 +346,19 @@ __global__ __launch_bounds__(QR_REG_THREADS) void k_qrb_panel_reg(QrbBatch B, in
       for (int t = 0; t < QR_NB; ++t)
         if (t == i) pc[s] = P[s][t];
     }
-    // squared norm below the diagonal; the owner of row c publishes alpha
-    double part = 0.0;
-#pragma unroll
-    for (int s = 0; s < QR_REG_ROWS; ++s) {
-      const int r = tid + QR_REG_THREADS * s;
-      if (r > c && r < m) part += pc[s] * pc[s];
-      if (r == c) red[QR_NB + 1] = pc[s];
-    }
-    part = wave_sum(part);
-    if (lane == 0) sh[wave][QR_NB] = part;
-    __syncthreads();
-    if (tid == 0) {
-      double s2 = 0.0;
-      for (int w = 0; w < QR_REG_WAVES; ++w) s2 += sh[w][QR_NB];
-      red[QR_NB] = s2;
-    }
-    __syncthreads();
-    const double xnorm2 = red[QR_NB];
-    const double alpha = red[QR_NB + 1];
-    double tau = 0.0, beta = alpha, sc = 0.0;
-    if (xnorm2 > 0.0) {
-      beta = -copysign(sqrt(alpha * alpha + xnorm2), alpha);
-      tau = (beta - alpha) / beta;
-      sc = 1.0 / (alpha - beta);
-    }
-    // reflector into column i (beta on the diagonal), dots with the other columns
     double d[QR_NB];
 #pragma unroll
     for (int t = 0; t < QR_NB; ++t) d[t] = 0.0;
-    double vr[QR_REG_ROWS];
 #pragma unroll
     for (int s = 0; s < QR_REG_ROWS; ++s) {
-      const int r = tid + QR_REG_THREADS * s;
-      double v = 0.0, nv = pc[s];
-      if (r == c) {
-        v = 1.0;
-        nv = beta;
-      } else if (r > c && r < m) {
-        v = pc[s] * sc;
-        nv = v;
-      }
-      vr[s] = v;
+      const int r = tid + NT * s;
+      if (r > c && r < m) {
 #pragma unroll
-      for (int t = 0; t < QR_NB; ++t) {
-        if (t == i) P[s][t] = nv;
-        else d[t] += v * P[s][t];
+        for (int t = 0; t < QR_NB; ++t) d[t] += pc[s] * P[s][t];
+      }
+      if (r == c) {
+#pragma unroll
+        for (int t = 0; t < QR_NB; ++t) rowc[bf][t] = P[s][t];
       }
     }
     static_assert(QR_NB == 16, "wave_sum16 reduces 16 columns");
@@ -392,34 +367,49 @@ __global__ __launch_bounds__(QR_REG_THREADS) void k_qrb_panel_reg(QrbBatch B, in
       if ((lane & 3) == 0) sh[wave][lane >> 2] = sum;
     }
     __syncthreads();
-    if (tid < jb) {
+    if (tid < QR_NB) {
       double s2 = 0.0;
-      for (int w = 0; w < QR_REG_WAVES; ++w) s2 += sh[w][tid];
-      red[tid] = s2;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) s2 += sh[w][tid];
+      red[bf][tid] = s2;
     }
     __syncthreads();
-    // H_c on the panel's trailing columns
+    const double xnorm2 = red[bf][i];
+    const double alpha = rowc[bf][i];
+    double tau = 0.0, beta = alpha, sc = 0.0;
+    if (xnorm2 > 0.0) {
+      beta = -copysign(sqrt(alpha * alpha + xnorm2), alpha);
+      tau = (beta - alpha) / beta;
+      sc = 1.0 / (alpha - beta);
+    }
+    // tau (v^T column t) for the trailing columns
+    double w[QR_NB];
 #pragma unroll
-    for (int t = 0; t < QR_NB; ++t) {
-      if (t > i && t < jb) {
-        const double f = tau * red[t];
+    for (int t = 0; t < QR_NB; ++t) w[t] = tau * (rowc[bf][t] + sc * red[bf][t]);
 #pragma unroll
-        for (int s = 0; s < QR_REG_ROWS; ++s) P[s][t] -= f * vr[s];
+    for (int s = 0; s < QR_REG_ROWS; ++s) {
+      const int r = tid + NT * s;
+      if (r < c || r >= m) continue;
+      const double v = (r == c) ? 1.0 : pc[s] * sc;
+#pragma unroll
+      for (int t = 0; t < QR_NB; ++t) {
+        if (t == i) P[s][t] = (r == c) ? beta : v;
+        else if (t > i && t < jb) P[s][t] -= w[t] * v;
       }
     }
-    // T[0:i, i] = -tau T[0:i, 0:i] (V_{0:i}^T v_c), T[i][i] = tau
+    // T[0:i, i] = -tau T[0:i, 0:i] (V_{0:i}^T v), T[i][i] = tau
     if (tid < i) {
       double s2 = 0.0;
-      for (int u = tid; u < i; ++u) s2 += T[tid][u] * red[u];
+      for (int u = tid; u < i; ++u) s2 += T[tid][u] * (rowc[bf][u] + sc * red[bf][u]);
       T[tid][i] = -tau * s2;
     }
     if (tid == 0) T[i][i] = tau;
-    __syncthreads();
   }
+  __syncthreads();
   // write back: W panel (R entries and reflectors), V (unit diagonal, zeros above), T
 #pragma unroll
   for (int s = 0; s < QR_REG_ROWS; ++s) {
-    const int r = tid + QR_REG_THREADS * s;
+    const int r = tid + NT * s;
     if (r < j0 || r >= m) continue;
 #pragma unroll
     for (int t = 0; t < QR_NB; ++t) {
@@ -430,7 +420,7 @@ __global__ __launch_bounds__(QR_REG_THREADS) void k_qrb_panel_reg(QrbBatch B, in
       }
     }
   }
-  for (int e = tid; e < QR_NB * QR_NB; e += QR_REG_THREADS) {
+  for (int e = tid; e < QR_NB * QR_NB; e += NT) {
     const int t = e / QR_NB, u = e % QR_NB;
     D.T[e] = (t < jb && u < jb && u >= t) ? T[t][u] : 0.0;
   }
@@ -548,8 +538,12 @@ void qr_blocked(Ctx &c, int cnt, const ConstMatView *A, const MatView *Q, const 
   for (int j0 = 0; j0 < kmax; j0 += QR_NB) {
     int mmax = 0;
     for (int i = 0; i < cnt; ++i) mmax = std::max(mmax, b.d[i].m);
-    if (mmax <= QR_REG_ROWS * QR_REG_THREADS)
-      hipLaunchKernelGGL(k_qrb_panel_reg, dim3(cnt), dim3(QR_REG_THREADS), 0, c.stream, b, j0);
+    if (mmax <= QR_REG_ROWS * 128)
+      hipLaunchKernelGGL(k_qrb_panel_reg<2>, dim3(cnt), dim3(128), 0, c.stream, b, j0);
+    else if (mmax <= QR_REG_ROWS * 256)
+      hipLaunchKernelGGL(k_qrb_panel_reg<4>, dim3(cnt), dim3(256), 0, c.stream, b, j0);
+    else if (mmax <= QR_REG_ROWS * 512)
+      hipLaunchKernelGGL(k_qrb_panel_reg<8>, dim3(cnt), dim3(512), 0, c.stream, b, j0);
     else
       hipLaunchKernelGGL(k_qrb_panel, dim3(cnt), dim3(LA_THREADS), 0, c.stream, b, j0);
     {

@@ -278,6 +278,330 @@ __global__ __launch_bounds__(NT) void k_sv_round(SvBatch B, int round) {
   }
 }
 
+// ---- Gram-matrix form of a block-pair round (blocked matrices)
+//
+// Same outer schedule, same rotation angles and the same threshold test as
+// k_sv_round, organised around the Gram matrix of the block pair: its NC
+// column slots (m rows, zero-padded to a multiple of 16 rows; empty slots
+// are zero columns and never rotate) are staged row-major in LDS, G = X^T X
+// is formed with float64 MFMAs, and the inner sweep runs on G as two-sided
+// Jacobi: the NC/2 disjoint rotations of an inner round act on G as
+// G <- R^T G R, 2 x 2 block by 2 x 2 block, with the rotated diagonal in the
+// stable form a_pp - t a_pq, a_qq + t a_pq (the off-diagonal of the pair set
+// to zero).  These are the column inner products the one-sided method would
+// recompute after each rotation.  The accumulated rotation J (NC x NC) is
+// applied to the columns, and to V, once per round with MFMAs.  An inner
+// round costs O(NC^2) LDS work instead of O(m NC), so a round is bound by
+// the two m x NC x NC products rather than by 31 dependent column passes.
+constexpr int SVG_THREADS = 512;
+constexpr int SVG_WAVES = SVG_THREADS / 64;
+// V slots held in registers per thread while the sweep runs (the V loads are
+// issued before the Gram product and consumed after it)
+constexpr int SVG_VREG = 40;
+
+typedef double d4v __attribute__((ext_vector_type(4)));
+
+// rows x NC (row-major, leading dimension NC + 1, rows a multiple of 16)
+// <- itself times J (NC x NC, same layout); each wave owns whole 16-row
+// blocks, reads them completely before overwriting them
+template <int NC>
+__device__ void svg_apply_j(double *Xs, const double *J, int rows, int wave, int lane) {
+  constexpr int LD = NC + 1, NT16 = NC / 16;
+  for (int rb = wave; rb < rows / 16; rb += SVG_WAVES) {
+    d4v acc[NT16];
+#pragma unroll
+    for (int t = 0; t < NT16; ++t) acc[t] = d4v{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k0 = 0; k0 < NC; k0 += 4) {
+      const int kk = k0 + (lane >> 4);
+      // A[i][k] = X[16 rb + i][k]: lane supplies i = lane % 16, k = lane / 16
+      const double a = Xs[(rb * 16 + (lane & 15)) * LD + kk];
+#pragma unroll
+      for (int t = 0; t < NT16; ++t) {
+        const double b = J[kk * LD + t * 16 + (lane & 15)];
+        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[t], 0, 0, 0);
+      }
+    }
+    // D register r is row 4 r + lane / 16, column lane % 16
+#pragma unroll
+    for (int t = 0; t < NT16; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        Xs[(rb * 16 + 4 * r + (lane >> 4)) * LD + t * 16 + (lane & 15)] = acc[t][r];
+  }
+}
+
+// column slots of a column-major m x n matrix (slot c holds column colidx[c],
+// -1: zero) into rows 0..mp of the row-major LDS block, rows >= m zero; the
+// global loads go out SVG_UNROLL at a time before their LDS stores
+constexpr int SVG_UNROLL = 8;
+template <int NC>
+__device__ void svg_stage(double *Xs, const double *src, int m, int mp, const int *colidx,
+                          int tid) {
+  constexpr int LD = NC + 1;
+  const int total = mp * NC;
+  for (int base = tid; base < total; base += SVG_UNROLL * SVG_THREADS) {
+    double v[SVG_UNROLL];
+#pragma unroll
+    for (int u = 0; u < SVG_UNROLL; ++u) {
+      const int idx = base + u * SVG_THREADS;
+      v[u] = 0.0;
+      if (idx < total) {
+        const int c = idx / mp, i = idx - c * mp;
+        const int gc = colidx[c];
+        if (gc >= 0 && i < m) v[u] = src[(int64_t)gc * m + i];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < SVG_UNROLL; ++u) {
+      const int idx = base + u * SVG_THREADS;
+      if (idx < total) {
+        const int c = idx / mp, i = idx - c * mp;
+        Xs[i * LD + c] = v[u];
+      }
+    }
+  }
+}
+
+template <int NC>
+__global__ __launch_bounds__(SVG_THREADS) void k_svg_round(SvBatch B, int round) {
+  static_assert(NC == 16 || NC == 32, "block pairs of 16 or 32 column slots");
+  constexpr int LD = NC + 1, P = NC / 2, NT16 = NC / 16;
+  extern __shared__ double lds[];
+  int mi = 0;
+  for (int i = 1; i < B.count; ++i)
+    if ((int)blockIdx.x >= B.d[i].first) mi = i;
+  const SvMat &D = B.d[mi];
+  const int tw = (int)blockIdx.x - D.first;
+  const int m = D.m, n = D.n, b = D.b;
+  const int mp = (m + 15) & ~15;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  __shared__ int colidx[NC];
+  __shared__ double rc[P], rs[P], rt[P];
+  __shared__ int rp[P], rq[P], rf[P];
+  __shared__ int rot;
+  if (tid == 0) {
+    int o = 0;
+    if (D.single) {
+      for (int c = 0; c < n; ++c) colidx[o++] = c;
+    } else {
+      const int nbp = D.nb + (D.nb & 1);
+      int blk[2] = {0, 0};
+      if (tw == 0) {
+        blk[0] = nbp - 1;
+        blk[1] = round;
+      } else {
+        blk[0] = (round + tw) % (nbp - 1);
+        blk[1] = (round - tw + nbp - 1) % (nbp - 1);
+      }
+      if (blk[0] > blk[1]) {
+        const int x = blk[0];
+        blk[0] = blk[1];
+        blk[1] = x;
+      }
+      for (int k = 0; k < 2; ++k)
+        if (blk[k] < D.nb)
+          for (int c = blk[k] * b; c < min(blk[k] * b + b, n); ++c) colidx[o++] = c;
+    }
+    while (o < NC) colidx[o++] = -1;
+    rot = 0;
+  }
+  double *Xs = lds;
+  double *G = Xs + (int64_t)mp * LD;
+  double *J = G + NC * LD;
+  double *Gp = J + NC * LD;
+  const double fl = 4.0 * sqrt((double)m) * SV_EPS;
+  const double floor2 = fl * fl * *D.fro2;
+  const double tol2 = (double)m * SV_EPS * SV_EPS;
+  __syncthreads();
+  // V slots of the pair: loads issued now into registers when they fit
+  const int np16 = (n + 15) & ~15;
+  const bool vreg = D.accumulate && np16 * NC <= SVG_VREG * SVG_THREADS;
+  double vr[SVG_VREG];
+#pragma unroll
+  for (int u = 0; u < SVG_VREG; ++u) {
+    const int idx = tid + u * SVG_THREADS;
+    vr[u] = 0.0;
+    if (vreg && idx < np16 * NC) {
+      const int c = idx / np16, i = idx - c * np16;
+      const int gc = colidx[c];
+      if (gc >= 0 && i < n) vr[u] = D.V[(int64_t)gc * n + i];
+    }
+  }
+  svg_stage<NC>(Xs, D.W, m, mp, colidx, tid);
+  for (int idx = tid; idx < NC * NC; idx += SVG_THREADS) {
+    const int i = idx / NC, j = idx - i * NC;
+    J[i * LD + j] = (i == j) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  // G = X^T X: 16 x 16 tiles of the upper block triangle (1 or 3), the rows
+  // split in two halves: waves 0.. take the first half into G, waves 4.. the
+  // second into Gp, then G += Gp (fixed order)
+  {
+    constexpr int NTILE = NT16 * (NT16 + 1) / 2;
+    const int half = wave / 4, wt = wave % 4;
+    int ta = -1, tb = -1;
+    if (wt < NTILE) {
+      ta = (wt == 2) ? 1 : 0;
+      tb = (wt == 0) ? 0 : 1;
+    }
+    const int kh = (mp / 16) * 8;  // first half: rows [0, kh), a multiple of 8
+    const int klo = half ? kh : 0, khi = half ? mp : kh;
+    if (ta >= 0) {
+      // two accumulators (rows k0..k0+3 and k0+4..k0+7 of each 8) so that
+      // consecutive MFMAs do not wait on each other
+      d4v acc = d4v{0.0, 0.0, 0.0, 0.0}, acc2 = d4v{0.0, 0.0, 0.0, 0.0};
+      for (int k0 = klo; k0 < khi; k0 += 8) {
+        const int k = k0 + (lane >> 4);
+        // A[i][k] = X[k][16 ta + i], B[k][j] = X[k][16 tb + j]
+        const double a = Xs[k * LD + ta * 16 + (lane & 15)];
+        const double bb = Xs[k * LD + tb * 16 + (lane & 15)];
+        const double a2 = Xs[(k + 4) * LD + ta * 16 + (lane & 15)];
+        const double bb2 = Xs[(k + 4) * LD + tb * 16 + (lane & 15)];
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, acc, 0, 0, 0);
+        acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(a2, bb2, acc2, 0, 0, 0);
+      }
+      acc += acc2;
+      // diagonal tiles keep their upper triangle, mirrored: G exactly symmetric
+      double *Gh = half ? Gp : G;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gi = ta * 16 + 4 * r + (lane >> 4), gj = tb * 16 + (lane & 15);
+        if (ta != tb || gi <= gj) {
+          Gh[gi * LD + gj] = acc[r];
+          Gh[gj * LD + gi] = acc[r];
+        }
+      }
+    }
+  }
+  __syncthreads();
+  for (int idx = tid; idx < NC * NC; idx += SVG_THREADS) {
+    const int i = idx / NC, j = idx - i * NC;
+    G[i * LD + j] += Gp[i * LD + j];
+  }
+  __syncthreads();
+  // one inner sweep: NC - 1 rounds of P disjoint pairs (round-robin)
+  for (int r = 0; r < NC - 1; ++r) {
+    if (tid < P) {
+      int p, q;
+      if (tid == 0) {
+        p = NC - 1;
+        q = r;
+      } else {
+        p = (r + tid) % (NC - 1);
+        q = (r - tid + NC - 1) % (NC - 1);
+      }
+      if (p > q) {
+        const int x = p;
+        p = q;
+        q = x;
+      }
+      const double al = G[p * LD + p], be = G[q * LD + q], ga = G[p * LD + q];
+      double cs = 1.0, sn = 0.0, tt = 0.0;
+      int f = 0;
+      // |cos| > tol without a square root (al, be > 0 past the floor test)
+      if (ga != 0.0 && al > floor2 && be > floor2 && ga * ga > tol2 * (al * be)) {
+        const double zeta = (be - al) / (2.0 * ga);
+        tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        cs = 1.0 / sqrt(1.0 + tt * tt);
+        sn = cs * tt;
+        f = 1;
+        atomicAdd(&rot, 1);
+      }
+      rp[tid] = p;
+      rq[tid] = q;
+      rc[tid] = cs;
+      rs[tid] = sn;
+      rt[tid] = tt;
+      rf[tid] = f;
+    }
+    __syncthreads();
+    // G <- R^T G R: thread per 2 x 2 block (pair a, pair b), a <= b, which
+    // also writes the mirrored block; blocks are disjoint
+    for (int u = tid; u < P * P; u += SVG_THREADS) {
+      const int a = u / P, c = u - a * P;
+      if (a > c || !(rf[a] | rf[c])) continue;
+      const int pa = rp[a], qa = rq[a];
+      if (a == c) {
+        const double al = G[pa * LD + pa], be = G[qa * LD + qa], ga = G[pa * LD + qa];
+        G[pa * LD + pa] = al - rt[a] * ga;
+        G[qa * LD + qa] = be + rt[a] * ga;
+        G[pa * LD + qa] = 0.0;
+        G[qa * LD + pa] = 0.0;
+        continue;
+      }
+      const int pb = rp[c], qb = rq[c];
+      const double ca = rc[a], sa = rs[a], cb = rc[c], sb = rs[c];
+      const double g11 = G[pa * LD + pb], g12 = G[pa * LD + qb];
+      const double g21 = G[qa * LD + pb], g22 = G[qa * LD + qb];
+      // columns (pb, qb) rotated, then rows (pa, qa)
+      const double h11 = cb * g11 - sb * g12, h12 = sb * g11 + cb * g12;
+      const double h21 = cb * g21 - sb * g22, h22 = sb * g21 + cb * g22;
+      const double n11 = ca * h11 - sa * h21, n21 = sa * h11 + ca * h21;
+      const double n12 = ca * h12 - sa * h22, n22 = sa * h12 + ca * h22;
+      G[pa * LD + pb] = n11;
+      G[pb * LD + pa] = n11;
+      G[pa * LD + qb] = n12;
+      G[qb * LD + pa] = n12;
+      G[qa * LD + pb] = n21;
+      G[pb * LD + qa] = n21;
+      G[qa * LD + qb] = n22;
+      G[qb * LD + qa] = n22;
+    }
+    // J <- J R
+    for (int u = tid; u < NC * P; u += SVG_THREADS) {
+      const int i = u / P, a = u - i * P;
+      if (!rf[a]) continue;
+      const int pa = rp[a], qa = rq[a];
+      const double x = J[i * LD + pa], y = J[i * LD + qa];
+      J[i * LD + pa] = rc[a] * x - rs[a] * y;
+      J[i * LD + qa] = rs[a] * x + rc[a] * y;
+    }
+    __syncthreads();
+  }
+  const int total = rot;
+  if (total == 0) return;  // J = I: columns and V unchanged
+  svg_apply_j<NC>(Xs, J, mp, wave, lane);
+  __syncthreads();
+  for (int idx = tid; idx < NC * m; idx += SVG_THREADS) {
+    const int c = idx / m, i = idx - c * m;
+    const int gc = colidx[c];
+    if (gc >= 0) D.W[(int64_t)gc * m + i] = Xs[i * LD + c];
+  }
+  if (D.accumulate) {
+    // V[:, cols] (n x NC) <- V[:, cols] J through the same LDS rows (n <= m)
+    __syncthreads();
+    if (vreg) {
+#pragma unroll
+      for (int u = 0; u < SVG_VREG; ++u) {
+        const int idx = tid + u * SVG_THREADS;
+        if (idx < np16 * NC) {
+          const int c = idx / np16, i = idx - c * np16;
+          Xs[i * LD + c] = vr[u];
+        }
+      }
+    } else {
+      svg_stage<NC>(Xs, D.V, n, np16, colidx, tid);
+    }
+    __syncthreads();
+    svg_apply_j<NC>(Xs, J, np16, wave, lane);
+    __syncthreads();
+    for (int idx = tid; idx < NC * n; idx += SVG_THREADS) {
+      const int c = idx / n, i = idx - c * n;
+      const int gc = colidx[c];
+      if (gc >= 0) D.V[(int64_t)gc * n + i] = Xs[i * LD + c];
+    }
+  }
+  if (tid == 0) atomicAdd(D.count, total);
+}
+
+// LDS of a k_svg_round<nc> launch for matrices of at most m rows: the
+// row-major block, G, J and the second half's G
+size_t svg_lds(int nc, int m) {
+  const size_t mp = (size_t)((m + 15) & ~15);
+  return (mp * (nc + 1) + 3 * (size_t)nc * (nc + 1)) * sizeof(double);
+}
+
 // singular values, descending order, outputs
 __global__ __launch_bounds__(SV_THREADS) void k_sv_finish(SvBatch B) {
   extern __shared__ double lds[];
@@ -329,7 +653,8 @@ size_t sv_lds_limit(Ctx &c) {
   int maxsh = 0;
   HIPC(hipDeviceGetAttribute(&maxsh, hipDeviceAttributeMaxSharedMemoryPerBlock, c.device));
   size_t stat = 0;
-  const void *kerns[2] = {(const void *)k_sv_round<SV_THREADS>, (const void *)k_sv_round<SVB_THREADS>};
+  const void *kerns[4] = {(const void *)k_sv_round<SV_THREADS>, (const void *)k_sv_round<SVB_THREADS>,
+                          (const void *)k_svg_round<32>, (const void *)k_svg_round<16>};
   for (const void *k : kerns) {
     hipFuncAttributes fa;
     HIPC(hipFuncGetAttributes(&fa, k));
@@ -491,6 +816,15 @@ void svd_jacobi_group(Ctx &c, int count, const ConstMatView *A, const MatView *U
     SvBatch B{};
     B.count = cnt;
     int64_t ws = 0;
+    // blocked matrices take the Gram-matrix rounds when the tallest of the
+    // launch fits LDS with 32 (else 16) column slots
+    int gram_nc = 0;
+    if (!single_group) {
+      int mmax = 0;
+      for (int i = 0; i < cnt; ++i) mmax = std::max(mmax, A[base + i].rows);
+      if (svg_lds(32, mmax) <= SV_LDS_LIMIT) gram_nc = 32;
+      else if (svg_lds(16, mmax) <= SV_LDS_LIMIT) gram_nc = 16;
+    }
     size_t lds_round = 0, lds_fin = 0;
     for (int i = 0; i < cnt; ++i) {
       const ConstMatView &a = A[base + i];
@@ -517,11 +851,13 @@ void svd_jacobi_group(Ctx &c, int count, const ConstMatView *A, const MatView *U
         c.check_range(S[base + i], 0, n - 1, 8, "svd S");
       }
       // one block pair when the whole matrix fits LDS, else blocks of SV_BQ
+      // (Gram rounds: NC / 2 for the whole launch)
       const bool one = n <= SV_SINGLE && (size_t)n * (m + n) * 8 <= SV_LDS_LIMIT;
       if (one != single_group) fail(QTT_E_ARG, "svd_batch: block-pair grouping");
-      int b = one ? (n + 1) / 2 : SV_BQ;
-      while (!one && b > 4 && (size_t)(2 * b) * (m + 2 * b) * 8 > SV_LDS_LIMIT) b /= 2;
-      if (!one && (size_t)(2 * b) * (m + 2 * b) * 8 > SV_LDS_LIMIT)
+      int b = one ? (n + 1) / 2 : (gram_nc ? gram_nc / 2 : SV_BQ);
+      while (!one && !gram_nc && b > 4 && (size_t)(2 * b) * (m + 2 * b) * 8 > SV_LDS_LIMIT)
+        b /= 2;
+      if (!one && !gram_nc && (size_t)(2 * b) * (m + 2 * b) * 8 > SV_LDS_LIMIT)
         fail(QTT_E_UNSUPPORTED, "svd_batch: matrix too tall");
       SvMat &d = B.d[i];
       d.A = a.p;
@@ -543,7 +879,7 @@ void svd_jacobi_group(Ctx &c, int count, const ConstMatView *A, const MatView *U
       d.vcs = V[base + i].cs;
       ws += (int64_t)m * n + (int64_t)n * n + 1;
       const int nc = d.single ? n : 2 * b;
-      lds_round = std::max(lds_round, (size_t)nc * (m + nc) * 8);
+      lds_round = std::max(lds_round, gram_nc ? svg_lds(gram_nc, m) : (size_t)nc * (m + nc) * 8);
       lds_fin = std::max(lds_fin, (size_t)(2 * n + 4) * 8);
     }
     double *Wb = c.buf("svd_work", ws);
@@ -588,6 +924,12 @@ void svd_jacobi_group(Ctx &c, int count, const ConstMatView *A, const MatView *U
         if (single_group)
           hipLaunchKernelGGL(k_sv_round<SV_THREADS>, dim3(wg), dim3(SV_THREADS), lds_round,
                              c.stream, R, r);
+        else if (gram_nc == 32)
+          hipLaunchKernelGGL(k_svg_round<32>, dim3(wg), dim3(SVG_THREADS), lds_round, c.stream,
+                             R, r);
+        else if (gram_nc == 16)
+          hipLaunchKernelGGL(k_svg_round<16>, dim3(wg), dim3(SVG_THREADS), lds_round, c.stream,
+                             R, r);
         else
           hipLaunchKernelGGL(k_sv_round<SVB_THREADS>, dim3(wg), dim3(SVB_THREADS), lds_round,
                              c.stream, R, r);
@@ -601,8 +943,8 @@ void svd_jacobi_group(Ctx &c, int count, const ConstMatView *A, const MatView *U
       HIPC(hipMemsetAsync(cnt_dev, 0, cnt * sizeof(int), c.stream));
     }
     if (sv_verbose())
-      std::fprintf(stderr, "[qtt] svd %dx%d (+%d) sweeps %d rounds/sweep %d\n", B.d[0].m, B.d[0].n,
-                   cnt - 1, sweeps_run, rounds);
+      std::fprintf(stderr, "[qtt] svd %dx%d (+%d) sweeps %d rounds/sweep %d gram %d\n", B.d[0].m,
+                   B.d[0].n, cnt - 1, sweeps_run, rounds, gram_nc);
     hipLaunchKernelGGL(k_sv_finish, dim3(cnt), dim3(SV_THREADS), lds_fin, c.stream, B);
     HIPC(hipGetLastError());
   }

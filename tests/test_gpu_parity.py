@@ -150,6 +150,22 @@ def test_truncate_four_term_sum_blocked_qr(Q, ctx, chi_in, chi):
     assert abs(disc - disc_ref) <= 1e-9 * max(disc_ref, 1e-30) + 1e-28
 
 
+def test_truncate_wide_centre_sixteen_slot_gram_rounds(Q, ctx):
+    """Four-term sum of bond-150 states on 10 sites: centre bonds of 600 give
+    a 600 x 600 Jacobi problem after the QR step (wide unfolding, so V is
+    accumulated), too tall for 32 column slots in LDS: the Gram-matrix block
+    rounds run with 16 slots over an odd number (75) of 8-column blocks."""
+    n = 10
+    xs = [rand(I.canonical_bonds(n, 150), 60 + t) for t in range(4)]
+    y = M.add([1.0, 0.5, -0.25, 0.75], xs)
+    d = dev(Q, y)
+    disc = Q.truncate(ctx, d, 200, 1e-12)
+    ref, disc_ref = M.truncate(y, 200, 1e-12)
+    assert d.bonds == M.bonds(ref)
+    assert M.rel_l2(d.cores(), ref) < TOL
+    assert abs(disc - disc_ref) <= 1e-9 * max(disc_ref, 1e-30) + 1e-28
+
+
 # ---------------------------------------------------------------- input compression
 def test_from_dense_matches_tt_svd(Q, ctx):
     n, chi = 6, 12
