@@ -29,6 +29,7 @@
 #include "qtt_internal.h"
 
 #include <cstdio>
+#include <type_traits>
 
 namespace qtt {
 
@@ -63,6 +64,7 @@ struct Prob {
   int64_t sCm, sCn, sCb1, sCb2;
   double alpha, beta;
   double *part;  // partial mode: part[ks][b][m][n]
+  int c32;  // result stored as float32 (operand storage is a template argument)
 };
 
 struct GemmK {
@@ -213,7 +215,11 @@ __device__ inline bf3 to_op<bf3>(double v) {
 // K goes through LDS in slices of KD (16 or 32) rows, each consumed as
 // KD / 16 MFMA steps of 16: the float32 / bfloat16 partial sums stay 16 deep
 // and float64 MFMAs accumulate in k order, so KD changes no result bit
-template <typename T, int BM, int BN, int WGM, int WGN, int KD>
+// SA, SB: storage types of A and B (float64, or float32 for the convection
+// networks of the mixed mode, with T = float); the operand words go through
+// registers in their storage type and are converted on the way into LDS
+template <typename T, int BM, int BN, int WGM, int WGN, int KD, typename SA = double,
+          typename SB = double>
 __global__ __launch_bounds__(64 * WGM * WGN) void k_gemm(GemmK g) {
   if (g.skip && *g.skip) return;
   if (g.flop_ctr && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(g.flop_ctr, g.flops);
@@ -262,8 +268,10 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_gemm(GemmK g) {
   const int m0 = (xcd ? (t / P.tn) : (t % P.tm)) * BM;
   const int n0 = (xcd ? (t % P.tn) : (t / P.tm)) * BN;
 
-  const double *A = P.A + b1 * P.sAb1 + b2 * P.sAb2;
-  const double *B = P.B + b1 * P.sBb1 + b2 * P.sBb2;
+  // element offsets into the operands' storage arrays
+  const int64_t aoff = b1 * P.sAb1 + b2 * P.sAb2, boff = b1 * P.sBb1 + b2 * P.sBb2;
+  const SA *Ap = reinterpret_cast<const SA *>(P.A);
+  const SB *Bp = reinterpret_cast<const SB *>(P.B);
   const bool a_m_unit = (P.sAm == 1);
   const bool b_n_unit = (P.sBn == 1);
 
@@ -273,7 +281,8 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_gemm(GemmK g) {
 #pragma unroll
     for (int j = 0; j < FN; ++j) acc[i][j] = d4v{0.0, 0.0, 0.0, 0.0};
 
-  double ra[AL], rb[BL];
+  SA ra[AL];
+  SB rb[BL];
   auto gload = [&](int k0) {
 #pragma unroll
     for (int i = 0; i < AL; ++i) {
@@ -281,7 +290,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_gemm(GemmK g) {
       const int mm = a_m_unit ? (idx % BM) : (idx / KD);
       const int kk = a_m_unit ? (idx / BM) : (idx % KD);
       const int gm = m0 + mm, gk = k0 + kk;
-      ra[i] = (gm < P.M && gk < kend) ? A[gm * P.sAm + gk * P.sAk] : 0.0;
+      ra[i] = (gm < P.M && gk < kend) ? Ap[aoff + gm * P.sAm + gk * P.sAk] : SA(0);
     }
 #pragma unroll
     for (int i = 0; i < BL; ++i) {
@@ -289,7 +298,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_gemm(GemmK g) {
       const int nn = b_n_unit ? (idx % BN) : (idx / KD);
       const int kk = b_n_unit ? (idx / BN) : (idx % KD);
       const int gn = n0 + nn, gk = k0 + kk;
-      rb[i] = (gn < P.N && gk < kend) ? B[gk * P.sBk + gn * P.sBn] : 0.0;
+      rb[i] = (gn < P.N && gk < kend) ? Bp[boff + gk * P.sBk + gn * P.sBn] : SB(0);
     }
   };
   auto sstore = [&](int buf) {
@@ -298,14 +307,14 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_gemm(GemmK g) {
       const int idx = tid + NTHR * i;
       const int mm = a_m_unit ? (idx % BM) : (idx / KD);
       const int kk = a_m_unit ? (idx / BM) : (idx % KD);
-      As[buf][kk][mm] = to_op<T>(ra[i]);
+      As[buf][kk][mm] = to_op<T>((double)ra[i]);
     }
 #pragma unroll
     for (int i = 0; i < BL; ++i) {
       const int idx = tid + NTHR * i;
       const int nn = b_n_unit ? (idx % BN) : (idx / KD);
       const int kk = b_n_unit ? (idx / BN) : (idx % KD);
-      Bs[buf][kk][nn] = to_op<T>(rb[i]);
+      Bs[buf][kk][nn] = to_op<T>((double)rb[i]);
     }
   };
 
@@ -343,10 +352,17 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_gemm(GemmK g) {
             const int64_t bidx = (int64_t)b2 * P.B1 + b1;
             P.part[(((int64_t)ks * P.B1 * P.B2 + bidx) * P.M + gm) * P.N + gn] = acc[i][j][r];
           } else {
-            double *cp = P.C + b1 * P.sCb1 + b2 * P.sCb2 + gm * P.sCm + gn * P.sCn;
+            const int64_t co = b1 * P.sCb1 + b2 * P.sCb2 + gm * P.sCm + gn * P.sCn;
             double v = P.alpha * acc[i][j][r];
-            if (P.beta != 0.0) v += P.beta * *cp;
-            *cp = v;
+            if (P.c32) {
+              float *cp = reinterpret_cast<float *>(P.C) + co;
+              if (P.beta != 0.0) v += P.beta * (double)*cp;
+              *cp = (float)v;
+            } else {
+              double *cp = P.C + co;
+              if (P.beta != 0.0) v += P.beta * *cp;
+              *cp = v;
+            }
           }
         }
       }
@@ -366,6 +382,7 @@ struct RedOut {
   int nsrc;
   RedSrc src[2];
   int64_t elem0;
+  int c32, x32;  // C / X stored as float32
 };
 struct RedK {
   int nout;
@@ -395,9 +412,13 @@ __global__ __launch_bounds__(256) void k_splitk_reduce(RedK R) {
     const int gm = (int)(r / O.N), gn = (int)(r % O.N);
     const int b1 = (int)(bidx % O.B1), b2 = (int)(bidx / O.B1);
     double v = O.alpha * s;
-    if (O.beta != 0.0)
-      v += O.beta * O.X[b1 * O.sXb1 + b2 * O.sXb2 + gm * O.sXm + gn * O.sXn];
-    O.C[b1 * O.sCb1 + b2 * O.sCb2 + gm * O.sCm + gn * O.sCn] = v;
+    if (O.beta != 0.0) {
+      const int64_t xo = b1 * O.sXb1 + b2 * O.sXb2 + gm * O.sXm + gn * O.sXn;
+      v += O.beta * (O.x32 ? (double)reinterpret_cast<const float *>(O.X)[xo] : O.X[xo]);
+    }
+    const int64_t co = b1 * O.sCb1 + b2 * O.sCb2 + gm * O.sCm + gn * O.sCn;
+    if (O.c32) reinterpret_cast<float *>(O.C)[co] = (float)v;
+    else O.C[co] = v;
   }
 }
 
@@ -407,19 +428,55 @@ void check_operands(Ctx &c, const Gemm &q) {
   span(lo, hi, q.K, q.sAk);
   span(lo, hi, q.B1, q.sAb1);
   span(lo, hi, q.B2, q.sAb2);
-  if (q.K > 0) c.check_range(q.A, lo, hi, sizeof(double), "gemm A");
+  if (q.K > 0) c.check_range(q.A, lo, hi, q.a32 ? sizeof(float) : sizeof(double), "gemm A");
   lo = hi = 0;
   span(lo, hi, q.K, q.sBk);
   span(lo, hi, q.N, q.sBn);
   span(lo, hi, q.B1, q.sBb1);
   span(lo, hi, q.B2, q.sBb2);
-  if (q.K > 0) c.check_range(q.B, lo, hi, sizeof(double), "gemm B");
+  if (q.K > 0) c.check_range(q.B, lo, hi, q.b32 ? sizeof(float) : sizeof(double), "gemm B");
   lo = hi = 0;
   span(lo, hi, q.M, q.sCm);
   span(lo, hi, q.N, q.sCn);
   span(lo, hi, q.B1, q.sCb1);
   span(lo, hi, q.B2, q.sCb2);
-  c.check_range(q.C, lo, hi, sizeof(double), "gemm C");
+  c.check_range(q.C, lo, hi, q.c32 ? sizeof(float) : sizeof(double), "gemm C");
+}
+
+// launch of one tile configuration with the operands' storage types (float32
+// storage only with float32 MFMAs; every problem of a launch shares them)
+template <typename T>
+void launch_tile(int MT, int sa, int sb, int64_t blocks, hipStream_t st, const GemmK &g) {
+  const dim3 grid((unsigned)blocks);
+  if constexpr (std::is_same<T, float>::value) {
+    if (MT == 128) {
+      if (sa && sb)
+        hipLaunchKernelGGL((k_gemm<T, 128, 128, 2, 4, 32, float, float>), grid, dim3(512), 0, st, g);
+      else if (sa)
+        hipLaunchKernelGGL((k_gemm<T, 128, 128, 2, 4, 32, float, double>), grid, dim3(512), 0, st,
+                           g);
+      else if (sb)
+        hipLaunchKernelGGL((k_gemm<T, 128, 128, 2, 4, 32, double, float>), grid, dim3(512), 0, st,
+                           g);
+      else
+        hipLaunchKernelGGL((k_gemm<T, 128, 128, 2, 4, 32>), grid, dim3(512), 0, st, g);
+    } else {
+      if (sa && sb)
+        hipLaunchKernelGGL((k_gemm<T, 64, 64, 2, 2, 16, float, float>), grid, dim3(256), 0, st, g);
+      else if (sa)
+        hipLaunchKernelGGL((k_gemm<T, 64, 64, 2, 2, 16, float, double>), grid, dim3(256), 0, st, g);
+      else if (sb)
+        hipLaunchKernelGGL((k_gemm<T, 64, 64, 2, 2, 16, double, float>), grid, dim3(256), 0, st, g);
+      else
+        hipLaunchKernelGGL((k_gemm<T, 64, 64, 2, 2, 16>), grid, dim3(256), 0, st, g);
+    }
+  } else {
+    if (sa || sb) fail(QTT_E_ARG, "gemm: float32 operand storage needs float32 MFMAs");
+    if (MT == 128)
+      hipLaunchKernelGGL((k_gemm<T, 128, 128, 2, 4, 32>), grid, dim3(512), 0, st, g);
+    else
+      hipLaunchKernelGGL((k_gemm<T, 64, 64, 2, 2, 16>), grid, dim3(256), 0, st, g);
+  }
 }
 
 // Result-invariant tile autotuning.  For a launch without split-K, whose
@@ -455,12 +512,7 @@ int tuned_tile(Ctx &c, int np, const Gemm *q, int ngroups, const double *const *
         return heuristic;
       }
       HIPC(hipEventRecord(e0, c.stream));
-      if (MT == 128)
-        hipLaunchKernelGGL((k_gemm<T, 128, 128, 2, 4, 32>), dim3((unsigned)blocks), dim3(512), 0,
-                           c.stream, g);
-      else
-        hipLaunchKernelGGL((k_gemm<T, 64, 64, 2, 2, 16>), dim3((unsigned)blocks), dim3(256), 0,
-                           c.stream, g);
+      launch_tile<T>(MT, q[0].a32, q[0].b32, blocks, c.stream, g);
       HIPC(hipGetLastError());
       HIPC(hipEventRecord(e1, c.stream));
       HIPC(hipEventSynchronize(e1));
@@ -492,6 +544,9 @@ void launch_group(Ctx &c, int np, const Gemm *q, int ngroups, const int *group,
       fail(QTT_E_ARG, "gemm group: bad output group");
     nsrc[group[i]] += 1;
   }
+  for (int i = 1; i < np; ++i)
+    if (q[i].a32 != q[0].a32 || q[i].b32 != q[0].b32)
+      fail(QTT_E_ARG, "gemm group: operand storage types must agree");
   int64_t part_need = 0;
   int64_t part_off[GEMM_GROUP] = {0};
   int keep[GEMM_GROUP];
@@ -540,6 +595,7 @@ void launch_group(Ctx &c, int np, const Gemm *q, int ngroups, const int *group,
       P.alpha = s.alpha;
       P.beta = s.beta;
       P.part = nullptr;
+      P.c32 = s.c32 ? 1 : 0;
       g.flops += 2.0 * s.M * (double)s.N * s.K * s.B1 * s.B2;
       const int64_t out_tiles = (int64_t)P.tm * P.tn * P.B1 * P.B2;
       P.ksplit = 1;
@@ -606,12 +662,7 @@ void launch_group(Ctx &c, int np, const Gemm *q, int ngroups, const int *group,
     sev.second = c.take_event();
     HIPC(hipEventRecord(sev.first, c.stream));
   }
-  if (big)
-    hipLaunchKernelGGL((k_gemm<T, 128, 128, 2, 4, 32>), dim3((unsigned)blocks), dim3(512), 0, c.stream,
-                       g);
-  else
-    hipLaunchKernelGGL((k_gemm<T, 64, 64, 2, 2, 16>), dim3((unsigned)blocks), dim3(256), 0, c.stream,
-                       g);
+  launch_tile<T>(MT, q[0].a32, q[0].b32, blocks, c.stream, g);
   HIPC(hipGetLastError());
   if (shape_rec) {
     HIPC(hipEventRecord(sev.second, c.stream));
@@ -660,9 +711,12 @@ void launch_group(Ctx &c, int np, const Gemm *q, int ngroups, const int *group,
           O.B2 = s.B2;
           O.alpha = s.alpha;
           O.beta = s.beta;
+          // an explicit beta input is float64; C doubles as X in C's type
+          O.c32 = s.c32 ? 1 : 0;
+          O.x32 = X[gi] ? 0 : O.c32;
           any = true;
         } else if (s.M != O.M || s.N != O.N || s.B1 != O.B1 || s.B2 != O.B2 || s.C != O.C ||
-                   s.alpha != O.alpha || s.beta != O.beta) {
+                   s.alpha != O.alpha || s.beta != O.beta || s.c32 != (O.c32 != 0)) {
           fail(QTT_E_ARG, "gemm group: summed problems must share the output");
         }
         O.src[O.nsrc].part = P.part;

@@ -137,7 +137,7 @@ __global__ __launch_bounds__(LA_THREADS) void k_qr(QRBatch batch) {
 
 // ---------------------------------------------------------------- blocked QR
 constexpr int QR_NB = 16;
-constexpr int QR_REG_ROWS = 4;  // rows per thread of the register-resident panel
+constexpr int QR_REG_MAXROWS = 4;  // rows per thread of the register-resident panel, at most
 
 struct QrbDesc {
   const double *A;
@@ -304,7 +304,7 @@ __device__ inline double wave_sum16(const double (&v)[16], int lane) {
   return d;
 }
 
-// register-resident panel for m <= QR_REG_ROWS * 64 NW: thread tid holds
+// register-resident panel for m <= ROWS * 64 NW: thread tid holds
 // rows r = tid + 64 NW s of the panel's columns, so a column step touches
 // HBM/L2 not at all.  One reduction per column: with x the entries of
 // column i below row c = j0 + i, the sums S[t] = sum_{r > c} x_r P[r][t]
@@ -316,21 +316,23 @@ __device__ inline double wave_sum16(const double (&v)[16], int lane) {
 // words read after the second are double-buffered by column parity.
 // Register columns are selected with compile-time indices and a predicate,
 // never indexed by i.
-template <int NW>
+// (ROWS = 1, 2 or 4 with 8 waves: the per-thread work of a column step
+// scales with ROWS, so the panel of a short matrix spreads over the waves)
+template <int NW, int ROWS>
 __global__ __launch_bounds__(64 * NW) void k_qrb_panel_reg(QrbBatch B, int j0) {
   constexpr int NT = 64 * NW;
   const QrbDesc &D = B.d[blockIdx.x];
   const int m = D.m, k = D.k;
   const int jb = min(QR_NB, k - j0);
-  if (jb <= 0 || m > QR_REG_ROWS * NT) return;
+  if (jb <= 0 || m > ROWS * NT) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   __shared__ double sh[NW][QR_NB];
   __shared__ double red[2][QR_NB];
   __shared__ double rowc[2][QR_NB];
   __shared__ double T[QR_NB][QR_NB + 1];
-  double P[QR_REG_ROWS][QR_NB];
+  double P[ROWS][QR_NB];
 #pragma unroll
-  for (int s = 0; s < QR_REG_ROWS; ++s) {
+  for (int s = 0; s < ROWS; ++s) {
     const int r = tid + NT * s;
 #pragma unroll
     for (int t = 0; t < QR_NB; ++t)
@@ -338,9 +340,9 @@ __global__ __launch_bounds__(64 * NW) void k_qrb_panel_reg(QrbBatch B, int j0) {
   }
   for (int i = 0; i < jb; ++i) {
     const int c = j0 + i, bf = i & 1;
-    double pc[QR_REG_ROWS];
+    double pc[ROWS];
 #pragma unroll
-    for (int s = 0; s < QR_REG_ROWS; ++s) {
+    for (int s = 0; s < ROWS; ++s) {
       pc[s] = 0.0;
 #pragma unroll
       for (int t = 0; t < QR_NB; ++t)
@@ -350,7 +352,7 @@ __global__ __launch_bounds__(64 * NW) void k_qrb_panel_reg(QrbBatch B, int j0) {
 #pragma unroll
     for (int t = 0; t < QR_NB; ++t) d[t] = 0.0;
 #pragma unroll
-    for (int s = 0; s < QR_REG_ROWS; ++s) {
+    for (int s = 0; s < ROWS; ++s) {
       const int r = tid + NT * s;
       if (r > c && r < m) {
 #pragma unroll
@@ -387,7 +389,7 @@ __global__ __launch_bounds__(64 * NW) void k_qrb_panel_reg(QrbBatch B, int j0) {
 #pragma unroll
     for (int t = 0; t < QR_NB; ++t) w[t] = tau * (rowc[bf][t] + sc * red[bf][t]);
 #pragma unroll
-    for (int s = 0; s < QR_REG_ROWS; ++s) {
+    for (int s = 0; s < ROWS; ++s) {
       const int r = tid + NT * s;
       if (r < c || r >= m) continue;
       const double v = (r == c) ? 1.0 : pc[s] * sc;
@@ -408,7 +410,7 @@ __global__ __launch_bounds__(64 * NW) void k_qrb_panel_reg(QrbBatch B, int j0) {
   __syncthreads();
   // write back: W panel (R entries and reflectors), V (unit diagonal, zeros above), T
 #pragma unroll
-  for (int s = 0; s < QR_REG_ROWS; ++s) {
+  for (int s = 0; s < ROWS; ++s) {
     const int r = tid + NT * s;
     if (r < j0 || r >= m) continue;
 #pragma unroll
@@ -455,6 +457,7 @@ __global__ void k_qrb_finish(QrbBatch B) {
   for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < tq + tr;
        idx += (int64_t)gridDim.x * blockDim.x) {
     if (idx < tq) {
+      if (!D.Q) continue;  // R only
       const int i = (int)(idx % m), c = (int)(idx / m);
       const double s = (D.W[(int64_t)c * m + c] < 0.0) ? -1.0 : 1.0;
       D.Q[i * D.qrs + c * D.qcs] = s * D.Qw[idx];
@@ -538,12 +541,12 @@ void qr_blocked(Ctx &c, int cnt, const ConstMatView *A, const MatView *Q, const 
   for (int j0 = 0; j0 < kmax; j0 += QR_NB) {
     int mmax = 0;
     for (int i = 0; i < cnt; ++i) mmax = std::max(mmax, b.d[i].m);
-    if (mmax <= QR_REG_ROWS * 128)
-      hipLaunchKernelGGL(k_qrb_panel_reg<2>, dim3(cnt), dim3(128), 0, c.stream, b, j0);
-    else if (mmax <= QR_REG_ROWS * 256)
-      hipLaunchKernelGGL(k_qrb_panel_reg<4>, dim3(cnt), dim3(256), 0, c.stream, b, j0);
-    else if (mmax <= QR_REG_ROWS * 512)
-      hipLaunchKernelGGL(k_qrb_panel_reg<8>, dim3(cnt), dim3(512), 0, c.stream, b, j0);
+    if (mmax <= 512)
+      hipLaunchKernelGGL((k_qrb_panel_reg<8, 1>), dim3(cnt), dim3(512), 0, c.stream, b, j0);
+    else if (mmax <= 1024)
+      hipLaunchKernelGGL((k_qrb_panel_reg<8, 2>), dim3(cnt), dim3(512), 0, c.stream, b, j0);
+    else if (mmax <= 512 * QR_REG_MAXROWS)
+      hipLaunchKernelGGL((k_qrb_panel_reg<8, 4>), dim3(cnt), dim3(512), 0, c.stream, b, j0);
     else
       hipLaunchKernelGGL(k_qrb_panel, dim3(cnt), dim3(LA_THREADS), 0, c.stream, b, j0);
     {
@@ -593,13 +596,13 @@ void qr_blocked(Ctx &c, int cnt, const ConstMatView *A, const MatView *Q, const 
     grouped(z1);
     grouped(z2);
   }
-  // Q = H_0 ... [I; 0], panels applied last to first
+  // Q = H_0 ... [I; 0], panels applied last to first (not for R-only requests)
   for (int j0 = ((kmax - 1) / QR_NB) * QR_NB; j0 >= 0; j0 -= QR_NB) {
     std::vector<Gemm> z1, z2;
     for (int i = 0; i < cnt; ++i) {
       const QrbDesc &D = b.d[i];
       const int jb = std::min(QR_NB, D.k - j0);
-      if (jb <= 0) continue;
+      if (jb <= 0 || !D.Q) continue;
       const int nq = D.k - j0;
       Gemm a;  // Z = V_p^T Q[j0:m, j0:k]
       a.M = jb;
@@ -657,10 +660,12 @@ void qr_batch(Ctx &c, int count, const ConstMatView *A, const MatView *Q, const 
       span(lo, hi, A[i].rows, A[i].rs);
       span(lo, hi, A[i].cols, A[i].cs);
       c.check_range(A[i].p, lo, hi, 8, "qr A");
-      lo = hi = 0;
-      span(lo, hi, Q[i].rows, Q[i].rs);
-      span(lo, hi, Q[i].cols, Q[i].cs);
-      c.check_range(Q[i].p, lo, hi, 8, "qr Q");
+      if (Q[i].p) {
+        lo = hi = 0;
+        span(lo, hi, Q[i].rows, Q[i].rs);
+        span(lo, hi, Q[i].cols, Q[i].cs);
+        c.check_range(Q[i].p, lo, hi, 8, "qr Q");
+      }
       lo = hi = 0;
       span(lo, hi, R[i].rows, R[i].rs);
       span(lo, hi, R[i].cols, R[i].cs);
@@ -680,6 +685,20 @@ void qr_batch(Ctx &c, int count, const ConstMatView *A, const MatView *Q, const 
       qr_blocked(c, cnt, bA.data() + b0, bQ.data() + b0, bR.data() + b0);
     }
     if (sA.empty()) return;
+    // the single-workgroup kernel always forms Q: R-only requests get scratch
+    int64_t qscr = 0;
+    for (const MatView &q : sQ)
+      if (!q.p) qscr += (int64_t)q.rows * q.cols;
+    if (qscr > 0) {
+      double *qs = c.buf("qr_Qscratch", qscr);
+      for (MatView &q : sQ)
+        if (!q.p) {
+          q = MatView{qs, q.rows, q.cols, q.cols, 1};
+          qs += (int64_t)q.rows * q.cols;
+        }
+      qr_batch(c, (int)sA.size(), sA.data(), sQ.data(), sR.data());
+      return;
+    }
     if ((int)sA.size() != count) {
       qr_batch(c, (int)sA.size(), sA.data(), sQ.data(), sR.data());
       return;

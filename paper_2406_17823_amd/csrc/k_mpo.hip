@@ -14,10 +14,13 @@ namespace qtt {
 
 namespace {
 
-__global__ __launch_bounds__(256) void k_mpo_csc(const double *T, double *Tout,
-                                                 const int *colptr, const int *rowidx,
-                                                 const double *val, int KI, int KO, int64_t post,
-                                                 int64_t total, const int *skip) {
+// TS: storage type of the tensors (float64, or float32 for the convection
+// networks of the mixed mode); the sums run in float64
+template <typename TS>
+__global__ __launch_bounds__(256) void k_mpo_csc(const TS *T, TS *Tout, const int *colptr,
+                                                 const int *rowidx, const double *val, int KI,
+                                                 int KO, int64_t post, int64_t total,
+                                                 const int *skip) {
   if (skip && *skip) return;
   for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
        idx += (int64_t)gridDim.x * blockDim.x) {
@@ -25,11 +28,11 @@ __global__ __launch_bounds__(256) void k_mpo_csc(const double *T, double *Tout,
     const int64_t t = idx / post;
     const int o = (int)(t % KO);
     const int64_t p = t / KO;
-    const double *src = T + p * KI * post + q;
+    const TS *src = T + p * KI * post + q;
     double s = 0.0;
     const int e = colptr[o + 1];
-    for (int z = colptr[o]; z < e; ++z) s += val[z] * src[(int64_t)rowidx[z] * post];
-    Tout[idx] = s;
+    for (int z = colptr[o]; z < e; ++z) s += val[z] * (double)src[(int64_t)rowidx[z] * post];
+    Tout[idx] = (TS)s;
   }
 }
 
@@ -103,11 +106,12 @@ void mpo_layer_grouped(Ctx &c, int nj, const MpoJob *jobs, const int *skip) {
 }
 
 void mpo_layer(Ctx &c, const double *T, double *Tout, const Mpo &W, int site, bool rev,
-               int64_t pre, int mi, int mo, int64_t post, const int *skip) {
+               int64_t pre, int mi, int mo, int64_t post, const int *skip, bool f32) {
   if (pre <= 0 || post <= 0) return;
   const int KI = 4 * mi, KO = 4 * mo;
-  c.check_range(T, 0, pre * KI * post - 1, 8, "mpo_layer in");
-  c.check_range(Tout, 0, pre * KO * post - 1, 8, "mpo_layer out");
+  const size_t es = f32 ? sizeof(float) : sizeof(double);
+  c.check_range(T, 0, pre * KI * post - 1, es, "mpo_layer in");
+  c.check_range(Tout, 0, pre * KO * post - 1, es, "mpo_layer out");
   const MpoCsc &z = W.csc[rev ? 1 : 0];
   const int *cp = z.colptr + z.cp_off[site];
   const int *ri = z.rowidx + z.nz_off[site];
@@ -115,8 +119,13 @@ void mpo_layer(Ctx &c, const double *T, double *Tout, const Mpo &W, int site, bo
   const int64_t total = pre * KO * post;
   int64_t g = (total + 255) / 256;
   if (g > 131072) g = 131072;
-  hipLaunchKernelGGL(k_mpo_csc, dim3((unsigned)g), dim3(256), 0, c.stream, T, Tout, cp, ri, vv, KI,
-                     KO, post, total, skip);
+  if (f32)
+    hipLaunchKernelGGL(k_mpo_csc<float>, dim3((unsigned)g), dim3(256), 0, c.stream,
+                       reinterpret_cast<const float *>(T), reinterpret_cast<float *>(Tout), cp, ri,
+                       vv, KI, KO, post, total, skip);
+  else
+    hipLaunchKernelGGL(k_mpo_csc<double>, dim3((unsigned)g), dim3(256), 0, c.stream, T, Tout, cp,
+                       ri, vv, KI, KO, post, total, skip);
   HIPC(hipGetLastError());
 }
 

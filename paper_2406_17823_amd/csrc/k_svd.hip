@@ -705,12 +705,20 @@ void svd_jacobi(Ctx &c, int count, const ConstMatView *A, const MatView *U, doub
 
 }  // namespace
 
-// Matrices with more than SVQ_MIN columns are first factorised A = Q R
-// (blocked Householder); the one-sided Jacobi then runs on X = R^T, whose
-// columns start much closer to orthogonal than those of A (about half the
-// sweeps on truncation unfoldings) and, for tall A, are also shorter.
-// X = U_X S V_X^T gives A = (Q V_X) S U_X^T.  A null U (U[i].p == nullptr)
-// asks for S and V only: the Jacobi rotations are then not accumulated.
+// Matrices with more than SVQ_MIN columns are first brought to a square
+// triangular factor by Householder QR steps, and the one-sided Jacobi runs
+// on its transpose, whose columns start much closer to orthogonal than A's
+// (and, for tall A, are shorter).  Each further QR of the previous R^T cuts
+// the sweeps on truncation unfoldings again (16 -> 9 -> 8 on a four-term RK4
+// sum), and the number of steps decides which singular vectors come out of
+// the Jacobi as its normalised columns, free of accumulated rotations:
+//   U and V wanted:  A = Q1 R1, X = R1^T = U_X S V_X^T, A = (Q1 V_X) S U_X^T:
+//                    V = U_X, U = Q1 V_X with the rotations accumulated;
+//   U only (null V): R1^T = Q2 R2, X = R2^T: A = (Q1 U_X) S (Q2 V_X)^T,
+//                    U = Q1 U_X;
+//   V only (null U): R2^T = Q3 R3, X = R3^T: A = (Q1 Q3 V_X) S (Q2 U_X)^T,
+//                    V = Q2 U_X.
+// Q factors that are not used are not formed.
 constexpr int SVQ_MIN = 32;
 
 void svd_batch(Ctx &c, int count, const ConstMatView *A, const MatView *U, double *const *S,
@@ -721,6 +729,7 @@ void svd_batch(Ctx &c, int count, const ConstMatView *A, const MatView *U, doubl
     if (U[i].rows != A[i].rows || U[i].cols != A[i].cols || V[i].rows != A[i].cols ||
         V[i].cols != A[i].cols)
       fail(QTT_E_SHAPE, "svd_batch: output shapes");
+    if (!U[i].p && !V[i].p) fail(QTT_E_ARG, "svd_batch: neither U nor V requested");
     (A[i].cols > SVQ_MIN ? qi : di).push_back(i);
   }
   if (!di.empty()) {
@@ -745,39 +754,68 @@ void svd_batch(Ctx &c, int count, const ConstMatView *A, const MatView *U, doubl
     svd_jacobi(c, (int)di.size(), a.data(), u.data(), s.data(), v.data());
   }
   if (qi.empty()) return;
+  const int cnt = (int)qi.size();
+  // number of QR steps per matrix (1: U and V, 2: U only, 3: V only)
+  std::vector<int> steps(cnt);
   int64_t qs = 0, ns = 0;
-  for (int i : qi) {
+  for (int k = 0; k < cnt; ++k) {
+    const int i = qi[k];
+    steps[k] = (U[i].p && V[i].p) ? 1 : (U[i].p ? 2 : 3);
     qs += (int64_t)A[i].rows * A[i].cols;
     ns += (int64_t)A[i].cols * A[i].cols;
   }
-  double *Qb = c.buf("svq_Q", qs);
-  double *Rb = c.buf("svq_R", ns);
+  double *Qb = c.buf("svq_Q", qs);     // Q1 (steps 1, 2)
+  double *Q2b = c.buf("svq_Q2", ns);   // Q2 (step 3)
+  double *Rb[2] = {c.buf("svq_R", ns), c.buf("svq_R2", ns)};  // R factors, ping-pong
   double *UXb = c.buf("svq_UX", ns);
   double *VXb = c.buf("svq_VX", ns);
-  std::vector<ConstMatView> a, x;
-  std::vector<MatView> q, r, ux, vx;
-  std::vector<double *> s;
-  int64_t qo = 0, no = 0;
-  for (int i : qi) {
-    const int m = A[i].rows, n = A[i].cols;
-    a.push_back(A[i]);
-    q.push_back(MatView{Qb + qo, m, n, n, 1});
-    r.push_back(MatView{Rb + no, n, n, n, 1});
-    x.push_back(ConstMatView{Rb + no, n, n, 1, n});  // R^T
-    ux.push_back(MatView{UXb + no, n, n, n, 1});
-    // without U the rotations need not be accumulated: V = U_X alone
-    vx.push_back(MatView{U[i].p ? VXb + no : nullptr, n, n, n, 1});
-    s.push_back(S[i]);
-    qo += (int64_t)m * n;
-    no += (int64_t)n * n;
+  std::vector<int64_t> qo(cnt), no(cnt);
+  {
+    int64_t o1 = 0, o2 = 0;
+    for (int k = 0; k < cnt; ++k) {
+      qo[k] = o1;
+      no[k] = o2;
+      o1 += (int64_t)A[qi[k]].rows * A[qi[k]].cols;
+      o2 += (int64_t)A[qi[k]].cols * A[qi[k]].cols;
+    }
   }
-  const int cnt = (int)qi.size();
-  qr_batch(c, cnt, a.data(), q.data(), r.data());
+  // QR step t (0-based) of every matrix that takes it; R of step t goes to Rb[t % 2]
+  for (int t = 0; t < 3; ++t) {
+    std::vector<ConstMatView> a;
+    std::vector<MatView> q, r;
+    for (int k = 0; k < cnt; ++k) {
+      if (steps[k] <= t) continue;
+      const int i = qi[k];
+      const int m = A[i].rows, n = A[i].cols;
+      double *R = Rb[t % 2] + no[k];
+      if (t == 0) {
+        a.push_back(A[i]);
+        q.push_back(MatView{steps[k] <= 2 ? Qb + qo[k] : nullptr, m, n, n, 1});
+      } else {
+        a.push_back(ConstMatView{Rb[(t - 1) % 2] + no[k], n, n, 1, n});  // previous R^T
+        q.push_back(MatView{(t == 1 && steps[k] == 3) ? Q2b + no[k] : nullptr, n, n, n, 1});
+      }
+      r.push_back(MatView{R, n, n, n, 1});
+    }
+    if (!a.empty()) qr_batch(c, (int)a.size(), a.data(), q.data(), r.data());
+  }
+  // one Jacobi batch over all of them: X = (last R)^T
+  std::vector<ConstMatView> x;
+  std::vector<MatView> ux, vx;
+  std::vector<double *> s;
+  for (int k = 0; k < cnt; ++k) {
+    const int n = A[qi[k]].cols;
+    x.push_back(ConstMatView{Rb[(steps[k] - 1) % 2] + no[k], n, n, 1, n});
+    ux.push_back(MatView{UXb + no[k], n, n, n, 1});
+    vx.push_back(MatView{steps[k] == 1 ? VXb + no[k] : nullptr, n, n, n, 1});
+    s.push_back(S[qi[k]]);
+  }
   svd_jacobi(c, cnt, x.data(), ux.data(), s.data(), vx.data());
   for (int k = 0; k < cnt; ++k) {
     const int i = qi[k];
     const int m = A[i].rows, n = A[i].cols;
-    {
+    if (steps[k] == 1) {
+      // V = U_X (copied into the caller's view)
       int64_t lo = 0, hi = 0;
       span(lo, hi, n, V[i].rs);
       span(lo, hi, n, V[i].cs);
@@ -788,20 +826,29 @@ void svd_batch(Ctx &c, int count, const ConstMatView *A, const MatView *U, doubl
                          V[i].cs, (const double *)ux[k].p, n, n);
       HIPC(hipGetLastError());
     }
-    if (!U[i].p) continue;
-    Gemm gq;  // U = Q V_X
-    gq.M = m;
-    gq.N = n;
+    Gemm gq;  // U = Q1 V_X (1 step), U = Q1 U_X (2), V = Q2 U_X (3)
     gq.K = n;
-    gq.A = q[k].p;
-    gq.sAm = n;
+    gq.N = n;
     gq.sAk = 1;
-    gq.B = vx[k].p;
-    gq.sBk = n;
     gq.sBn = 1;
-    gq.C = U[i].p;
-    gq.sCm = U[i].rs;
-    gq.sCn = U[i].cs;
+    gq.sBk = n;
+    if (steps[k] == 3) {
+      gq.M = n;
+      gq.A = Q2b + no[k];
+      gq.sAm = n;
+      gq.B = ux[k].p;
+      gq.C = V[i].p;
+      gq.sCm = V[i].rs;
+      gq.sCn = V[i].cs;
+    } else {
+      gq.M = m;
+      gq.A = Qb + qo[k];
+      gq.sAm = n;
+      gq.B = steps[k] == 1 ? vx[k].p : ux[k].p;
+      gq.C = U[i].p;
+      gq.sCm = U[i].rs;
+      gq.sCn = U[i].cs;
+    }
     gemm(c, gq);
   }
 }

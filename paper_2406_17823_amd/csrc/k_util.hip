@@ -21,6 +21,12 @@ __global__ void k_fill(double *p, int64_t n, double v) {
     p[i] = v;
 }
 
+__global__ void k_fill_f32(float *p, int64_t n, float v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
 __global__ void k_scale_copy(double *d, const double *s, int64_t n, double a) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
@@ -165,6 +171,13 @@ void fill(Ctx &c, double *p, int64_t n, double v) {
   if (n <= 0) return;
   c.check_range(p, 0, n - 1, 8, "fill");
   hipLaunchKernelGGL(k_fill, dim3(grid_for(n)), dim3(256), 0, c.stream, p, n, v);
+  HIPC(hipGetLastError());
+}
+
+void fill_f32(Ctx &c, float *p, int64_t n, float v) {
+  if (n <= 0) return;
+  c.check_range(p, 0, n - 1, 4, "fill_f32");
+  hipLaunchKernelGGL(k_fill_f32, dim3(grid_for(n)), dim3(256), 0, c.stream, p, n, v);
   HIPC(hipGetLastError());
 }
 

@@ -205,6 +205,10 @@ struct Gemm {
   int64_t sCm = 0, sCn = 0, sCb1 = 0, sCb2 = 0;
   double alpha = 1.0, beta = 0.0;
   const int *skip = nullptr;
+  // A, B or C held as float32 (the pointer is reinterpreted, strides count
+  // float32 elements): the convection networks of the mixed mode keep their
+  // environments and chain intermediates in float32 storage
+  bool a32 = false, b32 = false, c32 = false;
 };
 constexpr int GEMM_GROUP = 4;
 void gemm(Ctx &c, const Gemm &g);
@@ -223,6 +227,7 @@ void gemm_bf16x3(Ctx &c, const Gemm &g);
 
 // ---------------------------------------------------------------- small kernels
 void fill(Ctx &c, double *p, int64_t n, double v);
+void fill_f32(Ctx &c, float *p, int64_t n, float v);
 void scale_copy(Ctx &c, double *dst, const double *src, int64_t n, double s);
 void axpy_into(Ctx &c, double *y, const double *x, int64_t n, double s);
 // dst[i0][i1][i2] = s * src[i0*s0 + i1*s1 + i2*s2], dst packed (d0 x d1 x d2)
@@ -236,8 +241,9 @@ void hadamard_core(Ctx &c, double *y, const double *a, int la, int ra, const dou
 void mpo_core(Ctx &c, double *y, const double *W, int wl, int wr, const double *x, int l, int r);
 // one MPO layer of a network chain (sparse, HBM-streaming):
 // Tout[p][w_out][m'][q] = sum W[m][w_in][w_out][m'] T[p][m][w_in][q]
+// f32: T and Tout are float32 arrays (sums in float64)
 void mpo_layer(Ctx &c, const double *T, double *Tout, const Mpo &W, int site, bool rev,
-               int64_t pre, int mi, int mo, int64_t post, const int *skip);
+               int64_t pre, int mi, int mo, int64_t post, const int *skip, bool f32 = false);
 struct MpoJob {
   const double *T;
   double *Tout;
@@ -267,11 +273,13 @@ struct ConstMatView {
   int64_t rs, cs;
 };
 // Batched Householder QR of m x n matrices (reduced): Q (m x k), R (k x n),
-// k = min(m, n), diag(R) >= 0.  Outputs may alias nothing.
+// k = min(m, n), diag(R) >= 0.  Outputs may alias nothing.  A view with a
+// null pointer in Q asks for R only (the explicit Q is then not formed).
 void qr_batch(Ctx &c, int count, const ConstMatView *A, const MatView *Q, const MatView *R);
 // Batched one-sided Jacobi SVD of m x n (m >= n) matrices: A = U diag(S) V^T,
 // singular values descending.  U is m x n, V is n x n, S has n entries
-// (device).  A view with a null pointer in U asks for S and V only.
+// (device).  A view with a null pointer in U asks for S and V only, one with
+// a null pointer in V for U and S only.
 void svd_batch(Ctx &c, int count, const ConstMatView *A, const MatView *U, double *const *S,
                const MatView *V);
 

@@ -10,34 +10,6 @@ namespace qtt {
 
 namespace {
 
-__global__ void k_scale_cols(double *dst, const double *U, int rows, int cols, int64_t urs,
-                             int64_t ucs, const double *S) {
-  const int64_t n = (int64_t)rows * cols;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const int r = (int)(i / cols), cc = (int)(i % cols);
-    dst[i] = U[r * urs + cc * ucs] * S[cc];
-  }
-}
-
-void scale_cols(Ctx &c, double *dst, const double *U, int rows, int cols, int64_t urs,
-                int64_t ucs, const double *S) {
-  const int64_t n = (int64_t)rows * cols;
-  if (n <= 0) return;
-  c.check_range(dst, 0, n - 1, 8, "scale_cols dst");
-  {
-    int64_t lo = 0, hi = 0;
-    span(lo, hi, rows, urs);
-    span(lo, hi, cols, ucs);
-    c.check_range(U, lo, hi, 8, "scale_cols U");
-  }
-  c.check_range(S, 0, cols - 1, 8, "scale_cols S");
-  unsigned g = (unsigned)std::min<int64_t>(65536, (n + 255) / 256);
-  hipLaunchKernelGGL(k_scale_cols, dim3(g), dim3(256), 0, c.stream, dst, U, rows, cols, urs, ucs,
-                     S);
-  HIPC(hipGetLastError());
-}
-
 bool overlaps(const double *a, int64_t na, const double *b, int64_t nb) {
   return a < b + nb && b < a + na;
 }
@@ -399,9 +371,10 @@ void mps_truncate(Ctx &c, std::vector<Mps *> ys, int chi, double rtol, double *d
         A[i] = ConstMatView{src, l, 4 * r, 4 * (int64_t)r, 1};
       else
         A[i] = ConstMatView{src, 4 * r, l, 1, 4 * (int64_t)r};
-      // tall: only S and V are needed (G = A V[:, :keep] below)
+      // tall: only S and V are needed (G = M V[:, :keep] below); wide: only
+      // U and S (G = M U[:, :keep])
       U[i] = MatView{tall[i] ? nullptr : Ub + uo, m[i], nn[i], nn[i], 1};
-      V[i] = MatView{Vb + vo, nn[i], nn[i], nn[i], 1};
+      V[i] = MatView{tall[i] ? Vb + vo : nullptr, nn[i], nn[i], nn[i], 1};
       S[i] = Sdev + (int64_t)i * maxn;
       uo += (int64_t)m[i] * nn[i];
       vo += (int64_t)nn[i] * nn[i];
@@ -444,9 +417,22 @@ void mps_truncate(Ctx &c, std::vector<Mps *> ys, int chi, double rtol, double *d
         gm.sCn = 1;
         gemm(c, gm);
       } else {
-        // M^T = U' S V'^T: core rows = U'^T[:keep] ; G = V'[:, :keep] S
+        // M^T = U' S V'^T: core rows = U'^T[:keep] ; G = V'[:, :keep] S = M U'[:, :keep]
         permute3(c, WC + slot[i][k], Ub + uo, keep, 1, 4 * r, 1, 0, ns);
-        scale_cols(c, Gb + uo, Vb + vo, l, keep, ns, 1, S[i]);
+        Gemm gm;
+        gm.M = l;
+        gm.N = keep;
+        gm.K = 4 * r;
+        gm.A = A[i].p;
+        gm.sAm = 4 * (int64_t)r;
+        gm.sAk = 1;
+        gm.B = Ub + uo;
+        gm.sBk = ns;
+        gm.sBn = 1;
+        gm.C = Gb + uo;
+        gm.sCm = keep;
+        gm.sCn = 1;
+        gemm(c, gm);
       }
       Gemm g;  // WA[k-1] = WB[k-1] (4 lp x l) * G (l x keep)
       g.M = 4 * lp;

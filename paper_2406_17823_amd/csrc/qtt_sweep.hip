@@ -64,6 +64,14 @@ struct Net {
   double *env = nullptr;
   std::vector<int64_t> eoff;
   double *T = nullptr;
+  // float32-MFMA networks keep their environments and chain intermediates in
+  // float32 storage (half the bytes of the largest tensors of the step); env
+  // and T then point at float arrays and eoff counts float elements
+  bool f32s() const { return prec == QTT_PREC_F32; }
+  double *envp(int b) const {
+    return f32s() ? reinterpret_cast<double *>(reinterpret_cast<float *>(env) + eoff[b])
+                  : env + eoff[b];
+  }
 };
 
 struct Sweep {
@@ -151,6 +159,7 @@ struct Sweep {
       q.sCm = 4 * gp;
       q.sCn = 1;
       q.skip = skip;
+      q.a32 = q.c32 = N.f32s();
       gemm_for(N, q);
     }
     for (int l = pl - 1; l >= 0; --l) {
@@ -161,7 +170,7 @@ struct Sweep {
       double *dst = bufs[1 - cur];
       const double *core = N.lay[l].core(d, rev);
       if (N.lay[l].kind == LAYER_MPO) {
-        mpo_layer(c, src, dst, *N.lay[l].mpo, d, rev, pre, mi[l], mo[l], post, skip);
+        mpo_layer(c, src, dst, *N.lay[l].mpo, d, rev, pre, mi[l], mo[l], post, skip, N.f32s());
         cur = 1 - cur;
         continue;
       }
@@ -188,6 +197,7 @@ struct Sweep {
         q.sCn = 1;
         q.sCb1 = 4 * mo[l] * post;
         q.sCb2 = mo[l] * post;
+        q.b32 = q.c32 = N.f32s();
       }
       gemm_for(N, q);
       cur = 1 - cur;
@@ -204,8 +214,9 @@ struct Sweep {
     q.skip = skip;
     q.alpha = alpha;
     q.beta = 1.0;
+    q.a32 = q.b32 = N.f32s();  // T and the environment; out is float64
     if (!rev) {
-      const double *R = N.env + N.eoff[d + 1];
+      const double *R = N.envp(d + 1);
       q.M = 4 * al;
       q.N = ar;
       q.K = (int)rest;
@@ -219,7 +230,7 @@ struct Sweep {
       q.sCm = ar;
       q.sCn = 1;
     } else {
-      const double *L = N.env + N.eoff[d];
+      const double *L = N.envp(d);
       q.B2 = 4;
       q.M = ar;
       q.N = al;
@@ -263,9 +274,10 @@ struct Sweep {
     q.B = T;
     q.sBk = rest;
     q.sBn = 1;
-    q.C = N.env + N.eoff[bo];
+    q.C = N.envp(bo);
     q.sCm = rest;
     q.sCn = 1;
+    q.b32 = q.c32 = N.f32s();
     gemm_for(N, q);
   }
 
@@ -291,13 +303,20 @@ struct Sweep {
         N->eoff[b] = o;
         o += env_size(*N, b);
       }
-      N->env = c.buf("sw_env" + std::to_string(idx), o);
-      fill(c, N->env + N->eoff[0], 1, 1.0);
-      fill(c, N->env + N->eoff[n], 1, 1.0);
+      // float32 storage: sizes in float elements, buffers in doubles
+      const bool f = N->f32s();
+      N->env = c.buf("sw_env" + std::to_string(idx), f ? (o + 1) / 2 : o);
+      if (f) {
+        fill_f32(c, reinterpret_cast<float *>(N->envp(0)), 1, 1.0f);
+        fill_f32(c, reinterpret_cast<float *>(N->envp(n)), 1, 1.0f);
+      } else {
+        fill(c, N->envp(0), 1, 1.0);
+        fill(c, N->envp(n), 1, 1.0);
+      }
       int64_t own = 1;
       for (int d = 0; d < n; ++d) own = std::max(own, chain_max(*N, d));
       tmx = std::max(tmx, own);
-      if (!N->trial_ket) N->T = c.buf("sw_T" + std::to_string(idx), own);
+      if (!N->trial_ket) N->T = c.buf("sw_T" + std::to_string(idx), f ? (own + 1) / 2 : own);
       ++idx;
     }
     tmp = c.buf("sw_tmp", tmx);
@@ -581,7 +600,7 @@ struct Sweep {
     double *rh[2] = {rhs, rhs + s0};
     auto t0 = std::chrono::steady_clock::now();
     for (Net &N : rhs_nets()) {
-      const double *E = rev ? N.env + N.eoff[d + 1] : N.env + N.eoff[d];
+      const double *E = rev ? N.envp(d + 1) : N.envp(d);
       chain(N, d, rev, E, ket_core(N, d, rev), N.T, nullptr);
       open_into(N, d, rev, N.T, rh[N.bra], N.coef, nullptr);
     }
@@ -890,7 +909,7 @@ void project(Ctx &c, const Mps a[2], const Mps b[2], double h, const qtt_params 
   for (int d = n - 1; d >= 1; --d)
     for (Net *N : all) {
       if (reuse && b_free(*N)) continue;
-      S.chain(*N, d, true, N->env + N->eoff[d + 1], S.ket_core(*N, d, true), S.Tpen, nullptr);
+      S.chain(*N, d, true, N->envp(d + 1), S.ket_core(*N, d, true), S.Tpen, nullptr);
       S.env_from_T(*N, d, true, S.Tpen);
     }
   for (size_t idx = 0; idx < all.size(); ++idx) {
