@@ -220,10 +220,12 @@ int qtt_rk4_step_batched(qtt_ctx *ctx, int32_t nflows, qtt_mps *u, const qtt_par
  * sample_every-th launch is bracketed by HIP events on the context stream.
  * Enabling starts a new window; reading synchronises the stream. */
 enum {
-  QTT_KERNEL_GEMM_F64_T64 = 0,   /* k_gemm<double, 64, 64, 2, 2, 16>   */
-  QTT_KERNEL_GEMM_F32_T64 = 1,   /* k_gemm<float, 64, 64, 2, 2, 16>    */
-  QTT_KERNEL_GEMM_F64_T128 = 2,  /* k_gemm<double, 128, 128, 2, 4, 32> */
-  QTT_KERNEL_GEMM_F32_T128 = 3   /* k_gemm<float, 128, 128, 2, 4, 32>  */
+  /* each kind covers the instantiations k_gemm<T, BM, BN, WGM, WGN, KD, SA, SB>
+     for every operand storage type SA, SB */
+  QTT_KERNEL_GEMM_F64_T64 = 0,   /* k_gemm<double, 64, 64, 2, 2, 16, ...>   */
+  QTT_KERNEL_GEMM_F32_T64 = 1,   /* k_gemm<float, 64, 64, 2, 2, 16, ...>    */
+  QTT_KERNEL_GEMM_F64_T128 = 2,  /* k_gemm<double, 128, 128, 2, 4, 32, ...> */
+  QTT_KERNEL_GEMM_F32_T128 = 3   /* k_gemm<float, 128, 128, 2, 4, 32, ...>  */
 };
 typedef struct {
   int64_t launches;   /* launches in the window                          */

@@ -361,8 +361,11 @@ def kernel_timing(ctx, enable=True, sample_every=1):
 
 
 KERNEL_GEMM_F64_T64, KERNEL_GEMM_F32_T64, KERNEL_GEMM_F64_T128, KERNEL_GEMM_F32_T128 = 0, 1, 2, 3
-KERNEL_NAMES = {0: 'k_gemm<double, 64, 64, 2, 2, 16>', 1: 'k_gemm<float, 64, 64, 2, 2, 16>',
-                2: 'k_gemm<double, 128, 128, 2, 4, 32>', 3: 'k_gemm<float, 128, 128, 2, 4, 32>'}
+# timed GEMM kinds; each is a family of instantiations that differ only in the
+# operands' storage types (k_gemm<T, BM, BN, WGM, WGN, KD, SA, SB>)
+KERNEL_NAMES = {0: 'k_gemm<double, 64, 64, 2, 2, 16, *>', 1: 'k_gemm<float, 64, 64, 2, 2, 16, *>',
+                2: 'k_gemm<double, 128, 128, 2, 4, 32, *>',
+                3: 'k_gemm<float, 128, 128, 2, 4, 32, *>'}
 
 
 def kernel_stats(ctx, kernel):

@@ -6,7 +6,8 @@
         fraction of the window in which the GPU ran a kernel;
 
     python -m paper_2406_17823_amd.tracesum bytes FETCH_CSV WRITE_CSV KERNEL COPY_MIB
-        HBM bytes per dispatch of KERNEL from two counter-collection runs
+        HBM bytes per dispatch of KERNEL (a name, or a GEMM family
+        'k_gemm<T, BM, BN, WGM, WGN, KD, *>') from two counter-collection runs
         (FETCH_SIZE, WRITE_SIZE), each scaled by what the same counter reads
         for the calibration copy of COPY_MIB MiB (which reads and writes
         exactly that many bytes).
@@ -27,6 +28,17 @@ def _short(name):
         depth -= ch == '>'
         out.append(ch)
     return ''.join(out).strip()
+
+
+def _family(name):
+    """GEMM instantiations differing only in operand storage types form one
+    family, 'k_gemm<T, BM, BN, WGM, WGN, KD, *>' (the library times them as
+    one kind)."""
+    return re.sub(r', (double|float), (double|float)>$', ', *>', name)
+
+
+def _matches(name, kernel):
+    return _short(name) == kernel or ('*' in kernel and _family(_short(name)) == kernel)
 
 
 def _window(log, path):
@@ -80,6 +92,15 @@ def window(trace, log, path):
     print(f'{"total ms":>10} {"calls":>8} {"avg us":>9}  kernel')
     for k, (c, ms) in sorted(tot.items(), key=lambda x: -x[1][1])[:25]:
         print(f'{ms:10.2f} {c:8d} {1e3 * ms / c:9.2f}  {k}')
+    fam = collections.defaultdict(lambda: [0, 0.0])
+    for k, (c, ms) in tot.items():
+        if _family(k) != k:
+            fam[_family(k)][0] += c
+            fam[_family(k)][1] += ms
+    if fam:
+        print('GEMM families (all operand storage types):')
+        for k, (c, ms) in sorted(fam.items(), key=lambda x: -x[1][1]):
+            print(f'{ms:10.2f} {c:8d} {1e3 * ms / c:9.2f}  {k}')
 
 
 def _counter(csvfile, counter):
@@ -108,7 +129,7 @@ def bytes_per_dispatch(fetch_csv, write_csv, kernel, copy_mib):
         per = _counter(f, name)
         # the calibration copy: the largest dispatch outside the library
         cal = max((v for k, v in per.values() if 'qtt::' not in k), default=0.0)
-        vals = [v for k, v in per.values() if _short(k) == kernel]
+        vals = [v for k, v in per.values() if _matches(k, kernel)]
         if not vals or cal <= 0:
             print(f'{name}: no dispatches of {kernel} or no calibration copy')
             return
