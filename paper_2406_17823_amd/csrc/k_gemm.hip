@@ -49,6 +49,12 @@ template <> struct GemmKind<float> { static constexpr int value = 1; };
 template <> struct GemmKind<__bf16> { static constexpr int value = 2; };
 template <> struct GemmKind<bf3> { static constexpr int value = 3; };
 
+// accumulator of a 16 x 16 MFMA block: float32 for float32 MFMAs, float64
+// otherwise (bfloat16 products are summed in float32 per 16-deep step and in
+// float64 across steps)
+template <typename T> struct AccOf { typedef d4v type; };
+template <> struct AccOf<float> { typedef f4v type; };
+
 namespace {
 
 constexpr int KT = 16, PADM = 1;
@@ -100,15 +106,13 @@ struct Mfma<double, FM, FN, LD> {
   }
 };
 
+// float32: the accumulators stay float32 over the whole K range of the
+// tile (float32 accumulation, as the mixed mode prescribes); split-K
+// partials are summed in float64 by the reduction kernel
 template <int FM, int FN, int LD>
 struct Mfma<float, FM, FN, LD> {
   __device__ static void step(const float (*As)[LD], const float (*Bs)[LD], int lane, int m0,
-                              int n0, d4v (&acc)[FM][FN]) {
-    f4v f[FM][FN];
-#pragma unroll
-    for (int i = 0; i < FM; ++i)
-#pragma unroll
-      for (int j = 0; j < FN; ++j) f[i][j] = f4v{0.f, 0.f, 0.f, 0.f};
+                              int n0, f4v (&acc)[FM][FN]) {
 #pragma unroll
     for (int kq = 0; kq < KT / 4; ++kq) {
       const int kk = kq * 4 + (lane >> 4);
@@ -121,14 +125,8 @@ struct Mfma<float, FM, FN, LD> {
       for (int i = 0; i < FM; ++i)
 #pragma unroll
         for (int j = 0; j < FN; ++j)
-          f[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], f[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
     }
-#pragma unroll
-    for (int i = 0; i < FM; ++i)
-#pragma unroll
-      for (int j = 0; j < FN; ++j)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) acc[i][j][r] += (double)f[i][j][r];
   }
 };
 
@@ -275,11 +273,13 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_gemm(GemmK g) {
   const bool a_m_unit = (P.sAm == 1);
   const bool b_n_unit = (P.sBn == 1);
 
-  d4v acc[FM][FN];
+  typename AccOf<T>::type acc[FM][FN];
 #pragma unroll
   for (int i = 0; i < FM; ++i)
 #pragma unroll
-    for (int j = 0; j < FN; ++j) acc[i][j] = d4v{0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[i][j][r] = 0;
 
   SA ra[AL];
   SB rb[BL];
@@ -350,10 +350,11 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_gemm(GemmK g) {
         if (gm < P.M && gn < P.N) {
           if (!P.direct) {
             const int64_t bidx = (int64_t)b2 * P.B1 + b1;
-            P.part[(((int64_t)ks * P.B1 * P.B2 + bidx) * P.M + gm) * P.N + gn] = acc[i][j][r];
+            P.part[(((int64_t)ks * P.B1 * P.B2 + bidx) * P.M + gm) * P.N + gn] =
+                (double)acc[i][j][r];
           } else {
             const int64_t co = b1 * P.sCb1 + b2 * P.sCb2 + gm * P.sCm + gn * P.sCn;
-            double v = P.alpha * acc[i][j][r];
+            double v = P.alpha * (double)acc[i][j][r];
             if (P.c32) {
               float *cp = reinterpret_cast<float *>(P.C) + co;
               if (P.beta != 0.0) v += P.beta * (double)*cp;
@@ -383,17 +384,29 @@ struct RedOut {
   RedSrc src[2];
   int64_t elem0;
   int c32, x32;  // C / X stored as float32
+  const double *Y;  // dot partner laid out like C (float64), or null
 };
 struct RedK {
   int nout;
   RedOut o[GEMM_GROUP];
   const int *skip;
   int64_t total;
+  // fused dot sum_outputs C . Y: per-block partials in dpart, the last block
+  // to arrive (counter dctr, reset to 0 by it) sums them in block order
+  double *dpart, *dout;
+  unsigned *dctr;
 };
+
+__device__ inline double red_wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
 
 // out = alpha * (sum over sources, splits in order) + beta * X
 __global__ __launch_bounds__(256) void k_splitk_reduce(RedK R) {
   if (R.skip && *R.skip) return;
+  double dacc = 0.0;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < R.total;
        e += (int64_t)gridDim.x * blockDim.x) {
     int oi = 0;
@@ -419,6 +432,31 @@ __global__ __launch_bounds__(256) void k_splitk_reduce(RedK R) {
     const int64_t co = b1 * O.sCb1 + b2 * O.sCb2 + gm * O.sCm + gn * O.sCn;
     if (O.c32) reinterpret_cast<float *>(O.C)[co] = (float)v;
     else O.C[co] = v;
+    if (O.Y) dacc += v * O.Y[co];
+  }
+  if (!R.dout) return;
+  __shared__ double sh[4];
+  __shared__ bool last;
+  dacc = red_wave_sum(dacc);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = dacc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    R.dpart[blockIdx.x] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+    __threadfence();
+    last = (atomicAdd(R.dctr, 1u) == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  const volatile double *vp = R.dpart;
+  double a = 0.0;
+  for (int i = threadIdx.x; i < (int)gridDim.x; i += 256) a += vp[i];
+  a = red_wave_sum(a);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = a;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    *R.dout = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+    *R.dctr = 0;
   }
 }
 
@@ -531,7 +569,7 @@ int tuned_tile(Ctx &c, int np, const Gemm *q, int ngroups, const double *const *
 // one or two problems that share C; X[group] is the beta input, nullptr = C).
 template <typename T>
 void launch_group(Ctx &c, int np, const Gemm *q, int ngroups, const int *group,
-                  const double *const *X, const int *skip) {
+                  const double *const *X, const int *skip, const GemmDot *dot = nullptr) {
   GemmK g{};
   g.np = 0;
   g.skip = skip;
@@ -725,6 +763,16 @@ void launch_group(Ctx &c, int np, const Gemm *q, int ngroups, const int *group,
       }
       if (!any) continue;
       if (R.nout >= GEMM_GROUP) fail(QTT_E_ARG, "gemm group: too many reduced outputs");
+      if (dot) {
+        O.Y = dot->Y[gi];
+        int64_t lo = 0, hi = 0;
+        span(lo, hi, O.M, O.sCm);
+        span(lo, hi, O.N, O.sCn);
+        span(lo, hi, O.B1, O.sCb1);
+        span(lo, hi, O.B2, O.sCb2);
+        if (O.Y) c.check_range(O.Y, lo, hi, sizeof(double), "gemm dot partner");
+        if (O.c32) fail(QTT_E_ARG, "gemm dot: float64 outputs only");
+      }
       if (X[gi]) {
         int64_t lo = 0, hi = 0;
         span(lo, hi, O.M, O.sXm);
@@ -739,10 +787,24 @@ void launch_group(Ctx &c, int np, const Gemm *q, int ngroups, const int *group,
     }
     R.total = total;
     if (total > 0) {
-      const unsigned rg = (unsigned)std::min<int64_t>(4096, (total + 255) / 256);
+      unsigned rg = (unsigned)std::min<int64_t>(4096, (total + 255) / 256);
+      if (dot) {
+        rg = std::min<unsigned>(rg, (unsigned)dot->nparts);
+        c.check_range(dot->part, 0, rg - 1, sizeof(double), "gemm dot partials");
+        R.dpart = dot->part;
+        R.dout = dot->out;
+        R.dctr = dot->ctr;
+      }
       hipLaunchKernelGGL(k_splitk_reduce, dim3(rg), dim3(256), 0, c.stream, R);
       HIPC(hipGetLastError());
     }
+  }
+  if (dot) {
+    // every output must have gone through the reduction
+    for (int i = 0; i < np; ++i)
+      if (keep[i] >= 0 && g.p[keep[i]].direct)
+        fail(QTT_E_ARG, "gemm dot: outputs written directly by the GEMM");
+    if (part_need == 0) fail(QTT_E_ARG, "gemm dot: no reduced output");
   }
 }
 
@@ -773,10 +835,10 @@ void gemm_bf16x3(Ctx &c, const Gemm &g) {
 }
 
 void gemm_grouped(Ctx &c, int np, const Gemm *q, int ngroups, const int *group,
-                  const double *const *X, const int *skip, bool f32) {
+                  const double *const *X, const int *skip, bool f32, const GemmDot *dot) {
   if (np < 1 || np > GEMM_GROUP) fail(QTT_E_ARG, "gemm_grouped: 1..4 problems");
-  if (f32) launch_group<float>(c, np, q, ngroups, group, X, skip);
-  else launch_group<double>(c, np, q, ngroups, group, X, skip);
+  if (f32) launch_group<float>(c, np, q, ngroups, group, X, skip, dot);
+  else launch_group<double>(c, np, q, ngroups, group, X, skip, dot);
 }
 
 }  // namespace qtt

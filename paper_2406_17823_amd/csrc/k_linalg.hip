@@ -408,18 +408,34 @@ __global__ __launch_bounds__(64 * NW) void k_qrb_panel_reg(QrbBatch B, int j0) {
     if (tid == 0) T[i][i] = tau;
   }
   __syncthreads();
-  // write back: W panel (R entries and reflectors), V (unit diagonal, zeros above), T
+  // write back: W panel (R entries and reflectors), V (unit diagonal, zeros
+  // above), V T and V T^T of the thread's rows (T upper triangular, read
+  // from LDS on and above its diagonal only), T
 #pragma unroll
   for (int s = 0; s < ROWS; ++s) {
     const int r = tid + NT * s;
     if (r < j0 || r >= m) continue;
+    double v[QR_NB];
 #pragma unroll
     for (int t = 0; t < QR_NB; ++t) {
+      const int c = j0 + t;
+      v[t] = (t >= jb || r < c) ? 0.0 : (r == c ? 1.0 : P[s][t]);
       if (t < jb) {
-        const int c = j0 + t;
         D.W[(int64_t)c * m + r] = P[s][t];
-        D.V[(int64_t)c * m + r] = (r < c) ? 0.0 : (r == c ? 1.0 : P[s][t]);
+        D.V[(int64_t)c * m + r] = v[t];
       }
+    }
+#pragma unroll
+    for (int t = 0; t < QR_NB; ++t) {
+      if (t >= jb) continue;
+      double a = 0.0, bt = 0.0;
+#pragma unroll
+      for (int u = 0; u < QR_NB; ++u) {
+        if (u <= t) a += v[u] * T[u][t];
+        if (u >= t && u < jb) bt += v[u] * T[t][u];
+      }
+      D.VT[(int64_t)(j0 + t) * m + r] = a;
+      D.VTt[(int64_t)(j0 + t) * m + r] = bt;
     }
   }
   for (int e = tid; e < QR_NB * QR_NB; e += NT) {
@@ -547,9 +563,9 @@ void qr_blocked(Ctx &c, int cnt, const ConstMatView *A, const MatView *Q, const 
       hipLaunchKernelGGL((k_qrb_panel_reg<8, 2>), dim3(cnt), dim3(512), 0, c.stream, b, j0);
     else if (mmax <= 512 * QR_REG_MAXROWS)
       hipLaunchKernelGGL((k_qrb_panel_reg<8, 4>), dim3(cnt), dim3(512), 0, c.stream, b, j0);
-    else
+    if (mmax > 512 * QR_REG_MAXROWS) {
+      // matrices taller than the register panel: panel in HBM, V T by a second kernel
       hipLaunchKernelGGL(k_qrb_panel, dim3(cnt), dim3(LA_THREADS), 0, c.stream, b, j0);
-    {
       int64_t rows = 0;
       for (int i = 0; i < cnt; ++i) rows = std::max<int64_t>(rows, (int64_t)(b.d[i].m - j0) * QR_NB);
       const unsigned gv = (unsigned)std::max<int64_t>(1, std::min<int64_t>(2048, (rows + 255) / 256));

@@ -215,8 +215,21 @@ void gemm(Ctx &c, const Gemm &g);
 // up to GEMM_GROUP problems in one launch; problem i contributes to output
 // group group[i] (a group holds one or two problems sharing C, alpha, beta;
 // two problems are summed); X[group] (nullptr = C) is the beta input.
+// With dot, the reduction kernel also forms sum_groups C . Y[group] (Y laid
+// out like C, float64) into the device scalar out, deterministically (block
+// partials in part, summed in block order by the last block to arrive at the
+// counter ctr, which must be 0 and is left 0); every output must go through
+// the reduction (summed or split-K).
+struct GemmDot {
+  const double *Y[GEMM_GROUP];
+  double *out;
+  unsigned *ctr;
+  double *part;
+  int nparts;
+};
 void gemm_grouped(Ctx &c, int np, const Gemm *q, int ngroups, const int *group,
-                  const double *const *X, const int *skip, bool f32);
+                  const double *const *X, const int *skip, bool f32,
+                  const GemmDot *dot = nullptr);
 // float32-MFMA variant with float64 inputs/outputs (mixed precision mode)
 void gemm_f32(Ctx &c, const Gemm &g);
 // bfloat16-MFMA variant (float32 accumulation) with float64 inputs/outputs

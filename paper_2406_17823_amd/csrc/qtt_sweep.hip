@@ -348,7 +348,9 @@ struct Sweep {
     }
   }
 
-  void matvec(int d, const double *x, double *y, const int *skip) {
+  // dot: the reduction of the last GEMM also forms delta = y . x into the CG
+  // state (single-reduction CG)
+  void matvec(int d, const double *x, double *y, const int *skip, bool dot = false) {
     const int64_t s0 = centre_size(0, d);
     const double *xs[2] = {x, x + s0};
     double *ys[2] = {y, y + s0};
@@ -397,8 +399,22 @@ struct Sweep {
     }
     gemm_grouped(c, 4, kg, 4, kgrp, kX, skip, false);
     mpo_layer_grouped(c, 4, mj, skip);
-    gemm_grouped(c, 4, og, 2, ogrp, oX, skip, false);
+    if (dot) {
+      GemmDot gd{};
+      gd.Y[0] = xs[0];
+      gd.Y[1] = xs[1];
+      gd.out = &st->delta;
+      gd.ctr = &st->counter;
+      gd.part = dpart;
+      gd.nparts = DPART;
+      gemm_grouped(c, 4, og, 2, ogrp, oX, skip, false, &gd);
+    } else {
+      gemm_grouped(c, 4, og, 2, ogrp, oX, skip, false);
+    }
   }
+  static constexpr int DPART = 1024;
+  double *dpart = nullptr;  // partials of the fused dot
+  double *sv = nullptr;     // s = A p of the single-reduction CG
 
   void copy_skip(const double *x, double *y, int64_t n_, const int *skip);
 
@@ -429,6 +445,8 @@ struct Sweep {
     add(pp);
     add(q);
     add(rhs);
+    add(sv);
+    add(dpart);
     add(st);
     add(part);
     add(tmp);
@@ -524,14 +542,17 @@ struct Sweep {
               const double *rhs, int64_t ntot) {
     auto enqueue_iters = [&](int k) {
       for (int i = 0; i < k; ++i) {
-        matvec(d, pp, q, &st->done);
-        cg_alpha(c, pp, q, ntot, st, part);
-        cg_update(c, x, r, pp, q, ntot, st, part);
         if (pre) {
+          matvec(d, pp, q, &st->done);
+          cg_alpha(c, pp, q, ntot, st, part);
+          cg_update(c, x, r, pp, q, ntot, st, part);
           apply_pc(r, pcz, d, &st->done);
           pcg_next(c, r, pcz, pp, ntot, st, part);
         } else {
-          cg_pupdate(c, r, pp, ntot, st);
+          // single-reduction CG: one vector kernel and one matvec (w = A r
+          // in q, with delta = w . r fused into its reduction) per iteration
+          cg1_update(c, x, r, pp, sv, q, ntot, st, part);
+          matvec(d, r, q, &st->done, true);
         }
       }
     };
@@ -586,6 +607,8 @@ struct Sweep {
     if (pre) {
       apply_pc(r, pcz, d, &st->done);
       pcg_start(c, r, pcz, pp, ntot, st, part);
+    } else {
+      matvec(d, r, q, &st->done, true);  // w = A r, delta = w . r
     }
   }
 
@@ -596,6 +619,8 @@ struct Sweep {
     double *r = c.buf("sw_r", ntot);
     double *pp = c.buf("sw_p", ntot);
     double *q = c.buf("sw_q", ntot);
+    sv = c.buf("sw_s", ntot);
+    dpart = c.buf("sw_dpart", DPART);
     fill(c, rhs, ntot, 0.0);
     double *rh[2] = {rhs, rhs + s0};
     auto t0 = std::chrono::steady_clock::now();
