@@ -8,7 +8,8 @@
 //    2048 x 512 unfoldings of a four-term RK4 sum at chi = 128) use the blocked
 //    form: a panel of QR_NB columns is factorised by one workgroup per
 //    matrix, its reflectors are aggregated into I - V T V^T (compact WY), and
-//    the trailing columns and the explicit Q are updated by MFMA GEMMs.
+//    the trailing columns and the explicit Q are updated by a block-reflector
+//    kernel on float64 MFMAs (one workgroup per 32-column tile).
 //  (the SVD of the right-to-left pass of TT-rounding is in k_svd.hip)
 //
 // The working matrix lives column-major in a workspace slice in HBM/L2 so
@@ -138,6 +139,8 @@ __global__ __launch_bounds__(LA_THREADS) void k_qr(QRBatch batch) {
 // ---------------------------------------------------------------- blocked QR
 constexpr int QR_NB = 16;
 constexpr int QR_REG_MAXROWS = 4;  // rows per thread of the register-resident panel, at most
+
+typedef double d4v __attribute__((ext_vector_type(4)));
 
 struct QrbDesc {
   const double *A;
@@ -465,6 +468,111 @@ __global__ void k_qrb_vt(QrbBatch B, int j0) {
   }
 }
 
+// Block reflector applied to one 32-column tile X[j0:m, c0:c0+32) of one
+// matrix: X -= U (V_p^T X), with U = V_p T_p^T for the trailing columns of
+// the working matrix (which = 0) and U = V_p T_p for the explicit Q (which =
+// 1).  Both products run on float64 MFMAs inside one 8-wave workgroup: Z =
+// V_p^T X (16 x 32) with the rows dealt to the waves and the partials summed
+// in wave order through LDS, then X^T -= Z^T U^T on 16-row tiles (lanes along
+// rows, so X is read and written in 128-byte column segments), the loads of
+// a batch of tiles issued before their MFMAs.  One launch per panel replaces
+// two GEMMs, a split-K reduction and their launch gaps.
+constexpr int QA_COLS = 32, QA_THREADS = 512, QA_WAVES = QA_THREADS / 64, QA_BATCH = 4;
+
+__global__ __launch_bounds__(QA_THREADS) void k_qrb_apply(QrbBatch B, int j0, int which) {
+  const QrbDesc &D = B.d[blockIdx.y];
+  const int m = D.m;
+  const int jb = min(QR_NB, D.k - j0);
+  if (jb <= 0) return;
+  double *X;
+  const double *U;
+  int cbeg, cend;
+  if (which == 0) {
+    X = D.W;
+    U = D.VTt;
+    cbeg = j0 + jb;
+    cend = D.n;
+  } else {
+    if (!D.Q) return;
+    X = D.Qw;
+    U = D.VT;
+    cbeg = j0;
+    cend = D.k;
+  }
+  const int c0 = cbeg + (int)blockIdx.x * QA_COLS;
+  if (c0 >= cend) return;
+  const int nc = min(QA_COLS, cend - c0);
+  const int R = m - j0;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  __shared__ double Zs[QA_WAVES][QR_NB][QA_COLS + 1];
+  // Z = V_p^T X: A[t][k] = V[j0 + k][j0 + t], B[k][c] = X[j0 + k][c0 + c]
+  d4v z[2] = {d4v{0.0, 0.0, 0.0, 0.0}, d4v{0.0, 0.0, 0.0, 0.0}};
+#pragma unroll 8
+  for (int k0 = 4 * wave; k0 < R; k0 += 4 * QA_WAVES) {
+    const int kr = k0 + lk;
+    const int64_t r = j0 + kr;
+    const bool rv = kr < R;
+    const double a = (rv && li < jb) ? D.V[(int64_t)(j0 + li) * m + r] : 0.0;
+    const double b0 = (rv && li < nc) ? X[(int64_t)(c0 + li) * m + r] : 0.0;
+    const double b1 = (rv && 16 + li < nc) ? X[(int64_t)(c0 + 16 + li) * m + r] : 0.0;
+    z[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b0, z[0], 0, 0, 0);
+    z[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b1, z[1], 0, 0, 0);
+  }
+  // D register q: row 4 q + lane / 16, column lane % 16
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) Zs[wave][4 * q + lk][16 * h + li] = z[h][q];
+  __syncthreads();
+  for (int e = threadIdx.x; e < QR_NB * QA_COLS; e += QA_THREADS) {
+    const int t = e / QA_COLS, cc = e % QA_COLS;
+    double sum = Zs[0][t][cc];
+#pragma unroll
+    for (int w = 1; w < QA_WAVES; ++w) sum += Zs[w][t][cc];
+    Zs[0][t][cc] = sum;
+  }
+  __syncthreads();
+  // X^T[c][r] -= sum_t Z[t][c] U[r][t]: A[c][t] = Z[t][c] (LDS), B[t][r] = U[r][t]
+  const int ntiles = ((R + 15) / 16) * 2;
+  for (int base = wave; base < ntiles; base += QA_WAVES * QA_BATCH) {
+    double ub[QA_BATCH][4], xo[QA_BATCH][4];
+#pragma unroll
+    for (int j = 0; j < QA_BATCH; ++j) {
+      const int task = base + j * QA_WAVES;
+      const int rt = task >> 1, h = task & 1;
+      const int r = j0 + 16 * rt + li;
+      const bool ok = task < ntiles && 16 * h < nc && r < m;
+#pragma unroll
+      for (int t0 = 0; t0 < 4; ++t0) {
+        const int t = 4 * t0 + lk;
+        ub[j][t0] = (ok && t < jb) ? U[(int64_t)(j0 + t) * m + r] : 0.0;
+        const int cc = 16 * h + 4 * t0 + lk;
+        xo[j][t0] = (ok && cc < nc) ? X[(int64_t)(c0 + cc) * m + r] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < QA_BATCH; ++j) {
+      const int task = base + j * QA_WAVES;
+      const int rt = task >> 1, h = task & 1;
+      const int r = j0 + 16 * rt + li;
+      // wave-uniform skip: every lane takes part in the MFMAs (rows past m
+      // carry zeros and are not stored)
+      if (!(task < ntiles && 16 * h < nc)) continue;
+      d4v acc = d4v{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int t0 = 0; t0 < 4; ++t0)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Zs[0][4 * t0 + lk][16 * h + li], ub[j][t0], acc,
+                                                   0, 0, 0);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int cc = 16 * h + 4 * q + lk;
+        if (r < m && cc < nc) X[(int64_t)(c0 + cc) * m + r] = xo[j][q] - acc[q];
+      }
+    }
+  }
+}
+
 // sign convention diag(R) >= 0; Q (m x k) and R (k x n) into the caller views
 __global__ void k_qrb_finish(QrbBatch B) {
   const QrbDesc &D = B.d[blockIdx.y];
@@ -503,12 +611,11 @@ void qr_blocked(Ctx &c, int cnt, const ConstMatView *A, const MatView *Q, const 
   int kmax = 0, nmax = 0;
   for (int i = 0; i < cnt; ++i) {
     const int m = A[i].rows, n = A[i].cols, k = std::min(m, n);
-    ws += (int64_t)m * n + 4 * (int64_t)m * k + (int64_t)QR_NB * n + QR_NB * QR_NB;
+    ws += (int64_t)m * n + 4 * (int64_t)m * k + QR_NB * QR_NB;
     kmax = std::max(kmax, k);
     nmax = std::max(nmax, n);
   }
   double *Wb = c.buf("qrb_work", ws);
-  std::vector<double *> Z(cnt);
   int64_t o = 0;
   int64_t elems = 0;
   for (int i = 0; i < cnt; ++i) {
@@ -530,8 +637,6 @@ void qr_blocked(Ctx &c, int cnt, const ConstMatView *A, const MatView *Q, const 
     o += (int64_t)m * k;
     D.Qw = Wb + o;
     o += (int64_t)m * k;
-    Z[i] = Wb + o;
-    o += (int64_t)QR_NB * n;
     D.T = Wb + o;
     o += QR_NB * QR_NB;
     D.Q = Q[i].p;
@@ -545,15 +650,6 @@ void qr_blocked(Ctx &c, int cnt, const ConstMatView *A, const MatView *Q, const 
   const unsigned g = (unsigned)std::min<int64_t>(1024, (elems + 255) / 256);
   hipLaunchKernelGGL(k_qrb_load, dim3(g, cnt), dim3(256), 0, c.stream, b);
   HIPC(hipGetLastError());
-  // grouped GEMMs over the matrices (at most GEMM_GROUP per launch)
-  auto grouped = [&](std::vector<Gemm> &qs) {
-    for (size_t s0 = 0; s0 < qs.size(); s0 += GEMM_GROUP) {
-      const int np = (int)std::min<size_t>(GEMM_GROUP, qs.size() - s0);
-      int grp[GEMM_GROUP] = {0, 1, 2, 3};
-      const double *X[GEMM_GROUP] = {nullptr, nullptr, nullptr, nullptr};
-      gemm_grouped(c, np, qs.data() + s0, np, grp, X, nullptr, false);
-    }
-  };
   for (int j0 = 0; j0 < kmax; j0 += QR_NB) {
     int mmax = 0;
     for (int i = 0; i < cnt; ++i) mmax = std::max(mmax, b.d[i].m);
@@ -572,87 +668,31 @@ void qr_blocked(Ctx &c, int cnt, const ConstMatView *A, const MatView *Q, const 
       hipLaunchKernelGGL(k_qrb_vt, dim3(gv, cnt), dim3(256), 0, c.stream, b, j0);
     }
     HIPC(hipGetLastError());
-    std::vector<Gemm> z1, z2;
+    // trailing columns: W[j0:m, j0+jb:n] -= (V_p T_p^T)(V_p^T W[j0:m, j0+jb:n])
+    int tiles = 0;
     for (int i = 0; i < cnt; ++i) {
       const QrbDesc &D = b.d[i];
       const int jb = std::min(QR_NB, D.k - j0);
-      const int nt = D.n - j0 - jb;
-      if (jb <= 0 || nt <= 0) continue;
-      Gemm a;  // Z = V_p^T W[j0:m, j0+jb:n]
-      a.M = jb;
-      a.N = nt;
-      a.K = D.m - j0;
-      a.A = D.V + (int64_t)j0 * D.m + j0;
-      a.sAm = D.m;
-      a.sAk = 1;
-      a.B = D.W + (int64_t)(j0 + jb) * D.m + j0;
-      a.sBk = 1;
-      a.sBn = D.m;
-      a.C = Z[i];
-      a.sCm = nt;
-      a.sCn = 1;
-      z1.push_back(a);
-      Gemm u;  // W[j0:m, j0+jb:n] -= (V_p T_p^T) Z
-      u.M = D.m - j0;
-      u.N = nt;
-      u.K = jb;
-      u.A = D.VTt + (int64_t)j0 * D.m + j0;
-      u.sAm = 1;
-      u.sAk = D.m;
-      u.B = Z[i];
-      u.sBk = nt;
-      u.sBn = 1;
-      u.C = D.W + (int64_t)(j0 + jb) * D.m + j0;
-      u.sCm = 1;
-      u.sCn = D.m;
-      u.alpha = -1.0;
-      u.beta = 1.0;
-      z2.push_back(u);
+      const int nt = D.n - j0 - std::max(jb, 0);
+      if (jb > 0 && nt > 0) tiles = std::max(tiles, (nt + QA_COLS - 1) / QA_COLS);
     }
-    grouped(z1);
-    grouped(z2);
+    if (tiles > 0) {
+      hipLaunchKernelGGL(k_qrb_apply, dim3(tiles, cnt), dim3(QA_THREADS), 0, c.stream, b, j0, 0);
+      HIPC(hipGetLastError());
+    }
   }
-  // Q = H_0 ... [I; 0], panels applied last to first (not for R-only requests)
+  // Q = H_0 ... [I; 0], panels applied last to first (not for R-only requests):
+  // Q[j0:m, j0:k] -= (V_p T_p)(V_p^T Q[j0:m, j0:k])
   for (int j0 = ((kmax - 1) / QR_NB) * QR_NB; j0 >= 0; j0 -= QR_NB) {
-    std::vector<Gemm> z1, z2;
+    int tiles = 0;
     for (int i = 0; i < cnt; ++i) {
       const QrbDesc &D = b.d[i];
-      const int jb = std::min(QR_NB, D.k - j0);
-      if (jb <= 0 || !D.Q) continue;
-      const int nq = D.k - j0;
-      Gemm a;  // Z = V_p^T Q[j0:m, j0:k]
-      a.M = jb;
-      a.N = nq;
-      a.K = D.m - j0;
-      a.A = D.V + (int64_t)j0 * D.m + j0;
-      a.sAm = D.m;
-      a.sAk = 1;
-      a.B = D.Qw + (int64_t)j0 * D.m + j0;
-      a.sBk = 1;
-      a.sBn = D.m;
-      a.C = Z[i];
-      a.sCm = nq;
-      a.sCn = 1;
-      z1.push_back(a);
-      Gemm u;  // Q[j0:m, j0:k] -= (V_p T_p) Z
-      u.M = D.m - j0;
-      u.N = nq;
-      u.K = jb;
-      u.A = D.VT + (int64_t)j0 * D.m + j0;
-      u.sAm = 1;
-      u.sAk = D.m;
-      u.B = Z[i];
-      u.sBk = nq;
-      u.sBn = 1;
-      u.C = D.Qw + (int64_t)j0 * D.m + j0;
-      u.sCm = 1;
-      u.sCn = D.m;
-      u.alpha = -1.0;
-      u.beta = 1.0;
-      z2.push_back(u);
+      if (D.Q && D.k - j0 > 0) tiles = std::max(tiles, (D.k - j0 + QA_COLS - 1) / QA_COLS);
     }
-    grouped(z1);
-    grouped(z2);
+    if (tiles > 0) {
+      hipLaunchKernelGGL(k_qrb_apply, dim3(tiles, cnt), dim3(QA_THREADS), 0, c.stream, b, j0, 1);
+      HIPC(hipGetLastError());
+    }
   }
   hipLaunchKernelGGL(k_qrb_finish, dim3(g, cnt), dim3(256), 0, c.stream, b);
   HIPC(hipGetLastError());

@@ -16,19 +16,20 @@ namespace {
 
 // TS: storage type of the tensors (float64, or float32 for the convection
 // networks of the mixed mode); the sums run in float64
-template <typename TS>
+template <typename TS, typename IT>
 __global__ __launch_bounds__(256) void k_mpo_csc(const TS *T, TS *Tout, const int *colptr,
                                                  const int *rowidx, const double *val, int KI,
-                                                 int KO, int64_t post, int64_t total,
-                                                 const int *skip) {
+                                                 int KO, IT post, IT total, const int *skip) {
   if (skip && *skip) return;
-  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
-       idx += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t q = idx % post;
-    const int64_t t = idx / post;
-    const int o = (int)(t % KO);
-    const int64_t p = t / KO;
-    const TS *src = T + p * KI * post + q;
+  // IT: 32-bit index arithmetic whenever the tensor fits (the divisions per
+  // element are the kernel's main ALU cost)
+  for (IT idx = blockIdx.x * (IT)blockDim.x + threadIdx.x; idx < total;
+       idx += (IT)gridDim.x * blockDim.x) {
+    const IT q = idx % post;
+    const IT t = idx / post;
+    const int o = (int)(t % (IT)KO);
+    const IT p = t / (IT)KO;
+    const TS *src = T + (int64_t)p * KI * post + q;
     double s = 0.0;
     const int e = colptr[o + 1];
     for (int z = colptr[o]; z < e; ++z) s += val[z] * (double)src[(int64_t)rowidx[z] * post];
@@ -50,21 +51,23 @@ struct MJobs {
   int64_t total;
 };
 
+template <typename IT>
 __global__ __launch_bounds__(256) void k_mpo_csc_grouped(MJobs J, const int *skip) {
   if (skip && *skip) return;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < J.total;
-       e += (int64_t)gridDim.x * blockDim.x) {
+  for (IT e = blockIdx.x * (IT)blockDim.x + threadIdx.x; e < (IT)J.total;
+       e += (IT)gridDim.x * blockDim.x) {
     int ji = 0;
 #pragma unroll
     for (int i = 1; i < 4; ++i)
-      if (i < J.nj && e >= J.j[i].elem0) ji = i;
+      if (i < J.nj && (int64_t)e >= J.j[i].elem0) ji = i;
     const MJob &M = J.j[ji];
-    const int64_t idx = e - M.elem0;
-    const int64_t q = idx % M.post;
-    const int64_t t = idx / M.post;
-    const int o = (int)(t % M.KO);
-    const int64_t p = t / M.KO;
-    const double *src = M.T + p * M.KI * M.post + q;
+    const IT idx = e - (IT)M.elem0;
+    const IT post = (IT)M.post;
+    const IT q = idx % post;
+    const IT t = idx / post;
+    const int o = (int)(t % (IT)M.KO);
+    const IT p = t / (IT)M.KO;
+    const double *src = M.T + (int64_t)p * M.KI * M.post + q;
     double s = 0.0;
     const int end = M.colptr[o + 1];
     for (int z = M.colptr[o]; z < end; ++z) s += M.val[z] * src[(int64_t)M.rowidx[z] * M.post];
@@ -101,7 +104,12 @@ void mpo_layer_grouped(Ctx &c, int nj, const MpoJob *jobs, const int *skip) {
   if (total <= 0) return;
   int64_t g = (total + 255) / 256;
   if (g > 131072) g = 131072;
-  hipLaunchKernelGGL(k_mpo_csc_grouped, dim3((unsigned)g), dim3(256), 0, c.stream, J, skip);
+  if (total + g * 256 < ((int64_t)1 << 31))
+    hipLaunchKernelGGL(k_mpo_csc_grouped<unsigned>, dim3((unsigned)g), dim3(256), 0, c.stream, J,
+                       skip);
+  else
+    hipLaunchKernelGGL(k_mpo_csc_grouped<int64_t>, dim3((unsigned)g), dim3(256), 0, c.stream, J,
+                       skip);
   HIPC(hipGetLastError());
 }
 
@@ -119,13 +127,21 @@ void mpo_layer(Ctx &c, const double *T, double *Tout, const Mpo &W, int site, bo
   const int64_t total = pre * KO * post;
   int64_t g = (total + 255) / 256;
   if (g > 131072) g = 131072;
-  if (f32)
-    hipLaunchKernelGGL(k_mpo_csc<float>, dim3((unsigned)g), dim3(256), 0, c.stream,
-                       reinterpret_cast<const float *>(T), reinterpret_cast<float *>(Tout), cp, ri,
-                       vv, KI, KO, post, total, skip);
+  const bool small = total + (int64_t)g * 256 < ((int64_t)1 << 31);
+  const float *Tf = reinterpret_cast<const float *>(T);
+  float *Tof = reinterpret_cast<float *>(Tout);
+  if (f32 && small)
+    hipLaunchKernelGGL((k_mpo_csc<float, unsigned>), dim3((unsigned)g), dim3(256), 0, c.stream, Tf,
+                       Tof, cp, ri, vv, KI, KO, (unsigned)post, (unsigned)total, skip);
+  else if (f32)
+    hipLaunchKernelGGL((k_mpo_csc<float, int64_t>), dim3((unsigned)g), dim3(256), 0, c.stream, Tf,
+                       Tof, cp, ri, vv, KI, KO, post, total, skip);
+  else if (small)
+    hipLaunchKernelGGL((k_mpo_csc<double, unsigned>), dim3((unsigned)g), dim3(256), 0, c.stream, T,
+                       Tout, cp, ri, vv, KI, KO, (unsigned)post, (unsigned)total, skip);
   else
-    hipLaunchKernelGGL(k_mpo_csc<double>, dim3((unsigned)g), dim3(256), 0, c.stream, T, Tout, cp,
-                       ri, vv, KI, KO, post, total, skip);
+    hipLaunchKernelGGL((k_mpo_csc<double, int64_t>), dim3((unsigned)g), dim3(256), 0, c.stream, T,
+                       Tout, cp, ri, vv, KI, KO, post, total, skip);
   HIPC(hipGetLastError());
 }
 

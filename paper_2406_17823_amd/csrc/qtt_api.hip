@@ -21,7 +21,7 @@ template <typename F>
 int guard(qtt_ctx *ctx, F &&f) {
   if (!ctx) return QTT_E_ARG;
   ctx->c.err.clear();
-  ctx->c.user_ranges.clear();
+  ctx->c.clear_user();
   try {
     HIPC(hipSetDevice(ctx->c.device));
     if (ctx->c.own_stream) HIPC(hipStreamSynchronize(nullptr));
@@ -327,7 +327,7 @@ int qtt_rk4_step_batched(qtt_ctx *ctx, int32_t nflows, qtt_mps *u, const qtt_par
         qtt::Ctx &wc = *c.workers[w];
         for (int f = w; f < nflows; f += W) {
           wc.err.clear();
-          wc.user_ranges.clear();
+          wc.clear_user();
           try {
             reg(wc, u[2 * f]);
             reg(wc, u[2 * f + 1]);

@@ -35,6 +35,7 @@ void *Ctx::raw(const std::string &name, size_t bytes) {
     const size_t alloc = ((bytes + bytes / 4 + 4095) / 4096) * 4096;
     HIPC(hipMalloc(&b.ptr, alloc));
     b.bytes = alloc;
+    ranges_dirty = true;
   }
   return b.ptr;
 }
@@ -42,7 +43,10 @@ void *Ctx::raw(const std::string &name, size_t bytes) {
 void Ctx::sync() { HIPC(hipStreamSynchronize(stream)); }
 
 void Ctx::register_user(const void *p, size_t bytes) {
-  if (p && bytes) user_ranges.push_back({(uintptr_t)p, bytes});
+  if (p && bytes) {
+    user_ranges.push_back({(uintptr_t)p, bytes});
+    ranges_dirty = true;
+  }
 }
 
 void Ctx::check_range(const void *p, int64_t lo, int64_t hi, size_t esize,
@@ -50,13 +54,26 @@ void Ctx::check_range(const void *p, int64_t lo, int64_t hi, size_t esize,
   if (hi < lo) return;
   const uintptr_t a = (uintptr_t)p + (intptr_t)(lo * (int64_t)esize);
   const uintptr_t b = (uintptr_t)p + (intptr_t)((hi + 1) * (int64_t)esize);
-  auto inside = [&](uintptr_t base, size_t bytes) { return a >= base && b <= base + bytes; };
-  for (auto &kv : bufs)
-    if (kv.second.ptr && inside((uintptr_t)kv.second.ptr, kv.second.bytes)) return;
-  for (auto &r : user_ranges)
-    if (inside(r.first, r.second)) return;
-  for (size_t i = 0; i < owned_sizes.size(); ++i)
-    if (inside((uintptr_t)owned[i], owned_sizes[i])) return;
+  if (ranges_dirty) {
+    ranges.clear();
+    for (auto &kv : bufs)
+      if (kv.second.ptr)
+        ranges.push_back({(uintptr_t)kv.second.ptr, (uintptr_t)kv.second.ptr + kv.second.bytes});
+    for (auto &r : user_ranges) ranges.push_back({r.first, r.first + r.second});
+    for (size_t i = 0; i < owned_sizes.size(); ++i)
+      ranges.push_back({(uintptr_t)owned[i], (uintptr_t)owned[i] + owned_sizes[i]});
+    std::sort(ranges.begin(), ranges.end());
+    ranges_dirty = false;
+  }
+  // the allocation with the largest start at or below a (allocations do not
+  // overlap; user ranges may, hence the full scan before failing)
+  auto it = std::upper_bound(ranges.begin(), ranges.end(), a,
+                             [](uintptr_t v, const std::pair<uintptr_t, uintptr_t> &r) {
+                               return v < r.first;
+                             });
+  if (it != ranges.begin() && b <= std::prev(it)->second) return;
+  for (auto &r : ranges)
+    if (a >= r.first && b <= r.second) return;
   std::ostringstream s;
   s << what << ": access [" << lo << ", " << hi << "] outside every known allocation";
   fail(QTT_E_ARG, s.str());
@@ -68,6 +85,7 @@ double *Ctx::alloc_owned(int64_t ndouble) {
   HIPC(hipMalloc(&p, bytes));
   owned.push_back(p);
   owned_sizes.push_back(bytes);
+  ranges_dirty = true;
   return (double *)p;
 }
 

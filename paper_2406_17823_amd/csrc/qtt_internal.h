@@ -162,6 +162,14 @@ struct Ctx {
   void resolve_events();
   // caller buffers registered by the entry point (device address ranges)
   std::vector<std::pair<uintptr_t, size_t>> user_ranges;
+  void clear_user() {
+    user_ranges.clear();
+    ranges_dirty = true;
+  }
+  // every known allocation as [begin, end), sorted by begin (rebuilt after an
+  // allocation or registration), for the range checks of each launch
+  mutable std::vector<std::pair<uintptr_t, uintptr_t>> ranges;
+  mutable bool ranges_dirty = true;
 
   double *buf(const std::string &name, int64_t ndouble);  // grows, contents not kept
   void *raw(const std::string &name, size_t bytes);
