@@ -281,41 +281,50 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_gemm(GemmK g) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) acc[i][j][r] = 0;
 
+  // load slot i of a thread covers element (mm0 + dm i, kk0 + dk i) of the
+  // slice: the thread's first element and a slot step that are fixed for
+  // the whole K loop (consecutive threads along the operand's unit-stride
+  // dimension).  With HOIST the per-slice address is base + i * step + k0 *
+  // sk from per-thread bases kept in registers; the float32 128-tile, whose
+  // two workgroups per compute unit need it under 128 registers, recomputes
+  // the offsets instead.
+  static_assert(NTHR % BM == 0 && NTHR % BN == 0 && NTHR % KD == 0, "slot map");
+  constexpr bool HOIST = !(BM == 128 && GemmKind<T>::value == 1);
+  const int a_mm0 = a_m_unit ? tid % BM : tid / KD, a_kk0 = a_m_unit ? tid / BM : tid % KD;
+  const int a_dm = a_m_unit ? 0 : NTHR / KD, a_dk = a_m_unit ? NTHR / BM : 0;
+  const int b_nn0 = b_n_unit ? tid % BN : tid / KD, b_kk0 = b_n_unit ? tid / BN : tid % KD;
+  const int b_dn = b_n_unit ? 0 : NTHR / KD, b_dk = b_n_unit ? NTHR / BN : 0;
+  int64_t a_base = 0, a_step = 0, b_base = 0, b_step = 0;
+  if constexpr (HOIST) {
+    a_base = aoff + (int64_t)(m0 + a_mm0) * P.sAm + (int64_t)a_kk0 * P.sAk;
+    a_step = (int64_t)a_dm * P.sAm + (int64_t)a_dk * P.sAk;
+    b_base = boff + (int64_t)(n0 + b_nn0) * P.sBn + (int64_t)b_kk0 * P.sBk;
+    b_step = (int64_t)b_dn * P.sBn + (int64_t)b_dk * P.sBk;
+  }
   SA ra[AL];
   SB rb[BL];
   auto gload = [&](int k0) {
+    const int64_t ak = (int64_t)k0 * P.sAk, bk = (int64_t)k0 * P.sBk;
 #pragma unroll
     for (int i = 0; i < AL; ++i) {
-      const int idx = tid + NTHR * i;
-      const int mm = a_m_unit ? (idx % BM) : (idx / KD);
-      const int kk = a_m_unit ? (idx / BM) : (idx % KD);
-      const int gm = m0 + mm, gk = k0 + kk;
-      ra[i] = (gm < P.M && gk < kend) ? Ap[aoff + gm * P.sAm + gk * P.sAk] : SA(0);
+      const int gm = m0 + a_mm0 + a_dm * i, gk = k0 + a_kk0 + a_dk * i;
+      const int64_t off = HOIST ? a_base + i * a_step + ak : aoff + gm * P.sAm + gk * P.sAk;
+      ra[i] = (gm < P.M && gk < kend) ? Ap[off] : SA(0);
     }
 #pragma unroll
     for (int i = 0; i < BL; ++i) {
-      const int idx = tid + NTHR * i;
-      const int nn = b_n_unit ? (idx % BN) : (idx / KD);
-      const int kk = b_n_unit ? (idx / BN) : (idx % KD);
-      const int gn = n0 + nn, gk = k0 + kk;
-      rb[i] = (gn < P.N && gk < kend) ? Bp[boff + gk * P.sBk + gn * P.sBn] : SB(0);
+      const int gn = n0 + b_nn0 + b_dn * i, gk = k0 + b_kk0 + b_dk * i;
+      const int64_t off = HOIST ? b_base + i * b_step + bk : boff + gk * P.sBk + gn * P.sBn;
+      rb[i] = (gn < P.N && gk < kend) ? Bp[off] : SB(0);
     }
   };
   auto sstore = [&](int buf) {
 #pragma unroll
-    for (int i = 0; i < AL; ++i) {
-      const int idx = tid + NTHR * i;
-      const int mm = a_m_unit ? (idx % BM) : (idx / KD);
-      const int kk = a_m_unit ? (idx / BM) : (idx % KD);
-      As[buf][kk][mm] = to_op<T>((double)ra[i]);
-    }
+    for (int i = 0; i < AL; ++i)
+      As[buf][a_kk0 + a_dk * i][a_mm0 + a_dm * i] = to_op<T>((double)ra[i]);
 #pragma unroll
-    for (int i = 0; i < BL; ++i) {
-      const int idx = tid + NTHR * i;
-      const int nn = b_n_unit ? (idx % BN) : (idx / KD);
-      const int kk = b_n_unit ? (idx / BN) : (idx % KD);
-      Bs[buf][kk][nn] = to_op<T>((double)rb[i]);
-    }
+    for (int i = 0; i < BL; ++i)
+      Bs[buf][b_kk0 + b_dk * i][b_nn0 + b_dn * i] = to_op<T>((double)rb[i]);
   };
 
   if (kbeg < kend) {
@@ -338,35 +347,44 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_gemm(GemmK g) {
 
   // D(16x16): lane l holds column l % 16.  float32 / bfloat16: register r is
   // row 4*(l/16) + r; float64 16x16x4: register r is row 4*r + l/16.
+  // Output element (i, j, r) of the lane sits at row rowb + 16 i + rr(r) and
+  // column colb + 16 j: its offset is the lane's base plus a block term 16 i sm
+  // + 16 j sn (uniform) plus rr(r) sm, so the per-element address is a few
+  // adds; the store kind (partials, float32, float64, with beta) is uniform
+  // per problem and chosen outside the element loops.
+  const int rowb = m0 + wm * WTM, colb = n0 + wn * WTN + (lane & 15);
+  auto rr = [&](int r) {
+    return (GemmKind<T>::value == 0) ? (4 * r + (lane >> 4)) : ((lane >> 4) * 4 + r);
+  };
+  auto store_all = [&](auto *Cp, int64_t base, int64_t sm, int64_t sn, double alpha, double beta) {
 #pragma unroll
-  for (int i = 0; i < FM; ++i)
+    for (int i = 0; i < FM; ++i)
 #pragma unroll
-    for (int j = 0; j < FN; ++j)
+      for (int j = 0; j < FN; ++j) {
+        const int gn = colb + j * 16;
+        const int64_t bij = base + (int64_t)(rowb + i * 16) * sm + (int64_t)gn * sn;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = (GemmKind<T>::value == 0) ? (4 * r + (lane >> 4)) : ((lane >> 4) * 4 + r);
-        const int gm = m0 + wm * WTM + i * 16 + row;
-        const int gn = n0 + wn * WTN + j * 16 + (lane & 15);
-        if (gm < P.M && gn < P.N) {
-          if (!P.direct) {
-            const int64_t bidx = (int64_t)b2 * P.B1 + b1;
-            P.part[(((int64_t)ks * P.B1 * P.B2 + bidx) * P.M + gm) * P.N + gn] =
-                (double)acc[i][j][r];
-          } else {
-            const int64_t co = b1 * P.sCb1 + b2 * P.sCb2 + gm * P.sCm + gn * P.sCn;
-            double v = P.alpha * (double)acc[i][j][r];
-            if (P.c32) {
-              float *cp = reinterpret_cast<float *>(P.C) + co;
-              if (P.beta != 0.0) v += P.beta * (double)*cp;
-              *cp = (float)v;
-            } else {
-              double *cp = P.C + co;
-              if (P.beta != 0.0) v += P.beta * *cp;
-              *cp = v;
-            }
+        for (int r = 0; r < 4; ++r) {
+          const int gm = rowb + i * 16 + rr(r);
+          if (gm < P.M && gn < P.N) {
+            auto *cp = Cp + bij + (int64_t)rr(r) * sm;
+            double v = alpha * (double)acc[i][j][r];
+            if (beta != 0.0) v += beta * (double)*cp;
+            *cp = (decltype(+*cp))v;
           }
         }
       }
+  };
+  if (!P.direct) {
+    const int64_t bidx = (int64_t)b2 * P.B1 + b1;
+    store_all(P.part, ((int64_t)ks * P.B1 * P.B2 + bidx) * P.M * P.N, (int64_t)P.N, (int64_t)1,
+              1.0, 0.0);
+  } else if (P.c32) {
+    store_all(reinterpret_cast<float *>(P.C), b1 * P.sCb1 + b2 * P.sCb2, P.sCm, P.sCn, P.alpha,
+              P.beta);
+  } else {
+    store_all(P.C, b1 * P.sCb1 + b2 * P.sCb2, P.sCm, P.sCn, P.alpha, P.beta);
+  }
 }
 
 struct RedSrc {

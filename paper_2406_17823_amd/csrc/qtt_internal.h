@@ -148,6 +148,8 @@ struct Ctx {
   bool capturing = false;             // a stream capture is open
   int64_t cap_launches[KT_KINDS] = {0, 0, 0, 0};
   std::map<std::string, CgGraph> cg_graphs;
+  // iterations of the latest CG solve per (site, direction, preconditioning)
+  std::map<int, int> cg_hist;
   // per-shape GEMM timing (QTT_GEMM_STATS=1), printed when the context ends
   bool shape_stats = false;
   struct ShapeRec {

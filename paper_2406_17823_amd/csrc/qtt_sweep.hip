@@ -37,7 +37,12 @@ namespace qtt {
 namespace {
 
 enum { LAYER_MPO = 0, LAYER_HAD = 1 };
-constexpr int GRAPH_CHUNK = 16;
+// CG iterations are enqueued in an eager first chunk sized from the
+// iteration count of the previous solve at the same site and direction, then
+// in replayed graphs of GRAPH_CHUNK iterations until the device flag says
+// done; iterations enqueued past convergence return at once but still cost a
+// launch each, so both chunks are kept short
+constexpr int GRAPH_CHUNK = 4;
 
 struct Layer {
   int kind = LAYER_MPO;
@@ -556,7 +561,9 @@ struct Sweep {
         }
       }
     };
-    const int first_chunk = 8;
+    const int hkey = (d * 2 + (rev ? 1 : 0)) * 2 + (pre ? 1 : 0);
+    auto h = c.cg_hist.find(hkey);
+    const int first_chunk = (h == c.cg_hist.end()) ? 8 : std::max(2, std::min(64, h->second + 1));
     enqueue_iters(first_chunk);
     HIPC(hipMemcpyAsync(st_host, st, sizeof(CGState), hipMemcpyDeviceToHost, c.stream));
     c.sync();
@@ -591,6 +598,7 @@ struct Sweep {
       HIPC(hipMemcpyAsync(st_host, st, sizeof(CGState), hipMemcpyDeviceToHost, c.stream));
       c.sync();
     }
+    c.cg_hist[hkey] = st_host->iters;
   }
 
   // r = rhs - A x on the device and the CG state reset (warm start from x)
