@@ -390,6 +390,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_gemm(GemmK g) {
 struct RedSrc {
   const double *part;
   int ksplit;
+  double alpha;  // used when the output's sources carry different alphas
 };
 struct RedOut {
   double *C;
@@ -399,7 +400,8 @@ struct RedOut {
   int M, N, B1, B2;
   double alpha, beta;
   int nsrc;
-  RedSrc src[2];
+  int salpha;  // 1: out = sum_q alpha_q (sum over q's splits), else alpha (sum)
+  RedSrc src[GEMM_GROUP];
   int64_t elem0;
   int c32, x32;  // C / X stored as float32
   const double *Y;  // dot partner laid out like C (float64), or null
@@ -421,7 +423,8 @@ __device__ inline double red_wave_sum(double v) {
   return v;
 }
 
-// out = alpha * (sum over sources, splits in order) + beta * X
+// out = alpha * (sum over sources, splits in order) + beta * X, or with
+// per-source alphas sum_q alpha_q (sum over q's splits) + beta * X
 __global__ __launch_bounds__(256) void k_splitk_reduce(RedK R) {
   if (R.skip && *R.skip) return;
   double dacc = 0.0;
@@ -435,14 +438,23 @@ __global__ __launch_bounds__(256) void k_splitk_reduce(RedK R) {
     const int64_t idx = e - O.elem0;
     const int64_t per = (int64_t)O.M * O.N;
     const int64_t tot = per * O.B1 * O.B2;
-    double s = 0.0;
-    for (int q = 0; q < O.nsrc; ++q)
-      for (int k = 0; k < O.src[q].ksplit; ++k) s += O.src[q].part[(int64_t)k * tot + idx];
+    double v = 0.0;
+    if (O.salpha) {
+      for (int q = 0; q < O.nsrc; ++q) {
+        double s = 0.0;
+        for (int k = 0; k < O.src[q].ksplit; ++k) s += O.src[q].part[(int64_t)k * tot + idx];
+        v += O.src[q].alpha * s;
+      }
+    } else {
+      double s = 0.0;
+      for (int q = 0; q < O.nsrc; ++q)
+        for (int k = 0; k < O.src[q].ksplit; ++k) s += O.src[q].part[(int64_t)k * tot + idx];
+      v = O.alpha * s;
+    }
     const int64_t bidx = idx / per;
     const int64_t r = idx % per;
     const int gm = (int)(r / O.N), gn = (int)(r % O.N);
     const int b1 = (int)(bidx % O.B1), b2 = (int)(bidx / O.B1);
-    double v = O.alpha * s;
     if (O.beta != 0.0) {
       const int64_t xo = b1 * O.sXb1 + b2 * O.sXb2 + gm * O.sXm + gn * O.sXn;
       v += O.beta * (O.x32 ? (double)reinterpret_cast<const float *>(O.X)[xo] : O.X[xo]);
@@ -748,7 +760,7 @@ void launch_group(Ctx &c, int np, const Gemm *q, int ngroups, const int *group,
         if (group[i] != gi || keep[i] < 0) continue;
         const Prob &P = g.p[keep[i]];
         if (P.direct) continue;
-        if (O.nsrc >= 2) fail(QTT_E_ARG, "gemm group: at most two problems per output");
+        if (O.nsrc >= GEMM_GROUP) fail(QTT_E_ARG, "gemm group: too many problems per output");
         const Gemm &s = q[i];
         if (!any) {
           O.C = s.C;
@@ -772,11 +784,14 @@ void launch_group(Ctx &c, int np, const Gemm *q, int ngroups, const int *group,
           O.x32 = X[gi] ? 0 : O.c32;
           any = true;
         } else if (s.M != O.M || s.N != O.N || s.B1 != O.B1 || s.B2 != O.B2 || s.C != O.C ||
-                   s.alpha != O.alpha || s.beta != O.beta || s.c32 != (O.c32 != 0)) {
+                   s.beta != O.beta || s.c32 != (O.c32 != 0)) {
           fail(QTT_E_ARG, "gemm group: summed problems must share the output");
+        } else if (s.alpha != O.alpha) {
+          O.salpha = 1;
         }
         O.src[O.nsrc].part = P.part;
         O.src[O.nsrc].ksplit = P.ksplit;
+        O.src[O.nsrc].alpha = s.alpha;
         O.nsrc += 1;
       }
       if (!any) continue;

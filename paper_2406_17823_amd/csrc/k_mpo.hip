@@ -38,8 +38,8 @@ __global__ __launch_bounds__(256) void k_mpo_csc(const TS *T, TS *Tout, const in
 }
 
 struct MJob {
-  const double *T;
-  double *Tout;
+  const void *T;
+  void *Tout;
   const int *colptr, *rowidx;
   const double *val;
   int KI, KO;
@@ -51,7 +51,8 @@ struct MJobs {
   int64_t total;
 };
 
-template <typename IT>
+// up to four layers (one per job) in one launch over the concatenated outputs
+template <typename TS, typename IT>
 __global__ __launch_bounds__(256) void k_mpo_csc_grouped(MJobs J, const int *skip) {
   if (skip && *skip) return;
   for (IT e = blockIdx.x * (IT)blockDim.x + threadIdx.x; e < (IT)J.total;
@@ -67,25 +68,28 @@ __global__ __launch_bounds__(256) void k_mpo_csc_grouped(MJobs J, const int *ski
     const IT t = idx / post;
     const int o = (int)(t % (IT)M.KO);
     const IT p = t / (IT)M.KO;
-    const double *src = M.T + (int64_t)p * M.KI * M.post + q;
+    const TS *src = static_cast<const TS *>(M.T) + (int64_t)p * M.KI * M.post + q;
     double s = 0.0;
     const int end = M.colptr[o + 1];
-    for (int z = M.colptr[o]; z < end; ++z) s += M.val[z] * src[(int64_t)M.rowidx[z] * M.post];
-    M.Tout[idx] = s;
+    for (int z = M.colptr[o]; z < end; ++z)
+      s += M.val[z] * (double)src[(int64_t)M.rowidx[z] * M.post];
+    static_cast<TS *>(M.Tout)[idx] = (TS)s;
   }
 }
 
 }  // namespace
 
-void mpo_layer_grouped(Ctx &c, int nj, const MpoJob *jobs, const int *skip) {
+void mpo_layer_grouped(Ctx &c, int nj, const MpoJob *jobs, const int *skip, bool f32) {
   if (nj < 1 || nj > 4) fail(QTT_E_ARG, "mpo_layer_grouped: 1..4 jobs");
   MJobs J{};
   int64_t total = 0;
+  const size_t es = f32 ? sizeof(float) : sizeof(double);
   for (int i = 0; i < nj; ++i) {
     const MpoJob &s = jobs[i];
+    if (s.pre <= 0 || s.post <= 0) continue;
     const int KI = 4 * s.mi, KO = 4 * s.mo;
-    c.check_range(s.T, 0, s.pre * KI * s.post - 1, 8, "mpo_layer in");
-    c.check_range(s.Tout, 0, s.pre * KO * s.post - 1, 8, "mpo_layer out");
+    c.check_range(s.T, 0, s.pre * KI * s.post - 1, es, "mpo_layer in");
+    c.check_range(s.Tout, 0, s.pre * KO * s.post - 1, es, "mpo_layer out");
     const MpoCsc &z = s.W->csc[s.rev ? 1 : 0];
     MJob &m = J.j[J.nj++];
     m.T = s.T;
@@ -104,12 +108,19 @@ void mpo_layer_grouped(Ctx &c, int nj, const MpoJob *jobs, const int *skip) {
   if (total <= 0) return;
   int64_t g = (total + 255) / 256;
   if (g > 131072) g = 131072;
-  if (total + g * 256 < ((int64_t)1 << 31))
-    hipLaunchKernelGGL(k_mpo_csc_grouped<unsigned>, dim3((unsigned)g), dim3(256), 0, c.stream, J,
-                       skip);
+  const bool small = total + g * 256 < ((int64_t)1 << 31);
+  if (f32 && small)
+    hipLaunchKernelGGL((k_mpo_csc_grouped<float, unsigned>), dim3((unsigned)g), dim3(256), 0,
+                       c.stream, J, skip);
+  else if (f32)
+    hipLaunchKernelGGL((k_mpo_csc_grouped<float, int64_t>), dim3((unsigned)g), dim3(256), 0,
+                       c.stream, J, skip);
+  else if (small)
+    hipLaunchKernelGGL((k_mpo_csc_grouped<double, unsigned>), dim3((unsigned)g), dim3(256), 0,
+                       c.stream, J, skip);
   else
-    hipLaunchKernelGGL(k_mpo_csc_grouped<int64_t>, dim3((unsigned)g), dim3(256), 0, c.stream, J,
-                       skip);
+    hipLaunchKernelGGL((k_mpo_csc_grouped<double, int64_t>), dim3((unsigned)g), dim3(256), 0,
+                       c.stream, J, skip);
   HIPC(hipGetLastError());
 }
 

@@ -223,8 +223,8 @@ struct Gemm {
 constexpr int GEMM_GROUP = 4;
 void gemm(Ctx &c, const Gemm &g);
 // up to GEMM_GROUP problems in one launch; problem i contributes to output
-// group group[i] (a group holds one or two problems sharing C, alpha, beta;
-// two problems are summed); X[group] (nullptr = C) is the beta input.
+// group group[i] (the problems of a group share C and beta and are summed,
+// each scaled by its own alpha); X[group] (nullptr = C) is the beta input.
 // With dot, the reduction kernel also forms sum_groups C . Y[group] (Y laid
 // out like C, float64) into the device scalar out, deterministically (block
 // partials in part, summed in block order by the last block to arrive at the
@@ -277,7 +277,8 @@ struct MpoJob {
   int mi, mo;
 };
 // several MPO layers in one launch (at most 4)
-void mpo_layer_grouped(Ctx &c, int nj, const MpoJob *jobs, const int *skip);
+// f32: every job's tensors are float32 (the pointers are reinterpreted)
+void mpo_layer_grouped(Ctx &c, int nj, const MpoJob *jobs, const int *skip, bool f32 = false);
 void morton_gather(Ctx &c, double *grid, const double *vec, int n);   // vec (Morton) -> grid
 void morton_scatter(Ctx &c, double *vec, const double *grid, int n);  // grid -> vec (Morton)
 void dot(Ctx &c, const double *x, const double *y, int64_t n, double *out_dev);

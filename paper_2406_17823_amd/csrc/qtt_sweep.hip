@@ -69,6 +69,7 @@ struct Net {
   double *env = nullptr;
   std::vector<int64_t> eoff;
   double *T = nullptr;
+  double *tmpn = nullptr;  // the other half of T's ping-pong pair (grouped chains)
   // float32-MFMA networks keep their environments and chain intermediates in
   // float32 storage (half the bytes of the largest tensors of the step); env
   // and T then point at float arrays and eoff counts float elements
@@ -132,9 +133,19 @@ struct Sweep {
     else gemm(c, g);
   }
 
-  // T = chain through site d from the environment at the input bond
-  void chain(const Net &N, int d, bool rev, const double *E, const double *ketcore, double *T,
-             const int *skip) {
+  // one step of a network chain: a GEMM or an MPO layer
+  struct ChainStep {
+    bool mpo = false;
+    Gemm g;
+    MpoJob j{};
+  };
+
+  // the steps of the chain through site d from the environment at the input
+  // bond (steps[0] contracts the ket core, then the layers from the inner
+  // one out); the result lands in T, with tmp as the other half of the
+  // ping-pong pair.  Returns the number of steps (1 + N.nl).
+  int chain_plan(const Net &N, int d, bool rev, const double *E, const double *ketcore,
+                 double *T, double *tmp_buf, const int *skip, ChainStep *steps) {
     const int bi = rev ? d + 1 : d, bo = rev ? d : d + 1;
     const int a = v[N.bra].bond[bi];
     const Mps &kx = ketmps(N);
@@ -147,10 +158,12 @@ struct Sweep {
       mo[l] = N.lay[l].bond(bo);
       Pin *= mi[l];
     }
-    double *bufs[2] = {T, tmp};
+    double *bufs[2] = {T, tmp_buf};
     int cur = (pl % 2 == 0) ? 0 : 1;
+    int ns = 0;
     {
-      Gemm q;
+      ChainStep &st0 = steps[ns++];
+      Gemm &q = st0.g;
       q.M = (int)(a * Pin);
       q.N = 4 * gp;
       q.K = g;
@@ -165,7 +178,6 @@ struct Sweep {
       q.sCn = 1;
       q.skip = skip;
       q.a32 = q.c32 = N.f32s();
-      gemm_for(N, q);
     }
     for (int l = pl - 1; l >= 0; --l) {
       int64_t pre = a, post = gp;
@@ -173,21 +185,19 @@ struct Sweep {
       for (int i = l + 1; i < pl; ++i) post *= mo[i];
       const double *src = bufs[cur];
       double *dst = bufs[1 - cur];
-      const double *core = N.lay[l].core(d, rev);
+      ChainStep &st = steps[ns++];
       if (N.lay[l].kind == LAYER_MPO) {
-        mpo_layer(c, src, dst, *N.lay[l].mpo, d, rev, pre, mi[l], mo[l], post, skip, N.f32s());
-        cur = 1 - cur;
-        continue;
-      }
-      Gemm q;
-      q.skip = skip;
-      {
+        st.mpo = true;
+        st.j = MpoJob{src, dst, N.lay[l].mpo, d, rev, pre, post, mi[l], mo[l]};
+      } else {
+        Gemm &q = st.g;
+        q.skip = skip;
         q.B1 = (int)pre;
         q.B2 = 4;
         q.M = mo[l];
         q.N = (int)post;
         q.K = mi[l];
-        q.A = core;
+        q.A = N.lay[l].core(d, rev);
         q.sAm = 1;
         q.sAk = 4 * mo[l];
         q.sAb1 = 0;
@@ -204,19 +214,32 @@ struct Sweep {
         q.sCb2 = mo[l] * post;
         q.b32 = q.c32 = N.f32s();
       }
-      gemm_for(N, q);
       cur = 1 - cur;
+    }
+    return ns;
+  }
+
+  // T = chain through site d from the environment at the input bond
+  void chain(const Net &N, int d, bool rev, const double *E, const double *ketcore, double *T,
+             const int *skip) {
+    ChainStep steps[3];
+    const int ns = chain_plan(N, d, rev, E, ketcore, T, tmp, skip, steps);
+    for (int t = 0; t < ns; ++t) {
+      const ChainStep &st = steps[t];
+      if (st.mpo)
+        mpo_layer(c, st.j.T, st.j.Tout, *st.j.W, st.j.site, st.j.rev, st.j.pre, st.j.mi, st.j.mo,
+                  st.j.post, skip, N.f32s());
+      else
+        gemm_for(N, st.g);
     }
   }
 
   // out_i += alpha * (T contracted with the opposite environment)
-  void open_into(const Net &N, int d, bool rev, const double *T, double *out, double alpha,
-                 const int *skip) {
+  Gemm open_gemm(const Net &N, int d, bool rev, const double *T, double *out, double alpha) {
     const int al = v[N.bra].bond[d], ar = v[N.bra].bond[d + 1];
     const int bo = rev ? d : d + 1;
     const int64_t rest = env_size(N, bo) / v[N.bra].bond[bo];
     Gemm q;
-    q.skip = skip;
     q.alpha = alpha;
     q.beta = 1.0;
     q.a32 = q.b32 = N.f32s();  // T and the environment; out is float64
@@ -252,11 +275,15 @@ struct Sweep {
       q.sCn = 4 * ar;
       q.sCb2 = ar;
     }
-    gemm_for(N, q);
+    return q;
+  }
+
+  void open_into(const Net &N, int d, bool rev, const double *T, double *out, double alpha) {
+    gemm_for(N, open_gemm(N, d, rev, T, out, alpha));
   }
 
   // environment at the output bond from T and the (new) bra core of site d
-  void env_from_T(const Net &N, int d, bool rev, const double *T) {
+  Gemm env_gemm(const Net &N, int d, bool rev, const double *T) {
     const int al = v[N.bra].bond[d], ar = v[N.bra].bond[d + 1];
     const int bo = rev ? d : d + 1;
     const int64_t rest = env_size(N, bo) / v[N.bra].bond[bo];
@@ -283,8 +310,92 @@ struct Sweep {
     q.sCm = rest;
     q.sCn = 1;
     q.b32 = q.c32 = N.f32s();
-    gemm_for(N, q);
+    return q;
   }
+
+  void env_from_T(const Net &N, int d, bool rev, const double *T) {
+    gemm_for(N, env_gemm(N, d, rev, T));
+  }
+
+  // ---- grouped network contractions: the networks of one group share a
+  // contraction precision (float64 or float32 MFMA) and each step of their
+  // chains, their environment updates and their right-hand-side terms go
+  // out as one grouped launch for the whole group (the GEMMs of a step can
+  // have different shapes; MPO layers of a step share one launch)
+  static bool groupable(const Net &N) { return N.prec != QTT_PREC_BF16X3; }
+
+  void launch_gemms(int cnt, Gemm *q, bool f32, bool sum_outputs) {
+    int grp[GEMM_GROUP];
+    const double *C[GEMM_GROUP];
+    const double *X[GEMM_GROUP] = {nullptr, nullptr, nullptr, nullptr};
+    int ng = 0;
+    for (int k = 0; k < cnt; ++k) {
+      int gi = -1;
+      if (sum_outputs)
+        for (int u = 0; u < ng; ++u)
+          if (C[u] == q[k].C) gi = u;
+      if (gi < 0) {
+        C[ng] = q[k].C;
+        gi = ng++;
+      }
+      grp[k] = gi;
+    }
+    gemm_grouped(c, cnt, q, ng, grp, X, nullptr, f32);
+  }
+
+  // chains of the group's networks; E[k] is network k's input environment,
+  // T[k] / tmp_k[k] its result and scratch
+  void chain_group(int cnt, Net *const *Ns, int d, bool rev, const double *const *E,
+                   double *const *T, double *const *tmp_k) {
+    ChainStep steps[GEMM_GROUP][3];
+    int ns[GEMM_GROUP], nmax = 0;
+    for (int k = 0; k < cnt; ++k) {
+      ns[k] = chain_plan(*Ns[k], d, rev, E[k], ket_core(*Ns[k], d, rev), T[k], tmp_k[k], nullptr,
+                         steps[k]);
+      nmax = std::max(nmax, ns[k]);
+    }
+    const bool f32 = Ns[0]->f32s();
+    for (int t = 0; t < nmax; ++t) {
+      Gemm q[GEMM_GROUP];
+      MpoJob j[GEMM_GROUP];
+      int nq = 0, nj = 0;
+      for (int k = 0; k < cnt; ++k) {
+        if (t >= ns[k]) continue;
+        if (steps[k][t].mpo) j[nj++] = steps[k][t].j;
+        else q[nq++] = steps[k][t].g;
+      }
+      if (nq) launch_gemms(nq, q, f32, false);
+      if (nj) mpo_layer_grouped(c, nj, j, nullptr, f32);
+    }
+  }
+
+  void env_group(int cnt, Net *const *Ns, int d, bool rev, double *const *T) {
+    Gemm q[GEMM_GROUP];
+    for (int k = 0; k < cnt; ++k) q[k] = env_gemm(*Ns[k], d, rev, T[k]);
+    launch_gemms(cnt, q, Ns[0]->f32s(), false);
+  }
+
+  // groups of up to GEMM_GROUP networks of one precision, in list order
+  static std::vector<std::vector<Net *>> make_groups(const std::vector<Net *> &nets) {
+    std::vector<std::vector<Net *>> out;
+    std::vector<Net *> open[3];
+    for (Net *N : nets) {
+      if (!groupable(*N)) {
+        out.push_back({N});
+        continue;
+      }
+      auto &o = open[N->prec == QTT_PREC_F32 ? 1 : 0];
+      o.push_back(N);
+      if ((int)o.size() == GEMM_GROUP) {
+        out.push_back(o);
+        o.clear();
+      }
+    }
+    for (auto &o : open)
+      if (!o.empty()) out.push_back(o);
+    return out;
+  }
+  std::vector<std::vector<Net *>> rhs_groups, pen_groups;
 
   const double *ket_core(const Net &N, int d, bool rev) const {
     if (N.trial_ket) return rev ? vrev[N.ket_comp] + v[N.ket_comp].off(d) : v[N.ket_comp].core(d);
@@ -321,7 +432,9 @@ struct Sweep {
       int64_t own = 1;
       for (int d = 0; d < n; ++d) own = std::max(own, chain_max(*N, d));
       tmx = std::max(tmx, own);
-      if (!N->trial_ket) N->T = c.buf("sw_T" + std::to_string(idx), f ? (own + 1) / 2 : own);
+      N->T = c.buf("sw_T" + std::to_string(idx), f ? (own + 1) / 2 : own);
+      if (groupable(*N))
+        N->tmpn = c.buf("sw_Tb" + std::to_string(idx), f ? (own + 1) / 2 : own);
       ++idx;
     }
     tmp = c.buf("sw_tmp", tmx);
@@ -632,10 +745,29 @@ struct Sweep {
     fill(c, rhs, ntot, 0.0);
     double *rh[2] = {rhs, rhs + s0};
     auto t0 = std::chrono::steady_clock::now();
-    for (Net &N : rhs_nets()) {
-      const double *E = rev ? N.envp(d + 1) : N.envp(d);
-      chain(N, d, rev, E, ket_core(N, d, rev), N.T, nullptr);
-      open_into(N, d, rev, N.T, rh[N.bra], N.coef, nullptr);
+    for (auto &grp : rhs_groups) {
+      const int cnt = (int)grp.size();
+      if (!groupable(*grp[0])) {
+        for (Net *N : grp) {
+          const double *E = rev ? N->envp(d + 1) : N->envp(d);
+          chain(*N, d, rev, E, ket_core(*N, d, rev), N->T, nullptr);
+          open_into(*N, d, rev, N->T, rh[N->bra], N->coef);
+        }
+        continue;
+      }
+      const double *E[GEMM_GROUP];
+      double *T[GEMM_GROUP], *tm[GEMM_GROUP];
+      Gemm q[GEMM_GROUP];
+      for (int k = 0; k < cnt; ++k) {
+        E[k] = rev ? grp[k]->envp(d + 1) : grp[k]->envp(d);
+        T[k] = grp[k]->T;
+        tm[k] = grp[k]->tmpn;
+      }
+      chain_group(cnt, grp.data(), d, rev, E, T, tm);
+      // the terms of one component are summed in the reduction of one launch
+      for (int k = 0; k < cnt; ++k)
+        q[k] = open_gemm(*grp[k], d, rev, grp[k]->T, rh[grp[k]->bra], grp[k]->coef);
+      launch_gemms(cnt, q, grp[0]->f32s(), true);
     }
     auto load_guess = [&] {
       HIPC(hipMemcpyAsync(x, v[0].core(d), s0 * sizeof(double), hipMemcpyDeviceToDevice,
@@ -770,13 +902,43 @@ struct Sweep {
     }
   }
 
+  // environments at the new bond after a shift: the right-hand-side
+  // networks reuse the chain results of the local step (their ket does not
+  // change), the penalty networks contract the new trial cores
   void update_envs(int d, bool rev) {
-    for (Net &N : rhs) env_from_T(N, d, rev, N.T);
-    for (Net &N : pen) {
-      const double *E = rev ? N.env + N.eoff[d + 1] : N.env + N.eoff[d];
-      chain(N, d, rev, E, ket_core(N, d, rev), Tpen, nullptr);
-      env_from_T(N, d, rev, Tpen);
+    for (auto &grp : rhs_groups) {
+      if (!groupable(*grp[0])) {
+        for (Net *N : grp) env_from_T(*N, d, rev, N->T);
+        continue;
+      }
+      double *T[GEMM_GROUP];
+      for (size_t k = 0; k < grp.size(); ++k) T[k] = grp[k]->T;
+      env_group((int)grp.size(), grp.data(), d, rev, T);
     }
+    for (auto &grp : pen_groups) envs_through(grp, d, rev);
+  }
+
+  // chain and environment update of every network of a group through site
+  // d, from the environment at the input bond
+  void envs_through(std::vector<Net *> &grp, int d, bool rev) {
+    const int cnt = (int)grp.size();
+    if (!groupable(*grp[0])) {
+      for (Net *N : grp) {
+        const double *E = rev ? N->envp(d + 1) : N->envp(d);
+        chain(*N, d, rev, E, ket_core(*N, d, rev), Tpen, nullptr);
+        env_from_T(*N, d, rev, Tpen);
+      }
+      return;
+    }
+    const double *E[GEMM_GROUP];
+    double *T[GEMM_GROUP], *tm[GEMM_GROUP];
+    for (int k = 0; k < cnt; ++k) {
+      E[k] = rev ? grp[k]->envp(d + 1) : grp[k]->envp(d);
+      T[k] = grp[k]->T;
+      tm[k] = grp[k]->tmpn;
+    }
+    chain_group(cnt, grp.data(), d, rev, E, T, tm);
+    env_group(cnt, grp.data(), d, rev, T);
   }
 
   double norm_sq_site0() {
@@ -934,17 +1096,26 @@ void project(Ctx &c, const Mps a[2], const Mps b[2], double h, const qtt_params 
   for (Net &N : S.pen) all.push_back(&N);
   S.alloc(all);
   S.alloc_pen_tmp();
+  {
+    std::vector<Net *> r, q;
+    for (Net &N : S.rhs) r.push_back(&N);
+    for (Net &N : S.pen) q.push_back(&N);
+    S.rhs_groups = Sweep::make_groups(r);
+    S.pen_groups = Sweep::make_groups(q);
+  }
 
   // right environments, sites n-1 .. 1; the overlap and penalty networks do
   // not involve b and are copied from the first stage when it is cached
   auto b_free = [](const Net &N) { return N.nl == 0 || N.trial_ket; };
   auto env_total = [&](const Net &N) { return N.eoff[n] + 1; };
-  for (int d = n - 1; d >= 1; --d)
-    for (Net *N : all) {
-      if (reuse && b_free(*N)) continue;
-      S.chain(*N, d, true, N->envp(d + 1), S.ket_core(*N, d, true), S.Tpen, nullptr);
-      S.env_from_T(*N, d, true, S.Tpen);
-    }
+  {
+    std::vector<Net *> todo;
+    for (Net *N : all)
+      if (!(reuse && b_free(*N))) todo.push_back(N);
+    auto groups = Sweep::make_groups(todo);
+    for (int d = n - 1; d >= 1; --d)
+      for (auto &grp : groups) S.envs_through(grp, d, true);
+  }
   for (size_t idx = 0; idx < all.size(); ++idx) {
     if (!cache || !b_free(*all[idx])) continue;
     double *saved = c.buf("rk4c_env" + std::to_string(idx), env_total(*all[idx]));
