@@ -175,54 +175,6 @@ __global__ __launch_bounds__(CG_THREADS) void k_cg_update(double *x, double *r, 
   }
 }
 
-// single-reduction CG step (see qtt_cg.h); every block derives alpha and beta
-// from the same device scalars, the last block stores the new ones
-__global__ __launch_bounds__(CG_THREADS) void k_cg1_update(double *x, double *r, double *p,
-                                                           double *s, const double *w, int64_t n,
-                                                           CGState *st, double *part) {
-  if (st->done) return;
-  __shared__ double sh[4];
-  const double g = st->gamma, d = st->delta;
-  const bool first = st->first != 0;
-  const double beta = first ? 0.0 : g / st->gamma_prev;
-  const double alpha = first ? g / d : g / (d - beta * g / st->alpha_prev);
-  double a = 0.0;
-  for (int64_t i = blockIdx.x * (int64_t)CG_THREADS + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * CG_THREADS) {
-    // first step: p and s start from r and w (their old contents are not read)
-    const double pi = first ? r[i] : r[i] + beta * p[i];
-    const double si = first ? w[i] : w[i] + beta * s[i];
-    p[i] = pi;
-    s[i] = si;
-    x[i] += alpha * pi;
-    const double ri = r[i] - alpha * si;
-    r[i] = ri;
-    a += ri * ri;
-  }
-  const double sa = block_sum(a, sh);
-  if (arrive_last(st, part, blockIdx.x, sa, 0.0)) {
-    double rr, dummy;
-    sum_parts(part, gridDim.x, rr, dummy);
-    if (threadIdx.x == 0) {
-      st->iters += 1;
-      st->gamma_prev = g;
-      st->alpha_prev = alpha;
-      st->gamma = rr;
-      st->first = 0;
-      st->rr_new = rr;
-      if (!(rr == rr)) {
-        st->done = 1;  // NaN: stop, not converged
-      } else if (rr <= st->tol2) {
-        st->done = 1;
-        st->converged = 1;
-      } else if (st->iters >= st->maxit) {
-        st->done = 1;
-      }
-      st->counter = 0;
-    }
-  }
-}
-
 // unpreconditioned: beta = rr_new / rr, p = r + beta p
 __global__ __launch_bounds__(CG_THREADS) void k_cg_pupdate(const double *r, double *p, int64_t n,
                                                            CGState *st) {
@@ -331,13 +283,6 @@ void cg_update(Ctx &c, double *x, double *r, const double *p, const double *q, i
 
 void cg_pupdate(Ctx &c, const double *r, double *p, int64_t n, CGState *st) {
   hipLaunchKernelGGL(k_cg_pupdate, dim3(cg_grid(n)), dim3(CG_THREADS), 0, c.stream, r, p, n, st);
-  HIPC(hipGetLastError());
-}
-
-void cg1_update(Ctx &c, double *x, double *r, double *p, double *s, const double *w, int64_t n,
-                CGState *st, double *part) {
-  hipLaunchKernelGGL(k_cg1_update, dim3(cg_grid(n)), dim3(CG_THREADS), 0, c.stream, x, r, p, s, w,
-                     n, st, part);
   HIPC(hipGetLastError());
 }
 

@@ -27,6 +27,7 @@
 // (deterministic).  That kernel also sums several problems into one output
 // (the two pair terms j = 1, 2 of y_i) and adds a separate input X.
 #include "qtt_internal.h"
+#include "qtt_cg.h"
 
 #include <cstdio>
 #include <type_traits>
@@ -71,6 +72,7 @@ struct Prob {
   double alpha, beta;
   double *part;  // partial mode: part[ks][b][m][n]
   int c32;  // result stored as float32 (operand storage is a template argument)
+  const double *Bw, *Bs;  // CG operand: B read as B - alpha (Bw + beta Bs)
 };
 
 struct GemmK {
@@ -79,6 +81,7 @@ struct GemmK {
   const int *skip;
   double *flop_ctr;
   double flops;
+  const CGState *cgst;  // alpha and beta of the CG operand
 };
 
 // one KT-deep slice of MFMAs for a wave's FM x FN blocks of 16 x 16
@@ -215,11 +218,20 @@ __device__ inline bf3 to_op<bf3>(double v) {
 // and float64 MFMAs accumulate in k order, so KD changes no result bit
 // SA, SB: storage types of A and B (float64, or float32 for the convection
 // networks of the mixed mode, with T = float); the operand words go through
-// registers in their storage type and are converted on the way into LDS
+// registers in their storage type and are converted on the way into LDS.
+// BCG: B is the next CG residual r - alpha (w + beta s), formed as it loads
 template <typename T, int BM, int BN, int WGM, int WGN, int KD, typename SA = double,
-          typename SB = double>
+          typename SB = double, bool BCG = false>
 __global__ __launch_bounds__(64 * WGM * WGN) void k_gemm(GemmK g) {
   if (g.skip && *g.skip) return;
+  double cg_a = 0.0, cg_b = 0.0;
+  bool cg_first = false;
+  if constexpr (BCG) {
+    const double gm = g.cgst->gamma, dl = g.cgst->delta;
+    cg_first = g.cgst->first != 0;
+    cg_b = cg_first ? 0.0 : gm / g.cgst->gamma_prev;
+    cg_a = cg_first ? gm / dl : gm / (dl - cg_b * gm / g.cgst->alpha_prev);
+  }
   if (g.flop_ctr && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(g.flop_ctr, g.flops);
   constexpr int NTHR = 64 * WGM * WGN;
   constexpr int WTM = BM / WGM, WTN = BN / WGN;  // wave tile
@@ -315,7 +327,16 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_gemm(GemmK g) {
     for (int i = 0; i < BL; ++i) {
       const int gn = n0 + b_nn0 + b_dn * i, gk = k0 + b_kk0 + b_dk * i;
       const int64_t off = HOIST ? b_base + i * b_step + bk : boff + gk * P.sBk + gn * P.sBn;
-      rb[i] = (gn < P.N && gk < kend) ? Bp[off] : SB(0);
+      if constexpr (BCG) {
+        // first step: s starts from w (its old contents are not read)
+        rb[i] = 0.0;
+        if (gn < P.N && gk < kend) {
+          const double w = P.Bw[off];
+          rb[i] = Bp[off] - cg_a * (cg_first ? w : w + cg_b * P.Bs[off]);
+        }
+      } else {
+        rb[i] = (gn < P.N && gk < kend) ? Bp[off] : SB(0);
+      }
     }
   };
   auto sstore = [&](int buf) {
@@ -405,6 +426,7 @@ struct RedOut {
   int64_t elem0;
   int c32, x32;  // C / X stored as float32
   const double *Y;  // dot partner laid out like C (float64), or null
+  int64_t cgoff;    // fused CG step: position of C's element 0 in the vectors
 };
 struct RedK {
   int nout;
@@ -415,6 +437,9 @@ struct RedK {
   // to arrive (counter dctr, reset to 0 by it) sums them in block order
   double *dpart, *dout;
   unsigned *dctr;
+  // fused CG step (cst non-null): the outputs update the CG vectors
+  CGState *cst;
+  double *cx, *cr, *cw, *cp, *cs, *cz, *cpart;
 };
 
 __device__ inline double red_wave_sum(double v) {
@@ -428,6 +453,16 @@ __device__ inline double red_wave_sum(double v) {
 __global__ __launch_bounds__(256) void k_splitk_reduce(RedK R) {
   if (R.skip && *R.skip) return;
   double dacc = 0.0;
+  // fused CG step: alpha and beta of this iteration (see GemmCg)
+  double cg_a = 0.0, cg_b = 0.0, cg_rr = 0.0, cg_wr = 0.0, cg_g = 0.0;
+  bool cg_first = false;
+  if (R.cst) {
+    cg_g = R.cst->gamma;
+    const double dl = R.cst->delta;
+    cg_first = R.cst->first != 0;
+    cg_b = cg_first ? 0.0 : cg_g / R.cst->gamma_prev;
+    cg_a = cg_first ? cg_g / dl : cg_g / (dl - cg_b * cg_g / R.cst->alpha_prev);
+  }
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < R.total;
        e += (int64_t)gridDim.x * blockDim.x) {
     int oi = 0;
@@ -455,14 +490,88 @@ __global__ __launch_bounds__(256) void k_splitk_reduce(RedK R) {
     const int64_t r = idx % per;
     const int gm = (int)(r / O.N), gn = (int)(r % O.N);
     const int b1 = (int)(bidx % O.B1), b2 = (int)(bidx / O.B1);
-    if (O.beta != 0.0) {
+    if (O.beta != 0.0 && !R.cst) {
       const int64_t xo = b1 * O.sXb1 + b2 * O.sXb2 + gm * O.sXm + gn * O.sXn;
       v += O.beta * (O.x32 ? (double)reinterpret_cast<const float *>(O.X)[xo] : O.X[xo]);
     }
     const int64_t co = b1 * O.sCb1 + b2 * O.sCb2 + gm * O.sCm + gn * O.sCn;
+    if (R.cst) {
+      // first step: s and p start from w and r (old contents unread); the
+      // beta term of the matvec takes the new residual
+      const int64_t j = O.cgoff + co;
+      const double wi = R.cw[j], ri = R.cr[j];
+      const double si = cg_first ? wi : wi + cg_b * R.cs[j];
+      const double pi = cg_first ? ri : ri + cg_b * R.cp[j];
+      R.cs[j] = si;
+      R.cp[j] = pi;
+      R.cx[j] += cg_a * pi;
+      const double rn = ri - cg_a * si;
+      const double wn = v + O.beta * rn;
+      R.cr[j] = rn;
+      R.cw[j] = wn;
+      cg_rr += rn * rn;
+      cg_wr += wn * rn;
+      continue;
+    }
     if (O.c32) reinterpret_cast<float *>(O.C)[co] = (float)v;
     else O.C[co] = v;
     if (O.Y) dacc += v * O.Y[co];
+  }
+  if (R.cst) {
+    __shared__ double shc[2][4];
+    __shared__ bool lastc;
+    cg_rr = red_wave_sum(cg_rr);
+    cg_wr = red_wave_sum(cg_wr);
+    if ((threadIdx.x & 63) == 0) {
+      shc[0][threadIdx.x >> 6] = cg_rr;
+      shc[1][threadIdx.x >> 6] = cg_wr;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      R.cpart[2 * blockIdx.x] = (shc[0][0] + shc[0][1]) + (shc[0][2] + shc[0][3]);
+      R.cpart[2 * blockIdx.x + 1] = (shc[1][0] + shc[1][1]) + (shc[1][2] + shc[1][3]);
+      __threadfence();
+      lastc = (atomicAdd(&R.cst->counter, 1u) == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (!lastc) return;
+    __threadfence();
+    const volatile double *vp = R.cpart;
+    double a = 0.0, b = 0.0;
+    for (int i = threadIdx.x; i < (int)gridDim.x; i += 256) {
+      a += vp[2 * i];
+      b += vp[2 * i + 1];
+    }
+    a = red_wave_sum(a);
+    b = red_wave_sum(b);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) {
+      shc[0][threadIdx.x >> 6] = a;
+      shc[1][threadIdx.x >> 6] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const double rr = (shc[0][0] + shc[0][1]) + (shc[0][2] + shc[0][3]);
+      const double wr = (shc[1][0] + shc[1][1]) + (shc[1][2] + shc[1][3]);
+      CGState *st = R.cst;
+      st->iters += 1;
+      st->gamma_prev = cg_g;
+      st->alpha_prev = cg_a;
+      st->gamma = rr;
+      st->delta = wr;
+      st->first = 0;
+      st->rr_new = rr;
+      if (!(rr == rr)) {
+        st->done = 1;  // NaN: stop, not converged
+      } else if (rr <= st->tol2) {
+        st->done = 1;
+        st->converged = 1;
+      } else if (st->iters >= st->maxit) {
+        st->done = 1;
+      }
+      st->counter = 0;
+    }
+    return;
   }
   if (!R.dout) return;
   __shared__ double sh[4];
@@ -516,6 +625,13 @@ void check_operands(Ctx &c, const Gemm &q) {
 template <typename T>
 void launch_tile(int MT, int sa, int sb, int64_t blocks, hipStream_t st, const GemmK &g) {
   const dim3 grid((unsigned)blocks);
+  if (g.cgst) {
+    if (!std::is_same<T, double>::value || MT != 64 || sa || sb)
+      fail(QTT_E_ARG, "gemm: the CG operand needs float64 64-tiles");
+    hipLaunchKernelGGL((k_gemm<double, 64, 64, 2, 2, 16, double, double, true>), grid,
+                       dim3(256), 0, st, g);
+    return;
+  }
   if constexpr (std::is_same<T, float>::value) {
     if (MT == 128) {
       if (sa && sb)
@@ -599,7 +715,8 @@ int tuned_tile(Ctx &c, int np, const Gemm *q, int ngroups, const double *const *
 // one or two problems that share C; X[group] is the beta input, nullptr = C).
 template <typename T>
 void launch_group(Ctx &c, int np, const Gemm *q, int ngroups, const int *group,
-                  const double *const *X, const int *skip, const GemmDot *dot = nullptr) {
+                  const double *const *X, const int *skip, const GemmDot *dot = nullptr,
+                  const GemmCg *cg = nullptr) {
   GemmK g{};
   g.np = 0;
   g.skip = skip;
@@ -615,6 +732,12 @@ void launch_group(Ctx &c, int np, const Gemm *q, int ngroups, const int *group,
   for (int i = 1; i < np; ++i)
     if (q[i].a32 != q[0].a32 || q[i].b32 != q[0].b32)
       fail(QTT_E_ARG, "gemm group: operand storage types must agree");
+  g.cgst = q[0].cgst;
+  for (int i = 0; i < np; ++i) {
+    if (q[i].cgst != g.cgst) fail(QTT_E_ARG, "gemm group: CG operands must agree");
+    if (q[i].cgst && (!q[i].Bw || !q[i].Bs || q[i].b32))
+      fail(QTT_E_ARG, "gemm: the CG operand needs float64 w and s");
+  }
   int64_t part_need = 0;
   int64_t part_off[GEMM_GROUP] = {0};
   int keep[GEMM_GROUP];
@@ -664,6 +787,8 @@ void launch_group(Ctx &c, int np, const Gemm *q, int ngroups, const int *group,
       P.beta = s.beta;
       P.part = nullptr;
       P.c32 = s.c32 ? 1 : 0;
+      P.Bw = s.Bw;
+      P.Bs = s.Bs;
       g.flops += 2.0 * s.M * (double)s.N * s.K * s.B1 * s.B2;
       const int64_t out_tiles = (int64_t)P.tm * P.tn * P.B1 * P.B2;
       P.ksplit = 1;
@@ -689,11 +814,24 @@ void launch_group(Ctx &c, int np, const Gemm *q, int ngroups, const int *group,
     }
   };
   for (int i = 0; i < np; ++i)
-    if (q[i].M > 0 && q[i].N > 0 && q[i].B1 > 0 && q[i].B2 > 0) check_operands(c, q[i]);
+    if (q[i].M > 0 && q[i].N > 0 && q[i].B1 > 0 && q[i].B2 > 0) {
+      check_operands(c, q[i]);
+      if (q[i].cgst && q[i].K > 0) {
+        int64_t lo = 0, hi = 0;
+        span(lo, hi, q[i].K, q[i].sBk);
+        span(lo, hi, q[i].N, q[i].sBn);
+        span(lo, hi, q[i].B1, q[i].sBb1);
+        span(lo, hi, q[i].B2, q[i].sBb2);
+        c.check_range(q[i].Bw, lo, hi, sizeof(double), "gemm CG w");
+        c.check_range(q[i].Bs, lo, hi, sizeof(double), "gemm CG s");
+        c.check_range(q[i].cgst, 0, 0, sizeof(CGState), "gemm CG state");
+      }
+    }
   // tile size: 64 x 64 while split-K may be needed; otherwise the tuned
   // choice for this shape, or 128 x 128 when there is one such tile per CU
   int MT = (!may_split && tiles128 >= 256) ? 128 : 64;
-  if (!may_split) MT = tuned_tile<T>(c, np, q, ngroups, X, MT, build, g, blocks, part_need);
+  if (g.cgst) MT = 64;  // the CG operand exists for float64 64-tiles only
+  else if (!may_split) MT = tuned_tile<T>(c, np, q, ngroups, X, MT, build, g, blocks, part_need);
   build(MT);
   if (g.np == 0) return;
   if (blocks > 0x7fffffffLL) fail(QTT_E_UNSUPPORTED, "gemm grid too large");
@@ -796,6 +934,13 @@ void launch_group(Ctx &c, int np, const Gemm *q, int ngroups, const int *group,
       }
       if (!any) continue;
       if (R.nout >= GEMM_GROUP) fail(QTT_E_ARG, "gemm group: too many reduced outputs");
+      if (cg) {
+        O.cgoff = cg->off[gi];
+        if (O.c32 || O.B1 != 1 || O.B2 != 1 || O.sCn != 1 || O.sCm != O.N)
+          fail(QTT_E_ARG, "gemm cg: packed float64 outputs only");
+        if (O.cgoff < 0 || O.cgoff + (int64_t)O.M * O.N > cg->n)
+          fail(QTT_E_ARG, "gemm cg: output outside the vectors");
+      }
       if (dot) {
         O.Y = dot->Y[gi];
         int64_t lo = 0, hi = 0;
@@ -821,6 +966,20 @@ void launch_group(Ctx &c, int np, const Gemm *q, int ngroups, const int *group,
     R.total = total;
     if (total > 0) {
       unsigned rg = (unsigned)std::min<int64_t>(4096, (total + 255) / 256);
+      if (cg) {
+        rg = std::min<unsigned>(rg, (unsigned)cg->nparts);
+        c.check_range(cg->part, 0, 2 * (int64_t)rg - 1, sizeof(double), "gemm cg partials");
+        c.check_range(cg->st, 0, 0, sizeof(CGState), "gemm cg state");
+        for (double *vv : {cg->x, cg->r, cg->w, cg->p, cg->s})
+          c.check_range(vv, 0, cg->n - 1, sizeof(double), "gemm cg vector");
+        R.cst = cg->st;
+        R.cx = cg->x;
+        R.cr = cg->r;
+        R.cw = cg->w;
+        R.cp = cg->p;
+        R.cs = cg->s;
+        R.cpart = cg->part;
+      }
       if (dot) {
         rg = std::min<unsigned>(rg, (unsigned)dot->nparts);
         c.check_range(dot->part, 0, rg - 1, sizeof(double), "gemm dot partials");
@@ -832,12 +991,12 @@ void launch_group(Ctx &c, int np, const Gemm *q, int ngroups, const int *group,
       HIPC(hipGetLastError());
     }
   }
-  if (dot) {
+  if (dot || cg) {
     // every output must have gone through the reduction
     for (int i = 0; i < np; ++i)
       if (keep[i] >= 0 && g.p[keep[i]].direct)
-        fail(QTT_E_ARG, "gemm dot: outputs written directly by the GEMM");
-    if (part_need == 0) fail(QTT_E_ARG, "gemm dot: no reduced output");
+        fail(QTT_E_ARG, "gemm dot/cg: outputs written directly by the GEMM");
+    if (part_need == 0) fail(QTT_E_ARG, "gemm dot/cg: no reduced output");
   }
 }
 
@@ -868,10 +1027,12 @@ void gemm_bf16x3(Ctx &c, const Gemm &g) {
 }
 
 void gemm_grouped(Ctx &c, int np, const Gemm *q, int ngroups, const int *group,
-                  const double *const *X, const int *skip, bool f32, const GemmDot *dot) {
+                  const double *const *X, const int *skip, bool f32, const GemmDot *dot,
+                  const GemmCg *cg) {
   if (np < 1 || np > GEMM_GROUP) fail(QTT_E_ARG, "gemm_grouped: 1..4 problems");
-  if (f32) launch_group<float>(c, np, q, ngroups, group, X, skip, dot);
-  else launch_group<double>(c, np, q, ngroups, group, X, skip, dot);
+  if (dot && cg) fail(QTT_E_ARG, "gemm_grouped: dot and cg are exclusive");
+  if (f32) launch_group<float>(c, np, q, ngroups, group, X, skip, dot, cg);
+  else launch_group<double>(c, np, q, ngroups, group, X, skip, dot, cg);
 }
 
 }  // namespace qtt

@@ -333,6 +333,8 @@ __global__ __launch_bounds__(64 * NW) void k_qrb_panel_reg(QrbBatch B, int j0) {
   __shared__ double red[2][QR_NB];
   __shared__ double rowc[2][QR_NB];
   __shared__ double T[QR_NB][QR_NB + 1];
+  __shared__ double Y[QR_NB][QR_NB + 1];  // Y[u][i] = v_u . v_i, u < i
+  __shared__ double taus[QR_NB];
   double P[ROWS][QR_NB];
 #pragma unroll
   for (int s = 0; s < ROWS; ++s) {
@@ -402,13 +404,34 @@ __global__ __launch_bounds__(64 * NW) void k_qrb_panel_reg(QrbBatch B, int j0) {
         else if (t > i && t < jb) P[s][t] -= w[t] * v;
       }
     }
-    // T[0:i, i] = -tau T[0:i, 0:i] (V_{0:i}^T v), T[i][i] = tau
-    if (tid < i) {
-      double s2 = 0.0;
-      for (int u = tid; u < i; ++u) s2 += T[tid][u] * (rowc[bf][u] + sc * red[bf][u]);
-      T[tid][i] = -tau * s2;
+    // the products of the earlier reflectors with this one and tau, for T
+    if (tid < i) Y[tid][i] = rowc[bf][tid] + sc * red[bf][tid];
+    if (tid == 0) taus[i] = tau;
+  }
+  __syncthreads();
+  // T (upper triangular) after the column loop, off its critical path:
+  // T[i][i] = tau_i, T[0:i, i] = -tau_i T[0:i, 0:i] Y[0:i, i]; row t of T
+  // depends only on row t, so thread t forms it alone, in registers
+  if (tid < QR_NB) {
+    double Tr[QR_NB];
+#pragma unroll
+    for (int i = 0; i < QR_NB; ++i) {
+      double val = 0.0;
+      if (i < jb) {
+        if (i == tid) {
+          val = taus[i];
+        } else if (i > tid) {
+          double s2 = 0.0;
+#pragma unroll
+          for (int u = 0; u < i; ++u)
+            if (u >= tid) s2 += Tr[u] * Y[u][i];
+          val = -taus[i] * s2;
+        }
+      }
+      Tr[i] = val;
     }
-    if (tid == 0) T[i][i] = tau;
+#pragma unroll
+    for (int i = 0; i < QR_NB; ++i) T[tid][i] = Tr[i];
   }
   __syncthreads();
   // write back: W panel (R entries and reflectors), V (unit diagonal, zeros

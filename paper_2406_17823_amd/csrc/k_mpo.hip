@@ -43,37 +43,39 @@ struct MJob {
   const int *colptr, *rowidx;
   const double *val;
   int KI, KO;
-  int64_t post, total, elem0;
+  int64_t post, total;
+  unsigned blk0, nblk;  // the job's workgroups: blk0 .. blk0 + nblk - 1
 };
 struct MJobs {
   int nj;
   MJob j[4];
-  int64_t total;
 };
 
-// up to four layers (one per job) in one launch over the concatenated outputs
+// up to four layers (one per job) in one launch; each workgroup serves one
+// job (selected from the block index, so the job's fields are uniform)
 template <typename TS, typename IT>
 __global__ __launch_bounds__(256) void k_mpo_csc_grouped(MJobs J, const int *skip) {
   if (skip && *skip) return;
-  for (IT e = blockIdx.x * (IT)blockDim.x + threadIdx.x; e < (IT)J.total;
-       e += (IT)gridDim.x * blockDim.x) {
-    int ji = 0;
+  int ji = 0;
 #pragma unroll
-    for (int i = 1; i < 4; ++i)
-      if (i < J.nj && (int64_t)e >= J.j[i].elem0) ji = i;
-    const MJob &M = J.j[ji];
-    const IT idx = e - (IT)M.elem0;
-    const IT post = (IT)M.post;
+  for (int i = 1; i < 4; ++i)
+    if (i < J.nj && blockIdx.x >= J.j[i].blk0) ji = i;
+  const MJob &M = J.j[ji];
+  const IT post = (IT)M.post, total = (IT)M.total;
+  const int KI = M.KI, KO = M.KO;
+  const TS *T = static_cast<const TS *>(M.T);
+  TS *Tout = static_cast<TS *>(M.Tout);
+  for (IT idx = (IT)(blockIdx.x - M.blk0) * 256 + threadIdx.x; idx < total;
+       idx += (IT)M.nblk * 256) {
     const IT q = idx % post;
     const IT t = idx / post;
-    const int o = (int)(t % (IT)M.KO);
-    const IT p = t / (IT)M.KO;
-    const TS *src = static_cast<const TS *>(M.T) + (int64_t)p * M.KI * M.post + q;
+    const int o = (int)(t % (IT)KO);
+    const IT p = t / (IT)KO;
+    const TS *src = T + (int64_t)p * KI * post + q;
     double s = 0.0;
     const int end = M.colptr[o + 1];
-    for (int z = M.colptr[o]; z < end; ++z)
-      s += M.val[z] * (double)src[(int64_t)M.rowidx[z] * M.post];
-    static_cast<TS *>(M.Tout)[idx] = (TS)s;
+    for (int z = M.colptr[o]; z < end; ++z) s += M.val[z] * (double)src[(int64_t)M.rowidx[z] * post];
+    Tout[idx] = (TS)s;
   }
 }
 
@@ -82,7 +84,7 @@ __global__ __launch_bounds__(256) void k_mpo_csc_grouped(MJobs J, const int *ski
 void mpo_layer_grouped(Ctx &c, int nj, const MpoJob *jobs, const int *skip, bool f32) {
   if (nj < 1 || nj > 4) fail(QTT_E_ARG, "mpo_layer_grouped: 1..4 jobs");
   MJobs J{};
-  int64_t total = 0;
+  int64_t blocks = 0, biggest = 0;
   const size_t es = f32 ? sizeof(float) : sizeof(double);
   for (int i = 0; i < nj; ++i) {
     const MpoJob &s = jobs[i];
@@ -101,26 +103,25 @@ void mpo_layer_grouped(Ctx &c, int nj, const MpoJob *jobs, const int *skip, bool
     m.KO = KO;
     m.post = s.post;
     m.total = s.pre * KO * s.post;
-    m.elem0 = total;
-    total += m.total;
+    m.blk0 = (unsigned)blocks;
+    m.nblk = (unsigned)std::min<int64_t>((m.total + 255) / 256, 32768);
+    blocks += m.nblk;
+    biggest = std::max(biggest, m.total + (int64_t)m.nblk * 256);
   }
-  J.total = total;
-  if (total <= 0) return;
-  int64_t g = (total + 255) / 256;
-  if (g > 131072) g = 131072;
-  const bool small = total + g * 256 < ((int64_t)1 << 31);
+  if (blocks <= 0) return;
+  const bool small = biggest < ((int64_t)1 << 31);
   if (f32 && small)
-    hipLaunchKernelGGL((k_mpo_csc_grouped<float, unsigned>), dim3((unsigned)g), dim3(256), 0,
+    hipLaunchKernelGGL((k_mpo_csc_grouped<float, unsigned>), dim3((unsigned)blocks), dim3(256), 0,
                        c.stream, J, skip);
   else if (f32)
-    hipLaunchKernelGGL((k_mpo_csc_grouped<float, int64_t>), dim3((unsigned)g), dim3(256), 0,
+    hipLaunchKernelGGL((k_mpo_csc_grouped<float, int64_t>), dim3((unsigned)blocks), dim3(256), 0,
                        c.stream, J, skip);
   else if (small)
-    hipLaunchKernelGGL((k_mpo_csc_grouped<double, unsigned>), dim3((unsigned)g), dim3(256), 0,
-                       c.stream, J, skip);
+    hipLaunchKernelGGL((k_mpo_csc_grouped<double, unsigned>), dim3((unsigned)blocks), dim3(256),
+                       0, c.stream, J, skip);
   else
-    hipLaunchKernelGGL((k_mpo_csc_grouped<double, int64_t>), dim3((unsigned)g), dim3(256), 0,
-                       c.stream, J, skip);
+    hipLaunchKernelGGL((k_mpo_csc_grouped<double, int64_t>), dim3((unsigned)blocks), dim3(256),
+                       0, c.stream, J, skip);
   HIPC(hipGetLastError());
 }
 

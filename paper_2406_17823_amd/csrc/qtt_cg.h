@@ -10,8 +10,9 @@ struct CGState {
   int done, iters, maxit, converged, zero_x;
   int precond;  // PCG: rz is r . z, maintained by pcg_start / pcg_next
   unsigned int counter;
-  // single-reduction CG: gamma = r . r, delta = (A r) . r of the current
-  // residual, gamma_prev and alpha_prev of the previous iteration
+  // single-reduction CG (Chronopoulos-Gear; its step runs inside the
+  // matvec, GemmCg): gamma = r . r, delta = w . r with w = A r of the
+  // current residual, gamma_prev and alpha_prev of the previous iteration
   double gamma, delta, gamma_prev, alpha_prev;
   int first;
 };
@@ -23,13 +24,6 @@ void cg_alpha(Ctx &c, const double *p, const double *q, int64_t n, CGState *st, 
 void cg_update(Ctx &c, double *x, double *r, const double *p, const double *q, int64_t n,
                CGState *st, double *part);
 void cg_pupdate(Ctx &c, const double *r, double *p, int64_t n, CGState *st);
-// single-reduction CG step (Chronopoulos-Gear): with w = A r and delta =
-// w . r from the previous matvec, beta = gamma / gamma_prev, alpha = gamma /
-// (delta - beta gamma / alpha_prev) (first step: beta = 0, alpha = gamma /
-// delta); p = r + beta p, s = w + beta s, x += alpha p, r -= alpha s, gamma =
-// r . r and the convergence test.  The next matvec forms w = A r and delta.
-void cg1_update(Ctx &c, double *x, double *r, double *p, double *s, const double *w, int64_t n,
-                CGState *st, double *part);
 void pcg_start(Ctx &c, const double *r, const double *z, double *p, int64_t n, CGState *st,
                double *part);
 void pcg_next(Ctx &c, const double *r, const double *z, double *p, int64_t n, CGState *st,

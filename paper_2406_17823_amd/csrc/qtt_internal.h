@@ -205,6 +205,7 @@ inline void span(int64_t &lo, int64_t &hi, int64_t ext, int64_t stride) {
 // with arbitrary element strides.  skip: optional device flag; when it is
 // non-zero the kernel returns immediately (used to stop converged CG).
 // alpha_dev: optional device scalar multiplying alpha.
+struct CGState;
 struct Gemm {
   int M = 0, N = 0, K = 0, B1 = 1, B2 = 1;
   const double *A = nullptr;
@@ -219,6 +220,10 @@ struct Gemm {
   // float32 elements): the convection networks of the mixed mode keep their
   // environments and chain intermediates in float32 storage
   bool a32 = false, b32 = false, c32 = false;
+  // CG operand (float64 B only): B is read as B - alpha (Bw + beta Bs) with
+  // alpha, beta of the CG state cgst (see GemmCg)
+  const double *Bw = nullptr, *Bs = nullptr;
+  const CGState *cgst = nullptr;
 };
 constexpr int GEMM_GROUP = 4;
 void gemm(Ctx &c, const Gemm &g);
@@ -237,9 +242,32 @@ struct GemmDot {
   double *part;
   int nparts;
 };
+// CG step fused into the matvec (single-reduction CG, the local solves of
+// the sweep), one iteration per matvec: with alpha and beta from the state
+// (gamma = r.r, delta = w.r with w = A r, gamma_prev, alpha_prev; first
+// step: beta = 0, alpha = gamma / delta) the first GEMM of the matvec reads
+// its B operand as the next residual r - alpha (w + beta s) (Gemm::Bw and
+// Bs point at w and s laid out like B), and the reduction of the last GEMM
+// (q its output before the beta term, laid out like the CG vectors from
+// position off[group]; C is not written) takes every element through
+//   s = w + beta s, p = r + beta p, x += alpha p, r -= alpha s,
+//   w = q + beta_C r   (the new A r: the beta term uses the new r),
+// while the last block to arrive forms the new gamma and delta (block
+// partials in part, 2 per block, summed in block order), counts the
+// iteration and sets done on convergence, NaN or the iteration limit.
+// Every output must go through the reduction; the state counter must be 0
+// and is left 0.
+struct GemmCg {
+  CGState *st;
+  double *x, *r, *w, *p, *s;
+  int64_t n;
+  int64_t off[GEMM_GROUP];
+  double *part;
+  int nparts;
+};
 void gemm_grouped(Ctx &c, int np, const Gemm *q, int ngroups, const int *group,
                   const double *const *X, const int *skip, bool f32,
-                  const GemmDot *dot = nullptr);
+                  const GemmDot *dot = nullptr, const GemmCg *cg = nullptr);
 // float32-MFMA variant with float64 inputs/outputs (mixed precision mode)
 void gemm_f32(Ctx &c, const Gemm &g);
 // bfloat16-MFMA variant (float32 accumulation) with float64 inputs/outputs

@@ -468,7 +468,8 @@ struct Sweep {
 
   // dot: the reduction of the last GEMM also forms delta = y . x into the CG
   // state (single-reduction CG)
-  void matvec(int d, const double *x, double *y, const int *skip, bool dot = false) {
+  void matvec(int d, const double *x, double *y, const int *skip, bool dot = false,
+              const GemmCg *cg = nullptr) {
     const int64_t s0 = centre_size(0, d);
     const double *xs[2] = {x, x + s0};
     double *ys[2] = {y, y + s0};
@@ -496,6 +497,12 @@ struct Sweep {
       q.C = pT[k];
       q.sCm = 4 * gp;
       q.sCn = 1;
+      if (cg) {
+        // x is the CG residual r: the GEMM reads the next residual
+        q.Bw = cg->w + (xs[j] - x);
+        q.Bs = cg->s + (xs[j] - x);
+        q.cgst = cg->st;
+      }
       mj[k] = MpoJob{pT[k], pT2[k], N.lay[0].mpo, d, false, (int64_t)a, (int64_t)gp, mi, mo};
       const int64_t rest = (int64_t)mo * gp;
       Gemm &o = og[k];
@@ -527,7 +534,7 @@ struct Sweep {
       gd.nparts = DPART;
       gemm_grouped(c, 4, og, 2, ogrp, oX, skip, false, &gd);
     } else {
-      gemm_grouped(c, 4, og, 2, ogrp, oX, skip, false);
+      gemm_grouped(c, 4, og, 2, ogrp, oX, skip, false, nullptr, cg);
     }
   }
   static constexpr int DPART = 1024;
@@ -667,10 +674,22 @@ struct Sweep {
           apply_pc(r, pcz, d, &st->done);
           pcg_next(c, r, pcz, pp, ntot, st, part);
         } else {
-          // single-reduction CG: one vector kernel and one matvec (w = A r
-          // in q, with delta = w . r fused into its reduction) per iteration
-          cg1_update(c, x, r, pp, sv, q, ntot, st, part);
-          matvec(d, r, q, &st->done, true);
+          // single-reduction CG in one matvec per iteration (w = A r held in
+          // q): its first GEMM reads the next residual, its reduction
+          // updates the vectors and forms the two dot products
+          GemmCg gc{};
+          gc.st = st;
+          gc.x = x;
+          gc.r = r;
+          gc.w = q;
+          gc.p = pp;
+          gc.s = sv;
+          gc.n = ntot;
+          gc.off[0] = 0;
+          gc.off[1] = centre_size(0, d);
+          gc.part = part;
+          gc.nparts = 1024;
+          matvec(d, r, q, &st->done, false, &gc);
         }
       }
     };
