@@ -322,9 +322,8 @@ __device__ inline double wave_sum16(const double (&v)[16], int lane) {
 // (ROWS = 1, 2 or 4 with 8 waves: the per-thread work of a column step
 // scales with ROWS, so the panel of a short matrix spreads over the waves)
 template <int NW, int ROWS>
-__global__ __launch_bounds__(64 * NW) void k_qrb_panel_reg(QrbBatch B, int j0) {
+__device__ void qrb_panel_reg(const QrbDesc &D, int j0) {
   constexpr int NT = 64 * NW;
-  const QrbDesc &D = B.d[blockIdx.x];
   const int m = D.m, k = D.k;
   const int jb = min(QR_NB, k - j0);
   if (jb <= 0 || m > ROWS * NT) return;
@@ -470,6 +469,11 @@ __global__ __launch_bounds__(64 * NW) void k_qrb_panel_reg(QrbBatch B, int j0) {
   }
 }
 
+template <int NW, int ROWS>
+__global__ __launch_bounds__(64 * NW) void k_qrb_panel_reg(QrbBatch B, int j0) {
+  qrb_panel_reg<NW, ROWS>(B.d[blockIdx.x], j0);
+}
+
 // VT = V_p T_p and VTt = V_p T_p^T on rows j0..m (one thread per row and column)
 __global__ void k_qrb_vt(QrbBatch B, int j0) {
   const QrbDesc &D = B.d[blockIdx.y];
@@ -502,33 +506,13 @@ __global__ void k_qrb_vt(QrbBatch B, int j0) {
 // two GEMMs, a split-K reduction and their launch gaps.
 constexpr int QA_COLS = 32, QA_THREADS = 512, QA_WAVES = QA_THREADS / 64, QA_BATCH = 4;
 
-__global__ __launch_bounds__(QA_THREADS) void k_qrb_apply(QrbBatch B, int j0, int which) {
-  const QrbDesc &D = B.d[blockIdx.y];
+// X[j0:m, c0:c0+nc) -= U (V_p^T X) for one 32-column tile (see above)
+__device__ void qrb_apply_tile(const QrbDesc &D, int j0, int jb, double *X, const double *U,
+                               int c0, int nc, double (*Zs)[QR_NB][QA_COLS + 1]) {
   const int m = D.m;
-  const int jb = min(QR_NB, D.k - j0);
-  if (jb <= 0) return;
-  double *X;
-  const double *U;
-  int cbeg, cend;
-  if (which == 0) {
-    X = D.W;
-    U = D.VTt;
-    cbeg = j0 + jb;
-    cend = D.n;
-  } else {
-    if (!D.Q) return;
-    X = D.Qw;
-    U = D.VT;
-    cbeg = j0;
-    cend = D.k;
-  }
-  const int c0 = cbeg + (int)blockIdx.x * QA_COLS;
-  if (c0 >= cend) return;
-  const int nc = min(QA_COLS, cend - c0);
   const int R = m - j0;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  __shared__ double Zs[QA_WAVES][QR_NB][QA_COLS + 1];
   // Z = V_p^T X: A[t][k] = V[j0 + k][j0 + t], B[k][c] = X[j0 + k][c0 + c]
   d4v z[2] = {d4v{0.0, 0.0, 0.0, 0.0}, d4v{0.0, 0.0, 0.0, 0.0}};
 #pragma unroll 8
@@ -593,6 +577,76 @@ __global__ __launch_bounds__(QA_THREADS) void k_qrb_apply(QrbBatch B, int j0, in
         if (r < m && cc < nc) X[(int64_t)(c0 + cc) * m + r] = xo[j][q] - acc[q];
       }
     }
+  }
+}
+
+__global__ __launch_bounds__(QA_THREADS) void k_qrb_apply(QrbBatch B, int j0, int which) {
+  const QrbDesc &D = B.d[blockIdx.y];
+  const int jb = min(QR_NB, D.k - j0);
+  if (jb <= 0) return;
+  double *X;
+  const double *U;
+  int cbeg, cend;
+  if (which == 0) {
+    X = D.W;
+    U = D.VTt;
+    cbeg = j0 + jb;
+    cend = D.n;
+  } else {
+    if (!D.Q) return;
+    X = D.Qw;
+    U = D.VT;
+    cbeg = j0;
+    cend = D.k;
+  }
+  const int c0 = cbeg + (int)blockIdx.x * QA_COLS;
+  if (c0 >= cend) return;
+  __shared__ double Zs[QA_WAVES][QR_NB][QA_COLS + 1];
+  qrb_apply_tile(D, j0, jb, X, U, c0, min(QA_COLS, cend - c0), Zs);
+}
+
+// trailing update of panel j0 (as k_qrb_apply, which = 0) with look-ahead:
+// workgroup 0 of each matrix owns the first 32 trailing columns, which hold
+// the next panel, so once its tile is updated (its own writes, visible to
+// the workgroup after the barrier) it factors that panel in the same launch
+// while the other workgroups finish the trailing columns; one launch per
+// panel instead of two.  The next panel's writes (its columns of W, V, VT,
+// VTt and T) are disjoint from what the other workgroups read (panel j0's
+// columns of V and VTt, their own columns of W).
+template <int ROWS>
+__global__ __launch_bounds__(QA_THREADS) void k_qrb_apply_la(QrbBatch B, int j0) {
+  const QrbDesc &D = B.d[blockIdx.y];
+  const int jb = min(QR_NB, D.k - j0);
+  if (jb <= 0) return;
+  const int cbeg = j0 + jb, cend = D.n;
+  const int c0 = cbeg + (int)blockIdx.x * QA_COLS;
+  if (c0 >= cend) return;
+  __shared__ double Zs[QA_WAVES][QR_NB][QA_COLS + 1];
+  qrb_apply_tile(D, j0, jb, D.W, D.VTt, c0, min(QA_COLS, cend - c0), Zs);
+  if (blockIdx.x != 0 || j0 + QR_NB >= D.k) return;
+  __syncthreads();
+  qrb_panel_reg<QA_THREADS / 64, ROWS>(D, j0 + QR_NB);
+}
+
+// explicit Q = H_0 H_1 ... [I; 0] in one launch: the columns of Q are
+// independent, so each workgroup takes its 32-column tile through every
+// panel's block reflector, last panel first (a panel whose rows start at or
+// right of the tile's last column leaves it unchanged and is skipped).  The
+// tile's own global writes are visible to the whole workgroup after the
+// barrier; the arithmetic per column is that of one apply launch per panel.
+__global__ __launch_bounds__(QA_THREADS) void k_qrb_formq(QrbBatch B) {
+  const QrbDesc &D = B.d[blockIdx.y];
+  if (!D.Q) return;
+  const int c0 = (int)blockIdx.x * QA_COLS;
+  if (c0 >= D.k) return;
+  const int nc = min(QA_COLS, D.k - c0);
+  __shared__ double Zs[QA_WAVES][QR_NB][QA_COLS + 1];
+  for (int j0 = ((D.k - 1) / QR_NB) * QR_NB; j0 >= 0; j0 -= QR_NB) {
+    if (j0 >= c0 + nc) continue;
+    // columns left of j0 are zero in rows j0.. (untouched by this panel)
+    const int cs = max(c0, j0);
+    qrb_apply_tile(D, j0, min(QR_NB, D.k - j0), D.Qw, D.VT, cs, c0 + nc - cs, Zs);
+    __syncthreads();
   }
 }
 
@@ -673,47 +727,71 @@ void qr_blocked(Ctx &c, int cnt, const ConstMatView *A, const MatView *Q, const 
   const unsigned g = (unsigned)std::min<int64_t>(1024, (elems + 255) / 256);
   hipLaunchKernelGGL(k_qrb_load, dim3(g, cnt), dim3(256), 0, c.stream, b);
   HIPC(hipGetLastError());
-  for (int j0 = 0; j0 < kmax; j0 += QR_NB) {
-    int mmax = 0;
-    for (int i = 0; i < cnt; ++i) mmax = std::max(mmax, b.d[i].m);
-    if (mmax <= 512)
-      hipLaunchKernelGGL((k_qrb_panel_reg<8, 1>), dim3(cnt), dim3(512), 0, c.stream, b, j0);
-    else if (mmax <= 1024)
-      hipLaunchKernelGGL((k_qrb_panel_reg<8, 2>), dim3(cnt), dim3(512), 0, c.stream, b, j0);
-    else if (mmax <= 512 * QR_REG_MAXROWS)
-      hipLaunchKernelGGL((k_qrb_panel_reg<8, 4>), dim3(cnt), dim3(512), 0, c.stream, b, j0);
-    if (mmax > 512 * QR_REG_MAXROWS) {
+  int mmax = 0;
+  for (int i = 0; i < cnt; ++i) mmax = std::max(mmax, b.d[i].m);
+  if (mmax <= 512 * QR_REG_MAXROWS) {
+    // register panels: the first panel alone, then one launch per panel for
+    // its trailing update and the factorisation of the next panel
+    const int rows = mmax <= 512 ? 1 : (mmax <= 1024 ? 2 : 4);
+    if (rows == 1)
+      hipLaunchKernelGGL((k_qrb_panel_reg<8, 1>), dim3(cnt), dim3(512), 0, c.stream, b, 0);
+    else if (rows == 2)
+      hipLaunchKernelGGL((k_qrb_panel_reg<8, 2>), dim3(cnt), dim3(512), 0, c.stream, b, 0);
+    else
+      hipLaunchKernelGGL((k_qrb_panel_reg<8, 4>), dim3(cnt), dim3(512), 0, c.stream, b, 0);
+    HIPC(hipGetLastError());
+    for (int j0 = 0; j0 < kmax; j0 += QR_NB) {
+      int tiles = 0;
+      for (int i = 0; i < cnt; ++i) {
+        const QrbDesc &D = b.d[i];
+        const int jb = std::min(QR_NB, D.k - j0);
+        const int nt = D.n - j0 - std::max(jb, 0);
+        if (jb > 0 && nt > 0) tiles = std::max(tiles, (nt + QA_COLS - 1) / QA_COLS);
+      }
+      if (tiles == 0) continue;
+      if (rows == 1)
+        hipLaunchKernelGGL((k_qrb_apply_la<1>), dim3(tiles, cnt), dim3(QA_THREADS), 0, c.stream,
+                           b, j0);
+      else if (rows == 2)
+        hipLaunchKernelGGL((k_qrb_apply_la<2>), dim3(tiles, cnt), dim3(QA_THREADS), 0, c.stream,
+                           b, j0);
+      else
+        hipLaunchKernelGGL((k_qrb_apply_la<4>), dim3(tiles, cnt), dim3(QA_THREADS), 0, c.stream,
+                           b, j0);
+      HIPC(hipGetLastError());
+    }
+  } else {
+    for (int j0 = 0; j0 < kmax; j0 += QR_NB) {
       // matrices taller than the register panel: panel in HBM, V T by a second kernel
       hipLaunchKernelGGL(k_qrb_panel, dim3(cnt), dim3(LA_THREADS), 0, c.stream, b, j0);
       int64_t rows = 0;
       for (int i = 0; i < cnt; ++i) rows = std::max<int64_t>(rows, (int64_t)(b.d[i].m - j0) * QR_NB);
       const unsigned gv = (unsigned)std::max<int64_t>(1, std::min<int64_t>(2048, (rows + 255) / 256));
       hipLaunchKernelGGL(k_qrb_vt, dim3(gv, cnt), dim3(256), 0, c.stream, b, j0);
-    }
-    HIPC(hipGetLastError());
-    // trailing columns: W[j0:m, j0+jb:n] -= (V_p T_p^T)(V_p^T W[j0:m, j0+jb:n])
-    int tiles = 0;
-    for (int i = 0; i < cnt; ++i) {
-      const QrbDesc &D = b.d[i];
-      const int jb = std::min(QR_NB, D.k - j0);
-      const int nt = D.n - j0 - std::max(jb, 0);
-      if (jb > 0 && nt > 0) tiles = std::max(tiles, (nt + QA_COLS - 1) / QA_COLS);
-    }
-    if (tiles > 0) {
-      hipLaunchKernelGGL(k_qrb_apply, dim3(tiles, cnt), dim3(QA_THREADS), 0, c.stream, b, j0, 0);
       HIPC(hipGetLastError());
+      // trailing columns: W[j0:m, j0+jb:n] -= (V_p T_p^T)(V_p^T W[j0:m, j0+jb:n])
+      int tiles = 0;
+      for (int i = 0; i < cnt; ++i) {
+        const QrbDesc &D = b.d[i];
+        const int jb = std::min(QR_NB, D.k - j0);
+        const int nt = D.n - j0 - std::max(jb, 0);
+        if (jb > 0 && nt > 0) tiles = std::max(tiles, (nt + QA_COLS - 1) / QA_COLS);
+      }
+      if (tiles > 0) {
+        hipLaunchKernelGGL(k_qrb_apply, dim3(tiles, cnt), dim3(QA_THREADS), 0, c.stream, b, j0,
+                           0);
+        HIPC(hipGetLastError());
+      }
     }
   }
   // Q = H_0 ... [I; 0], panels applied last to first (not for R-only requests):
-  // Q[j0:m, j0:k] -= (V_p T_p)(V_p^T Q[j0:m, j0:k])
-  for (int j0 = ((kmax - 1) / QR_NB) * QR_NB; j0 >= 0; j0 -= QR_NB) {
+  // Q[j0:m, j0:k] -= (V_p T_p)(V_p^T Q[j0:m, j0:k]), all panels in one launch
+  {
     int tiles = 0;
-    for (int i = 0; i < cnt; ++i) {
-      const QrbDesc &D = b.d[i];
-      if (D.Q && D.k - j0 > 0) tiles = std::max(tiles, (D.k - j0 + QA_COLS - 1) / QA_COLS);
-    }
+    for (int i = 0; i < cnt; ++i)
+      if (b.d[i].Q) tiles = std::max(tiles, (b.d[i].k + QA_COLS - 1) / QA_COLS);
     if (tiles > 0) {
-      hipLaunchKernelGGL(k_qrb_apply, dim3(tiles, cnt), dim3(QA_THREADS), 0, c.stream, b, j0, 1);
+      hipLaunchKernelGGL(k_qrb_formq, dim3(tiles, cnt), dim3(QA_THREADS), 0, c.stream, b);
       HIPC(hipGetLastError());
     }
   }

@@ -874,50 +874,60 @@ struct Sweep {
       }
     }
     qr_batch(c, 2, A, Q, R);
+    // R (or L) into the neighbouring cores: both products in one launch
     ro = 0;
+    Gemm g[2];
+    double *dst[2];
+    int64_t dsz[2], doff[2];
     for (int i = 0; i < 2; ++i) {
       const int l = v[i].bond[d], r = v[i].bond[d + 1];
-      Gemm g;
       if (right) {
         const int r2 = v[i].bond[d + 2];
-        g.M = r;
-        g.N = 4 * r2;
-        g.K = r;
-        g.A = Rb + ro;
-        g.sAm = r;
-        g.sAk = 1;
-        g.B = v[i].core(d + 1);
-        g.sBk = 4 * r2;
-        g.sBn = 1;
-        g.C = Tb + to;
-        g.sCm = 4 * r2;
-        g.sCn = 1;
-        gemm(c, g);
-        HIPC(hipMemcpyAsync(v[i].core(d + 1), Tb + to, v[i].core_size(d + 1) * sizeof(double),
-                            hipMemcpyDeviceToDevice, c.stream));
+        g[i].M = r;
+        g[i].N = 4 * r2;
+        g[i].K = r;
+        g[i].A = Rb + ro;
+        g[i].sAm = r;
+        g[i].sAk = 1;
+        g[i].B = v[i].core(d + 1);
+        g[i].sBk = 4 * r2;
+        g[i].sBn = 1;
+        g[i].C = Tb + to;
+        g[i].sCm = 4 * r2;
+        g[i].sCn = 1;
+        dst[i] = v[i].core(d + 1);
+        dsz[i] = v[i].core_size(d + 1);
         ro += (int64_t)r * r;
-        to += v[i].core_size(d + 1);
       } else {
         const int lp = v[i].bond[d - 1];
-        g.M = 4 * lp;
-        g.N = l;
-        g.K = l;
-        g.A = v[i].core(d - 1);
-        g.sAm = l;
-        g.sAk = 1;
-        g.B = Rb + ro;
-        g.sBk = 1;
-        g.sBn = l;
-        g.C = Tb + to;
-        g.sCm = l;
-        g.sCn = 1;
-        gemm(c, g);
-        HIPC(hipMemcpyAsync(v[i].core(d - 1), Tb + to, v[i].core_size(d - 1) * sizeof(double),
-                            hipMemcpyDeviceToDevice, c.stream));
+        g[i].M = 4 * lp;
+        g[i].N = l;
+        g[i].K = l;
+        g[i].A = v[i].core(d - 1);
+        g[i].sAm = l;
+        g[i].sAk = 1;
+        g[i].B = Rb + ro;
+        g[i].sBk = 1;
+        g[i].sBn = l;
+        g[i].C = Tb + to;
+        g[i].sCm = l;
+        g[i].sCn = 1;
+        dst[i] = v[i].core(d - 1);
+        dsz[i] = v[i].core_size(d - 1);
         ro += (int64_t)l * l;
-        to += v[i].core_size(d - 1);
-        reverse_core(v[i], vrev[i], d);
       }
+      doff[i] = to;
+      to += dsz[i];
+    }
+    {
+      const int grp[2] = {0, 1};
+      const double *X[2] = {nullptr, nullptr};
+      gemm_grouped(c, 2, g, 2, grp, X, nullptr, false);
+    }
+    for (int i = 0; i < 2; ++i) {
+      HIPC(hipMemcpyAsync(dst[i], Tb + doff[i], dsz[i] * sizeof(double), hipMemcpyDeviceToDevice,
+                          c.stream));
+      if (!right) reverse_core(v[i], vrev[i], d);
     }
   }
 
