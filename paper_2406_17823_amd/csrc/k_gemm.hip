@@ -423,7 +423,8 @@ struct RedOut {
   int nsrc;
   int salpha;  // 1: out = sum_q alpha_q (sum over q's splits), else alpha (sum)
   RedSrc src[GEMM_GROUP];
-  int64_t elem0;
+  int64_t total;           // elements of this output
+  unsigned blk0, nblk;     // its workgroups: blk0 .. blk0 + nblk - 1
   int c32, x32;  // C / X stored as float32
   const double *Y;  // dot partner laid out like C (float64), or null
   int64_t cgoff;    // fused CG step: position of C's element 0 in the vectors
@@ -441,6 +442,29 @@ struct RedK {
   CGState *cst;
   double *cx, *cr, *cw, *cp, *cs, *cz, *cpart;
 };
+
+// s += p[0], p[tot], ..., p[(ks - 1) tot] in that order; the loads of a
+// batch of eight are issued before their adds (independent addresses), so a
+// thread waits for one memory latency per batch rather than per split
+__device__ inline void red_add_splits(double &s, const double *p, int ks, int64_t tot) {
+  int k = 0;
+  for (; k + 8 <= ks; k += 8) {
+    double t[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) t[u] = p[(int64_t)(k + u) * tot];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += t[u];
+  }
+  if (k + 4 <= ks) {
+    double t[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) t[u] = p[(int64_t)(k + u) * tot];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) s += t[u];
+    k += 4;
+  }
+  for (; k < ks; ++k) s += p[(int64_t)k * tot];
+}
 
 __device__ inline double red_wave_sum(double v) {
 #pragma unroll
@@ -463,27 +487,27 @@ __global__ __launch_bounds__(256) void k_splitk_reduce(RedK R) {
     cg_b = cg_first ? 0.0 : cg_g / R.cst->gamma_prev;
     cg_a = cg_first ? cg_g / dl : cg_g / (dl - cg_b * cg_g / R.cst->alpha_prev);
   }
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < R.total;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    int oi = 0;
+  // each workgroup serves one output (selected from the block index, so the
+  // output's fields are uniform across it)
+  int oi = 0;
 #pragma unroll
-    for (int k = 1; k < GEMM_GROUP; ++k)
-      if (k < R.nout && e >= R.o[k].elem0) oi = k;
-    const RedOut &O = R.o[oi];
-    const int64_t idx = e - O.elem0;
-    const int64_t per = (int64_t)O.M * O.N;
-    const int64_t tot = per * O.B1 * O.B2;
+  for (int k = 1; k < GEMM_GROUP; ++k)
+    if (k < R.nout && blockIdx.x >= R.o[k].blk0) oi = k;
+  const RedOut &O = R.o[oi];
+  const int64_t per = (int64_t)O.M * O.N;
+  const int64_t tot = O.total;
+  for (int64_t idx = (int64_t)(blockIdx.x - O.blk0) * blockDim.x + threadIdx.x; idx < tot;
+       idx += (int64_t)O.nblk * blockDim.x) {
     double v = 0.0;
     if (O.salpha) {
       for (int q = 0; q < O.nsrc; ++q) {
         double s = 0.0;
-        for (int k = 0; k < O.src[q].ksplit; ++k) s += O.src[q].part[(int64_t)k * tot + idx];
+        red_add_splits(s, O.src[q].part + idx, O.src[q].ksplit, tot);
         v += O.src[q].alpha * s;
       }
     } else {
       double s = 0.0;
-      for (int q = 0; q < O.nsrc; ++q)
-        for (int k = 0; k < O.src[q].ksplit; ++k) s += O.src[q].part[(int64_t)k * tot + idx];
+      for (int q = 0; q < O.nsrc; ++q) red_add_splits(s, O.src[q].part + idx, O.src[q].ksplit, tot);
       v = O.alpha * s;
     }
     const int64_t bidx = idx / per;
@@ -959,15 +983,29 @@ void launch_group(Ctx &c, int np, const Gemm *q, int ngroups, const int *group,
         span(lo, hi, O.B2, O.sXb2);
         c.check_range(O.X, lo, hi, sizeof(double), "gemm X");
       }
-      O.elem0 = total;
-      total += (int64_t)O.M * O.N * O.B1 * O.B2;
+      O.total = (int64_t)O.M * O.N * O.B1 * O.B2;
+      total += O.total;
       R.o[R.nout++] = O;
     }
     R.total = total;
     if (total > 0) {
-      unsigned rg = (unsigned)std::min<int64_t>(4096, (total + 255) / 256);
+      // workgroups per output: one per 256 elements, scaled down to the cap
+      // (at most 4096, or the partial slots of a fused dot / CG step)
+      int64_t cap = 4096;
+      if (cg) cap = std::min<int64_t>(cap, cg->nparts);
+      if (dot) cap = std::min<int64_t>(cap, dot->nparts);
+      int64_t want = 0;
+      for (int o = 0; o < R.nout; ++o) want += (R.o[o].total + 255) / 256;
+      unsigned rg = 0;
+      for (int o = 0; o < R.nout; ++o) {
+        int64_t nb = (R.o[o].total + 255) / 256;
+        if (want > cap) nb = std::max<int64_t>(1, nb * (cap - R.nout) / want);
+        R.o[o].blk0 = rg;
+        R.o[o].nblk = (unsigned)nb;
+        rg += (unsigned)nb;
+      }
+      if (rg > cap) fail(QTT_E_UNSUPPORTED, "gemm reduction: workgroup count");
       if (cg) {
-        rg = std::min<unsigned>(rg, (unsigned)cg->nparts);
         c.check_range(cg->part, 0, 2 * (int64_t)rg - 1, sizeof(double), "gemm cg partials");
         c.check_range(cg->st, 0, 0, sizeof(CGState), "gemm cg state");
         for (double *vv : {cg->x, cg->r, cg->w, cg->p, cg->s})
@@ -981,7 +1019,6 @@ void launch_group(Ctx &c, int np, const Gemm *q, int ngroups, const int *group,
         R.cpart = cg->part;
       }
       if (dot) {
-        rg = std::min<unsigned>(rg, (unsigned)dot->nparts);
         c.check_range(dot->part, 0, rg - 1, sizeof(double), "gemm dot partials");
         R.dpart = dot->part;
         R.dout = dot->out;

@@ -89,10 +89,13 @@ double *Ctx::alloc_owned(int64_t ndouble) {
   return (double *)p;
 }
 
+// timing-only events (read after a stream synchronisation): no system-scope
+// fence, so recording one costs no cache write-back and the interval between
+// two of them is the work between them, as a kernel trace reports it
 hipEvent_t Ctx::take_event() {
   if (kt.pool.empty()) {
     hipEvent_t e;
-    HIPC(hipEventCreate(&e));
+    HIPC(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
     return e;
   }
   hipEvent_t e = kt.pool.back();

@@ -31,10 +31,10 @@ def _short(name):
 
 
 def _family(name):
-    """GEMM instantiations differing only in operand storage types form one
-    family, 'k_gemm<T, BM, BN, WGM, WGN, KD, *>' (the library times them as
-    one kind)."""
-    return re.sub(r', (double|float), (double|float)>$', ', *>', name)
+    """GEMM instantiations differing only in operand storage types (and the
+    CG-operand flag) form one family, 'k_gemm<T, BM, BN, WGM, WGN, KD, *>'
+    (the library times them as one kind)."""
+    return re.sub(r', (double|float), (double|float)(, (true|false))?>$', ', *>', name)
 
 
 def _matches(name, kernel):
