@@ -106,6 +106,16 @@ __global__ __launch_bounds__(CG_THREADS) void k_cg_init(const double *rhs, const
   }
 }
 
+// state reset before a solve (the fields cg_init does not set itself)
+__global__ void k_cg_reset(CGState *st, double rtol, int maxit, int precond) {
+  if (threadIdx.x != 0) return;
+  st->rtol = rtol;
+  st->maxit = maxit;
+  st->precond = precond;
+  st->done = 0;
+  st->counter = 0;
+}
+
 __global__ void k_cg_zero_if(double *x, int64_t n, const CGState *st) {
   if (!st->zero_x) return;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
@@ -250,6 +260,12 @@ inline unsigned cg_grid(int64_t n) {
 
 static void chk(Ctx &c, const double *v, int64_t n, const char *w) {
   c.check_range(v, 0, n - 1, 8, w);
+}
+
+void cg_reset(Ctx &c, CGState *st, double rtol, int maxit, int precond) {
+  c.check_range(st, 0, 0, sizeof(CGState), "cg state");
+  hipLaunchKernelGGL(k_cg_reset, dim3(1), dim3(64), 0, c.stream, st, rtol, maxit, precond);
+  HIPC(hipGetLastError());
 }
 
 void cg_init(Ctx &c, const double *rhs, const double *q, double *r, double *p, double *x,

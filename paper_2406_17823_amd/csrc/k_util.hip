@@ -165,7 +165,42 @@ __global__ void k_nonfinite(const double *x, int64_t n, int *flag) {
     if (!isfinite(x[i])) *flag = 1;
 }
 
+// up to four contiguous copies in one launch (blockIdx.y selects the pair)
+struct CopyPairs {
+  double *dst[4];
+  const double *src[4];
+  int64_t n[4];
+};
+__global__ void k_copy_pairs(CopyPairs P) {
+  const int k = blockIdx.y;
+  double *d = P.dst[k];
+  const double *s = P.src[k];
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < P.n[k];
+       i += (int64_t)gridDim.x * blockDim.x)
+    d[i] = s[i];
+}
+
 }  // namespace
+
+void copy_pairs(Ctx &c, int np, double *const *dst, const double *const *src, const int64_t *n) {
+  if (np < 1 || np > 4) fail(QTT_E_ARG, "copy_pairs: 1..4 copies");
+  CopyPairs P{};
+  int64_t mx = 0;
+  for (int k = 0; k < np; ++k) {
+    if (n[k] > 0) {
+      c.check_range(src[k], 0, n[k] - 1, sizeof(double), "copy_pairs src");
+      c.check_range(dst[k], 0, n[k] - 1, sizeof(double), "copy_pairs dst");
+    }
+    P.dst[k] = dst[k];
+    P.src[k] = src[k];
+    P.n[k] = std::max<int64_t>(n[k], 0);
+    mx = std::max(mx, P.n[k]);
+  }
+  if (mx == 0) return;
+  const unsigned g = (unsigned)std::min<int64_t>(1024, (mx + 255) / 256);
+  hipLaunchKernelGGL(k_copy_pairs, dim3(g, np), dim3(256), 0, c.stream, P);
+  HIPC(hipGetLastError());
+}
 
 void fill(Ctx &c, double *p, int64_t n, double v) {
   if (n <= 0) return;

@@ -17,6 +17,9 @@ struct CGState {
   int first;
 };
 
+// rtol, maxit, precond set, done and the arrival counter cleared, on the
+// device (no host copy: the host does not wait for the stream)
+void cg_reset(Ctx &c, CGState *st, double rtol, int maxit, int precond);
 // partial-sum buffer: 2 * 512 doubles
 void cg_init(Ctx &c, const double *rhs, const double *q, double *r, double *p, double *x,
              int64_t n, CGState *st, double *part);

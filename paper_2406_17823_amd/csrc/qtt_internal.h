@@ -278,6 +278,8 @@ void gemm_bf16x3(Ctx &c, const Gemm &g);
 
 // ---------------------------------------------------------------- small kernels
 void fill(Ctx &c, double *p, int64_t n, double v);
+// dst[k][0:n[k]) = src[k][0:n[k]) for up to four non-overlapping pairs, one launch
+void copy_pairs(Ctx &c, int np, double *const *dst, const double *const *src, const int64_t *n);
 void fill_f32(Ctx &c, float *p, int64_t n, float v);
 void scale_copy(Ctx &c, double *dst, const double *src, int64_t n, double s);
 void axpy_into(Ctx &c, double *y, const double *x, int64_t n, double s);

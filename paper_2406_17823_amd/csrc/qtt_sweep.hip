@@ -736,12 +736,7 @@ struct Sweep {
   // r = rhs - A x on the device and the CG state reset (warm start from x)
   void cg_start(int d, bool pre, double *x, double *r, double *pp, double *q, const double *rhs,
                 int64_t ntot) {
-    st_host->rtol = p.cg_rtol;
-    st_host->maxit = p.cg_maxit;
-    st_host->counter = 0;
-    st_host->done = 0;
-    st_host->precond = pre ? 1 : 0;
-    HIPC(hipMemcpyAsync(st, st_host, sizeof(CGState), hipMemcpyHostToDevice, c.stream));
+    cg_reset(c, st, p.cg_rtol, p.cg_maxit, pre ? 1 : 0);
     matvec(d, x, q, nullptr);
     cg_init(c, rhs, q, r, pp, x, ntot, st, part);
     if (pre) {
@@ -789,10 +784,10 @@ struct Sweep {
       launch_gemms(cnt, q, grp[0]->f32s(), true);
     }
     auto load_guess = [&] {
-      HIPC(hipMemcpyAsync(x, v[0].core(d), s0 * sizeof(double), hipMemcpyDeviceToDevice,
-                          c.stream));
-      HIPC(hipMemcpyAsync(x + s0, v[1].core(d), s1 * sizeof(double), hipMemcpyDeviceToDevice,
-                          c.stream));
+      double *const dst[2] = {x, x + s0};
+      const double *const src[2] = {v[0].core(d), v[1].core(d)};
+      const int64_t len[2] = {s0, s1};
+      copy_pairs(c, 2, dst, src, len);
     };
     load_guess();
     if (stats && c.timing) {
@@ -835,9 +830,12 @@ struct Sweep {
     } else if (!converged) {
       warn = std::max(warn, (int)QTT_W_CG_MAXIT);
     }
-    HIPC(hipMemcpyAsync(v[0].core(d), x, s0 * sizeof(double), hipMemcpyDeviceToDevice, c.stream));
-    HIPC(hipMemcpyAsync(v[1].core(d), x + s0, s1 * sizeof(double), hipMemcpyDeviceToDevice,
-                        c.stream));
+    {
+      double *const dst[2] = {v[0].core(d), v[1].core(d)};
+      const double *const src[2] = {x, x + s0};
+      const int64_t len[2] = {s0, s1};
+      copy_pairs(c, 2, dst, src, len);
+    }
   }
 
   static double ms_since(std::chrono::steady_clock::time_point t0) {
@@ -924,11 +922,12 @@ struct Sweep {
       const double *X[2] = {nullptr, nullptr};
       gemm_grouped(c, 2, g, 2, grp, X, nullptr, false);
     }
-    for (int i = 0; i < 2; ++i) {
-      HIPC(hipMemcpyAsync(dst[i], Tb + doff[i], dsz[i] * sizeof(double), hipMemcpyDeviceToDevice,
-                          c.stream));
-      if (!right) reverse_core(v[i], vrev[i], d);
+    {
+      const double *const src[2] = {Tb + doff[0], Tb + doff[1]};
+      copy_pairs(c, 2, dst, src, dsz);
     }
+    if (!right)
+      for (int i = 0; i < 2; ++i) reverse_core(v[i], vrev[i], d);
   }
 
   // environments at the new bond after a shift: the right-hand-side
