@@ -256,14 +256,17 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_gemm(GemmK g) {
   const Prob &P = g.p[pi];
 
   int64_t bid = (int64_t)blockIdx.x - P.block0;
-  // single-problem launches: workgroups are dealt round-robin to the 8 XCDs
-  // (each with its own L2), so renumber the blocks such that every XCD walks
-  // a contiguous range of tiles, N-tile fastest: the tiles sharing an A row
-  // panel then run back to back on one XCD and read it from its L2
-  const bool xcd = (g.np == 1) && (P.tn > 1);
+  // every problem starts at a multiple of 8 blocks; the padding blocks after
+  // a problem's last tile have nothing to do
+  const int64_t ptotal = (int64_t)P.tm * P.tn * P.ksplit * P.B1 * P.B2;
+  if (bid >= ptotal) return;
+  // workgroups are dealt round-robin to the 8 XCDs (each with its own L2),
+  // so renumber each problem's blocks such that every XCD walks a contiguous
+  // range of its tiles, N-tile fastest: the tiles sharing an A row panel then
+  // run back to back on one XCD and read it from its L2
+  const bool xcd = (P.tn > 1);
   if (xcd) {
-    const int64_t total = (int64_t)P.tm * P.tn * P.ksplit * P.B1 * P.B2;
-    const int64_t l8 = total & ~(int64_t)7;
+    const int64_t l8 = ptotal & ~(int64_t)7;
     if (bid < l8) bid = (bid & 7) * (l8 >> 3) + (bid >> 3);
   }
   const int tiles = P.tm * P.tn;
@@ -833,6 +836,8 @@ void launch_group(Ctx &c, int np, const Gemm *q, int ngroups, const int *group,
       P.direct = (P.ksplit == 1 && nsrc[group[i]] == 1 && X[group[i]] == nullptr) ? 1 : 0;
       part_off[g.np - 1] = part_need;
       if (!P.direct) part_need += (int64_t)P.ksplit * P.M * P.N * P.B1 * P.B2;
+      // problems start on a multiple of 8 blocks (one per XCD, see k_gemm)
+      blocks = (blocks + 7) & ~(int64_t)7;
       P.block0 = blocks;
       blocks += out_tiles * P.ksplit;
     }
