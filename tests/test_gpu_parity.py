@@ -239,6 +239,32 @@ def test_project_matches_oracle_split_k_matvec(Q, ctx):
         assert M.rel_l2(v[i].cores(), ref[i]) < TOL
 
 
+def test_project_cg_iteration_limit(Q, ctx):
+    """cg_maxit = 3: every local solve stops after three iterations (the CG
+    step runs inside the matvec, the limit is tested in its reduction); the
+    state, the iteration counts and the warning match the oracle's textbook
+    CG stopped at the same iteration."""
+    n, chi = 5, 8
+    dx = 1.0 / (1 << n)
+    u = I.decaying_jet(n)
+    b = _mps_pair(u, chi)
+    a = [M.scale(c, 0.25) for c in b]
+    h = 1e-3 / 3
+    prm = Q.params(re=1e3, dt=1e-3, chi=chi, dx=dx, max_sweeps=2, cg_maxit=3)
+    v = [dev(Q, c) for c in a]
+    rc, st = Q.project(ctx, [dev(Q, c) for c in a], [dev(Q, c) for c in b], h, prm, v)
+    ost = S.Stats()
+    ref = S.project(a, b, h, S.Params(re=1e3, dt=1e-3, chi=chi, dx=dx, max_sweeps=2,
+                                      cg_maxit=3), a, ost)
+    assert rc == Q.W_CG_MAXIT
+    assert ost.cg_maxit_hits > 0 and st['cg_maxit_hits'] == ost.cg_maxit_hits
+    assert st['cg_iters_max'] == 3
+    assert st['cg_iters_total'] == ost.cg_iters_total
+    for i in range(2):
+        assert v[i].bonds == M.bonds(ref[i])
+        assert M.rel_l2(v[i].cores(), ref[i]) < TOL
+
+
 @pytest.mark.parametrize('flow,n,chi', [('shear', 5, 8), ('jet', 5, 8), ('spectrum', 6, 16)])
 def test_rk4_matches_oracle(Q, ctx, flow, n, chi):
     dx = 1.0 / (1 << n)
