@@ -11,7 +11,8 @@ computes on the N x N grid:
     (I + mu h^2 D^T D) v = a - h B(b), D v = D_1 v_1 + D_2 v_2, solved
     per Fourier mode in closed form (D_j is circulant);
   * RK4 as four Euler minimisations with the b-table (App. B, Table RK4,
-    Eqs. U1-U4).
+    Eqs. U1-U4); RK1 as one minimisation and RK2 as the midpoint pair of
+    minimisations (App. B, Eqs. euler, midpoint_calc, full_calc).
 """
 import numpy as np
 
@@ -109,6 +110,32 @@ def rk4_step(u, dt, re, mu, dx, lap_mode=0):
             b = (c * U[-1][0] + cu * u[0], c * U[-1][1] + cu * u[1])
         U.append(euler_project(a, b, RK4_H[k] * dt, re, mu, dx, lap_mode))
     return (sum(x[0] for x in U), sum(x[1] for x in U))
+
+
+def rk1_step(u, dt, re, mu, dx, lap_mode=0):
+    """Explicit Euler as one minimisation (App. B, Eq. euler): a = b = u."""
+    return euler_project(u, u, dt, re, mu, dx, lap_mode)
+
+
+def rk2_step(u, dt, re, mu, dx, lap_mode=0):
+    """Midpoint RK2 as two minimisations (App. B, Eqs. midpoint_calc,
+    full_calc): u_mid from (a, b, h) = (u, u, dt/2), then (u, u_mid, dt)."""
+    mid = euler_project(u, u, 0.5 * dt, re, mu, dx, lap_mode)
+    return euler_project(u, mid, dt, re, mu, dx, lap_mode)
+
+
+def classical_euler(u, dt, re, dx, lap_mode=0):
+    """Textbook explicit Euler on du/dt = -B(u) (no penalty)."""
+    B = B_field(u[0], u[1], re, dx, lap_mode)
+    return (u[0] - dt * B[0], u[1] - dt * B[1])
+
+
+def classical_midpoint(u, dt, re, dx, lap_mode=0):
+    """Textbook explicit midpoint rule on du/dt = -B(u) (no penalty)."""
+    B = B_field(u[0], u[1], re, dx, lap_mode)
+    m = (u[0] - 0.5 * dt * B[0], u[1] - 0.5 * dt * B[1])
+    Bm = B_field(m[0], m[1], re, dx, lap_mode)
+    return (u[0] - dt * Bm[0], u[1] - dt * Bm[1])
 
 
 def classical_rk4(u, dt, re, dx, lap_mode=0):

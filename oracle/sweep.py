@@ -20,6 +20,11 @@ tolerance (Sec. II.C) or after max_sweeps sweeps.
 RK4 (App. B, Table RK4, Eqs. U1-U4): four minimisations with a = u/4,
 h = dt/6, dt/3, dt/3, dt/6 and b = u, 3 U1 + u/4, 3/2 U2 + 5/8 u,
 3 U3 + u/4; the new state is the sum U1 + U2 + U3 + U4 compressed to chi.
+
+RK1 and RK2 (App. B, Eqs. euler, midpoint_calc, full_calc): explicit Euler is
+one minimisation with a = b = u, h = dt; the midpoint method takes
+u_mid = argmin Theta(v; u, u, dt/2), then argmin Theta(v; u, u_mid, dt).
+Every minimisation starts from the guess v = u (the paper does not say).
 """
 from dataclasses import dataclass
 
@@ -272,3 +277,23 @@ def rk4_step(u, prm, stats=None):
     new = [M.truncate(M.add([1.0] * 4, [U[k][i] for k in range(4)]), prm.chi,
                       prm.svd_rtol)[0] for i in range(2)]
     return new, st
+
+
+def rk1_step(u, prm, stats=None):
+    """One explicit Euler step (App. B, Eq. euler): argmin Theta(v; u, u, dt),
+    from the guess u; returns (u_new, [stats])."""
+    s = Stats()
+    new = project([M.copy(u[0]), M.copy(u[1])], [M.copy(u[0]), M.copy(u[1])], prm.dt, prm,
+                  [M.copy(u[0]), M.copy(u[1])], s)
+    return new, [s]
+
+
+def rk2_step(u, prm, stats=None):
+    """One midpoint (RK2) step (App. B, Eqs. midpoint_calc, full_calc): the
+    state at t + dt/2 from Theta(v; u, u, dt/2), then the full step from
+    Theta(v; u, u_mid, dt), both from the guess u; returns (u_new, stats)."""
+    a = [M.copy(u[0]), M.copy(u[1])]
+    s1, s2 = Stats(), Stats()
+    mid = project(a, a, 0.5 * prm.dt, prm, [M.copy(u[0]), M.copy(u[1])], s1)
+    new = project(a, mid, prm.dt, prm, [M.copy(u[0]), M.copy(u[1])], s2)
+    return new, [s1, s2]

@@ -47,6 +47,47 @@ def test_mu_zero_rk4_is_classical_rk4():
         np.testing.assert_allclose(a[i], b[i], atol=1e-14)
 
 
+def test_mu_zero_rk1_rk2_are_textbook_euler_and_midpoint():
+    """At mu = 0 the minimiser is a - h B(b), so the RK1 / RK2 schedules
+    (App. B, Eqs. euler, midpoint_calc, full_calc) must be the textbook
+    explicit Euler and midpoint rules."""
+    n = 4
+    dx = 1.0 / (1 << n)
+    u = I.spectrum(n, 4, k0=3.0)
+    for mine, ref in ((Dn.rk1_step, Dn.classical_euler), (Dn.rk2_step, Dn.classical_midpoint)):
+        a = mine(u, 1e-3, 500.0, 0.0, dx)
+        b = ref(u, 1e-3, 500.0, dx)
+        for i in range(2):
+            np.testing.assert_allclose(a[i], b[i], atol=1e-14)
+
+
+def test_rk1_rk2_observed_order():
+    """Global error at a fixed time against a fine RK4 reference halves with
+    the step for RK1 and quarters for RK2 (mu = 0: pure time integration)."""
+    n = 4
+    dx = 1.0 / (1 << n)
+    u0 = I.spectrum(n, 4, k0=2.0)
+    T, re = 0.04, 200.0
+
+    def run(step, dt):
+        u = u0
+        for _ in range(int(round(T / dt))):
+            u = step(u, dt, re, 0.0, dx)
+        return u
+
+    ref = u0
+    for _ in range(400):
+        ref = Dn.classical_rk4(ref, T / 400, re, dx)
+
+    def err(step, dt):
+        u = run(step, dt)
+        return float(np.sqrt(sum(np.sum((u[i] - ref[i]) ** 2) for i in range(2))))
+
+    for step, lo, hi in ((Dn.rk1_step, 1.6, 2.4), (Dn.rk2_step, 3.3, 4.7)):
+        ratio = err(step, T / 8) / err(step, T / 16)
+        assert lo < ratio < hi, (step.__name__, ratio)
+
+
 def test_skew_symmetric_convection_conserves_energy():
     n = 5
     dx = 1.0 / (1 << n)
@@ -97,6 +138,21 @@ def test_rk4_full_rank_equals_grid_step():
     prm = S.Params(re=1e3, dt=1e-3, chi=64, dx=dx, max_sweeps=1)
     new, _ = S.rk4_step(uc, prm)
     ref = Dn.rk4_step(u, prm.dt, prm.re, prm.mu, dx)
+    for i in range(2):
+        np.testing.assert_allclose(M.to_dense(new[i]), ref[i], atol=1e-11)
+
+
+@pytest.mark.parametrize('order', [1, 2])
+def test_rk1_rk2_full_rank_equal_grid_step(order):
+    n = 4
+    dx = 1.0 / (1 << n)
+    u = I.spectrum(n, 2, k0=3.0)
+    uc = _mps_of(u, 64)
+    u = (M.to_dense(uc[0]), M.to_dense(uc[1]))
+    prm = S.Params(re=1e3, dt=1e-3, chi=64, dx=dx, max_sweeps=1)
+    new, st = (S.rk1_step if order == 1 else S.rk2_step)(uc, prm)
+    assert len(st) == order
+    ref = (Dn.rk1_step if order == 1 else Dn.rk2_step)(u, prm.dt, prm.re, prm.mu, dx)
     for i in range(2):
         np.testing.assert_allclose(M.to_dense(new[i]), ref[i], atol=1e-11)
 
