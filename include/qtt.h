@@ -200,6 +200,18 @@ int qtt_project(qtt_ctx *ctx, const qtt_mps *a, const qtt_mps *b, double h,
  * bonds min(chi, 4^k, 4^(n-k)). */
 int qtt_rk4_step(qtt_ctx *ctx, qtt_mps *u, const qtt_params *p, qtt_stats *stats);
 
+/* One time step in place on u (array of two MPS) with the RK schedule of
+ * the given order (App. B): order 1 is explicit Euler (Eq. euler), one
+ * minimisation of Theta with (a, b, h) = (u, u, dt); order 2 is the
+ * midpoint rule (Eqs. midpoint_calc, full_calc): u_mid from (u, u, dt/2),
+ * then u from (u, u_mid, dt); order 4 is qtt_rk4_step.  Orders 1 and 2 start
+ * every minimisation from the guess u and keep u's bond profile (no
+ * truncation, no capacity beyond u's current size); order 4 needs the
+ * capacity qtt_rk4_step states.  Any other order: QTT_E_ARG.  Warnings as
+ * qtt_project. */
+int qtt_rk_step(qtt_ctx *ctx, qtt_mps *u, const qtt_params *p, int32_t order,
+                qtt_stats *stats);
+
 /* One RK4 step (as qtt_rk4_step) of each of nflows independent flows, for
  * many flows of uneven size at once.  u holds 2 * nflows MPS (flow f:
  * u[2f], u[2f+1]), p and stats (may be NULL) nflows entries.  The flows are

@@ -303,6 +303,29 @@ int qtt_rk4_step(qtt_ctx *ctx, qtt_mps *u, const qtt_params *p, qtt_stats *stats
   });
 }
 
+int qtt_rk_step(qtt_ctx *ctx, qtt_mps *u, const qtt_params *p, int32_t order, qtt_stats *stats) {
+  return guard(ctx, [&] {
+    check_params(p);
+    if (!u || (order != 1 && order != 2 && order != 4))
+      qtt::fail(QTT_E_ARG, "rk_step: bad arguments (order 1, 2 or 4)");
+    reg(ctx->c, u[0]);
+    reg(ctx->c, u[1]);
+    qtt::Mps um[2] = {qtt::from_c(u[0]), qtt::from_c(u[1])};
+    for (int i = 0; i < 2; ++i) check_finite(ctx->c, um[i], "rk_step: state");
+    if (stats) std::memset(stats, 0, sizeof(qtt_stats));
+    int warn = 0;
+    try {
+      qtt::rk_step(ctx->c, um, *p, order, stats);
+    } catch (qtt::Error &e) {
+      if (e.code <= 0) throw;
+      warn = e.code;
+    }
+    qtt::to_c(um[0], &u[0]);
+    qtt::to_c(um[1], &u[1]);
+    if (warn) throw qtt::Error{warn, "rk_step: warning"};
+  });
+}
+
 int qtt_rk4_step_batched(qtt_ctx *ctx, int32_t nflows, qtt_mps *u, const qtt_params *p,
                          qtt_stats *stats, int32_t workers) {
   return guard(ctx, [&] {

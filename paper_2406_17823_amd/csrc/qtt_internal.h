@@ -366,6 +366,8 @@ struct StageCache {
 void project(Ctx &c, const Mps a[2], const Mps b[2], double h, const qtt_params &p, Mps v[2],
              qtt_stats *st, int stage, StageCache *cache = nullptr);
 void rk4_step(Ctx &c, Mps u[2], const qtt_params &p, qtt_stats *st);
+// order 1 (explicit Euler), 2 (midpoint) or 4 (rk4_step)
+void rk_step(Ctx &c, Mps u[2], const qtt_params &p, int order, qtt_stats *st);
 
 // ---------------------------------------------------------------- learned preconditioner
 void pc_init(Ctx &c);                   // allocate and draw the weights once

@@ -1205,6 +1205,59 @@ void project(Ctx &c, const Mps a[2], const Mps b[2], double h, const qtt_params 
   if (S.warn) throw Error{S.warn, "project: warning"};
 }
 
+// RK1 / RK2 schedules (App. B, Eqs. euler, midpoint_calc, full_calc): one
+// minimisation with (a, b, h) = (u, u, dt), or the midpoint pair (u, u, dt/2)
+// then (u, u_mid, dt); every minimisation starts from the guess u, so the
+// second one reuses the first one's cached canonical guess and b-free
+// environments.  The state keeps its bond profile (the trial MPS's).
+static void rk_low_order(Ctx &c, Mps u[2], const qtt_params &p, int order, qtt_stats *st) {
+  const int n = u[0].n;
+  if (u[1].n != n) fail(QTT_E_SHAPE, "rk_step: site counts differ");
+  for (int i = 0; i < 2; ++i) check_profile(u[i], "rk_step: state");
+  Mps a[2], mid[2], v[2];
+  for (int i = 0; i < 2; ++i) {
+    const int64_t sz = u[i].size();
+    a[i] = u[i];
+    a[i].data = c.buf("rkl_a" + std::to_string(i), sz);
+    a[i].capacity = sz;
+    mps_copy(c, u[i], a[i]);
+    mid[i] = u[i];
+    mid[i].data = c.buf("rkl_m" + std::to_string(i), sz);
+    mid[i].capacity = sz;
+    v[i] = u[i];
+    v[i].data = c.buf("rkl_v" + std::to_string(i), sz);
+    v[i].capacity = sz;
+  }
+  int warn = 0;
+  auto run = [&](auto &&f) {
+    try {
+      f();
+    } catch (Error &e) {
+      if (e.code > 0) warn = std::max(warn, e.code);
+      else throw;
+    }
+  };
+  StageCache cache;
+  if (order == 1) {
+    for (int i = 0; i < 2; ++i) mps_copy(c, a[i], v[i]);
+    run([&] { project(c, a, a, p.dt, p, v, st, 0, &cache); });
+  } else {
+    for (int i = 0; i < 2; ++i) mps_copy(c, a[i], mid[i]);
+    run([&] { project(c, a, a, 0.5 * p.dt, p, mid, st, 0, &cache); });
+    for (int i = 0; i < 2; ++i) mps_copy(c, a[i], v[i]);
+    run([&] { project(c, a, mid, p.dt, p, v, st, 1, &cache); });
+  }
+  for (int i = 0; i < 2; ++i) mps_copy(c, v[i], u[i]);
+  c.sync();
+  if (warn) throw Error{warn, "rk_step: warning"};
+}
+
+void rk_step(Ctx &c, Mps u[2], const qtt_params &p, int order, qtt_stats *st) {
+  if (order == 4) rk4_step(c, u, p, st);
+  else if (order == 1 || order == 2) rk_low_order(c, u, p, order, st);
+  else fail(QTT_E_ARG, "rk_step: order must be 1, 2 or 4");
+}
+
 void rk4_step(Ctx &c, Mps u[2], const qtt_params &p, qtt_stats *st) {
   const int n = u[0].n;
   if (u[1].n != n) fail(QTT_E_SHAPE, "rk4: site counts differ");

@@ -61,7 +61,7 @@ SYMBOLS = ['qtt_kernel_timing', 'qtt_kernel_stats_read', 'qtt_ctx_create', 'qtt_
            'qtt_mpo_derivative', 'qtt_add', 'qtt_truncate', 'qtt_apply_mpo', 'qtt_hadamard',
            'qtt_inner', 'qtt_to_dense', 'qtt_from_dense', 'qtt_project', 'qtt_rk4_step',
            'qtt_precond_config', 'qtt_precond_info', 'qtt_precond_weights', 'qtt_precond_grad',
-           'qtt_rk4_step_batched']
+           'qtt_rk4_step_batched', 'qtt_rk_step']
 
 _lib = None
 
@@ -93,6 +93,7 @@ def lib():
         'qtt_project': (I32, [P, pm, pm, D, ctypes.POINTER(c_params), pm,
                               ctypes.POINTER(c_stats)]),
         'qtt_rk4_step': (I32, [P, pm, ctypes.POINTER(c_params), ctypes.POINTER(c_stats)]),
+        'qtt_rk_step': (I32, [P, pm, ctypes.POINTER(c_params), I32, ctypes.POINTER(c_stats)]),
         'qtt_kernel_timing': (I32, [P, I32, I32]),
         'qtt_kernel_stats_read': (I32, [P, I32, ctypes.POINTER(c_kstats)]),
         'qtt_precond_config': (I32, [P, I32, D, ctypes.c_uint64, I32]),
@@ -337,6 +338,18 @@ def rk4_step(ctx, u, prm):
     U = (c_mps * 2)(u[0].struct(), u[1].struct())
     st = c_stats()
     rc = ctx.check(lib().qtt_rk4_step(ctx.h, U, ctypes.byref(prm), ctypes.byref(st)), 'rk4_step')
+    u[0].take(U[0])
+    u[1].take(U[1])
+    return rc, st.as_dict()
+
+
+def rk_step(ctx, u, prm, order):
+    """One step of the RK schedule of the given order (1: explicit Euler,
+    2: midpoint, 4: RK4) in place on u; returns (code, stats dict)."""
+    U = (c_mps * 2)(u[0].struct(), u[1].struct())
+    st = c_stats()
+    rc = ctx.check(lib().qtt_rk_step(ctx.h, U, ctypes.byref(prm), int(order), ctypes.byref(st)),
+                   'rk_step')
     u[0].take(U[0])
     u[1].take(U[1])
     return rc, st.as_dict()

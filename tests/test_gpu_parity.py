@@ -281,7 +281,55 @@ def test_rk4_matches_oracle(Q, ctx, flow, n, chi):
         assert M.rel_l2(d[i].cores(), ref[i]) < TOL
 
 
+@pytest.mark.parametrize('order,flow,n,chi', [(1, 'jet', 5, 8), (2, 'jet', 5, 8),
+                                               (1, 'spectrum', 6, 16), (2, 'spectrum', 6, 16)])
+def test_rk1_rk2_match_oracle(Q, ctx, order, flow, n, chi):
+    """Explicit Euler and midpoint schedules (one and two minimisations from
+    the guess u) against the oracle's, through the C ABI."""
+    dx = 1.0 / (1 << n)
+    u = I.decaying_jet(n) if flow == 'jet' else I.spectrum(n, 3, 4.0)
+    uc = _mps_pair(u, chi)
+    d = [dev(Q, c) for c in uc]
+    prm = Q.params(re=1e3, dt=1e-3, chi=chi, dx=dx, max_sweeps=2)
+    rc, st = Q.rk_step(ctx, d, prm, order)
+    assert rc == 0
+    step = S.rk1_step if order == 1 else S.rk2_step
+    ref, ost = step(uc, S.Params(re=1e3, dt=1e-3, chi=chi, dx=dx, max_sweeps=2))
+    for i in range(2):
+        assert d[i].bonds == M.bonds(uc[i]) == M.bonds(ref[i])
+        assert M.rel_l2(d[i].cores(), ref[i]) < TOL
+    assert st['cg_solves'] == sum(s.cg_solves for s in ost)
+    assert abs(st['cg_iters_total'] - sum(s.cg_iters_total for s in ost)) <= \
+        2 * st['cg_solves']
+
+
+def test_rk_step_order_four_is_rk4_step(Q, ctx):
+    n, chi = 5, 8
+    dx = 1.0 / (1 << n)
+    uc = _mps_pair(I.shear_layer(n), chi)
+    cap = Q.mps_size(Q.canonical_bonds(n, chi))
+    prm = Q.params(re=1e3, dt=1e-3, chi=chi, dx=dx, max_sweeps=1)
+    d1 = [dev(Q, c, capacity=cap) for c in uc]
+    d2 = [dev(Q, c, capacity=cap) for c in uc]
+    assert Q.rk4_step(ctx, d1, prm)[0] == 0
+    assert Q.rk_step(ctx, d2, prm, 4)[0] == 0
+    for i in range(2):
+        assert d1[i].bonds == d2[i].bonds
+        assert np.array_equal(np.concatenate([c.ravel() for c in d1[i].cores()]),
+                              np.concatenate([c.ravel() for c in d2[i].cores()]))
+
+
 # ---------------------------------------------------------------- error paths
+def test_rk_step_bad_order(Q, ctx):
+    n, chi = 4, 4
+    uc = _mps_pair(I.shear_layer(n), chi)
+    d = [dev(Q, c) for c in uc]
+    prm = Q.params(re=1e3, dt=1e-3, chi=chi, dx=1.0 / (1 << n))
+    with pytest.raises(Q.QttError) as e:
+        Q.rk_step(ctx, d, prm, 3)
+    assert e.value.code == -1  # QTT_E_ARG
+
+
 def test_capacity_error(Q, ctx):
     x = rand([1, 4, 4, 1], 30)
     y = Q.MPS.empty([1, 1, 1, 1], capacity=4)
