@@ -58,6 +58,10 @@ def parse():
     ap.add_argument('--cpu-sample', type=int, default=1, help='time the CPU oracle sample')
     ap.add_argument('--save-state', default='', help='write the state after warm-up (.npz)')
     ap.add_argument('--load-state', default='', help='start from a saved state (no spin-up)')
+    ap.add_argument('--schedules', default='',
+                    help='also time the RK1 / RK2 schedules (e.g. "1,2") of every path from '
+                         'the same state; reported under "schedules" with the relative L2 '
+                         'difference to the float64 RK4 result after the same steps')
     ap.add_argument('--calib-copy-mib', type=int, default=0,
                     help='run one device-to-device copy of this many MiB before the timed '
                          'steps (reference dispatch for hardware byte counters)')
@@ -236,6 +240,37 @@ def main():
             results[p_]['rel_l2_vs_f64'] = max(
                 rel_l2(Q, ctx, finals[p_][i], finals['f64'][i], chi) for i in range(2))
 
+    schedules = None
+    if args.schedules:
+        schedules = {}
+        for order in [int(x) for x in args.schedules.split(',') if x]:
+            res = {}
+            for path in paths:
+                prm = prm_for(path)
+                w = [clone(Q, state[0]), clone(Q, state[1])]
+                Q.rk_step(ctx, w, prm, order)  # untimed: workspace growth, graphs
+                del w
+                u = [clone(Q, state[0]), clone(Q, state[1])]
+                cg_total, cg_solves = 0, 0
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                for _ in range(args.steps):
+                    rc, st = Q.rk_step(ctx, u, prm, order)
+                    cg_total += st['cg_iters_total']
+                    cg_solves += st['cg_solves']
+                torch.cuda.synchronize()
+                el = time.perf_counter() - t1
+                r = dict(steps_per_s=args.steps / el, cg_iters_per_solve=cg_total / max(cg_solves, 1),
+                         bonds=[u[0].bonds, u[1].bonds])
+                if 'f64' in finals:
+                    r['rel_l2_vs_rk4_f64'] = max(rel_l2(Q, ctx, u[i], finals['f64'][i], chi)
+                                                 for i in range(2))
+                res[path] = r
+                log(f'rk{order} {path}', r)
+            schedules[f'rk{order}'] = res
+        if 'f64' in finals:
+            schedules['rk4_f64_bonds'] = [finals['f64'][0].bonds, finals['f64'][1].bonds]
+
     # roofline of the dominant kernel of the timed (value) path
     ks = kstats[main_path]
 
@@ -300,6 +335,8 @@ def main():
                 paths={k: dict(v, **({} if k not in kstats else {})) for k, v in results.items()},
                 rel_l2_mixed_vs_f64=rel,
                 roofline=roofline, cpu_baseline=cpu)
+    if schedules is not None:
+        line['schedules'] = schedules
     print(json.dumps(line), flush=True)
     ctx.close()
 
