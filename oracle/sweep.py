@@ -21,6 +21,12 @@ RK4 (App. B, Table RK4, Eqs. U1-U4): four minimisations with a = u/4,
 h = dt/6, dt/3, dt/3, dt/6 and b = u, 3 U1 + u/4, 3/2 U2 + 5/8 u,
 3 U3 + u/4; the new state is the sum U1 + U2 + U3 + U4 compressed to chi.
 
+Explicit right-hand side (rhs_mode 1, the other reading of the Hadamard
+term): B(b) is fitted once as a chi-bounded MPS w, a least-squares fit on
+the bonds of b by the same one-site sweep with the B(b) networks alone (the
+local matrix is the identity), and each minimisation then sees a - h w
+through two layer-free networks per component.
+
 RK1 and RK2 (App. B, Eqs. euler, midpoint_calc, full_calc): explicit Euler is
 one minimisation with a = b = u, h = dt; the midpoint method takes
 u_mid = argmin Theta(v; u, u, dt/2), then argmin Theta(v; u, u_mid, dt).
@@ -47,6 +53,7 @@ class Params:
     max_sweeps: int = 2
     lap_mode: int = 0          # 0: three-point D_j^2, 1: D_j o D_j
     svd_rtol: float = 1e-12    # relative singular-value cutoff in truncation
+    rhs_mode: int = 0          # 0: B(b) inside the networks, 1: B(b) fitted first
 
 
 @dataclass
@@ -147,21 +154,35 @@ class Network:
         return open_site(self.L[d], self.layer_cores(d), ket_core, self.R[d])
 
 
-def build_networks(a, b, h, prm, n):
-    """Right-hand-side networks and penalty networks of the local system."""
+def build_networks(a, b, h, prm, n, w=None, fit=False):
+    """Right-hand-side networks and penalty networks of the local system.
+
+    fit: the networks of B_i(b) alone and no penalty (the local solution is
+    the projected right-hand side: a least-squares fit of B(b) on the trial
+    bonds); w given: the right-hand side a_i - h w_i from a fitted B."""
     D = [O.derivative_mpo(n, 1, 1, prm.dx), O.derivative_mpo(n, 2, 1, prm.dx)]
     DT = [O.mpo_transpose(W) for W in D]
     Lap = O.laplacian_mpo(n, prm.dx, prm.lap_mode)
-    H = [hadamard_mpo(b[0]), hadamard_mpo(b[1])]
     rhs = []
-    for i in range(2):
-        rhs.append(Network(i, [], ('fixed', a[i]), 1.0))
-        for j in range(2):
-            # b_j (.) D_j b_i  and  D_j (b_j (.) b_i), weight -h/2 each
-            rhs.append(Network(i, [H[j], D[j]], ('fixed', b[i]), -0.5 * h))
-            rhs.append(Network(i, [D[j], H[j]], ('fixed', b[i]), -0.5 * h))
-        rhs.append(Network(i, [Lap], ('fixed', b[i]), h / prm.re))
+    if w is not None:
+        for i in range(2):
+            rhs.append(Network(i, [], ('fixed', a[i]), 1.0))
+            rhs.append(Network(i, [], ('fixed', w[i]), -h))
+    else:
+        H = [hadamard_mpo(b[0]), hadamard_mpo(b[1])]
+        # B_i(b) = sum_j 1/2 (b_j (.) D_j b_i + D_j (b_j (.) b_i)) - (1/Re) D_j^2 b_i,
+        # entering the right-hand side with the weight -h (weight 1 when fitted)
+        g = 1.0 if fit else -h
+        for i in range(2):
+            if not fit:
+                rhs.append(Network(i, [], ('fixed', a[i]), 1.0))
+            for j in range(2):
+                rhs.append(Network(i, [H[j], D[j]], ('fixed', b[i]), 0.5 * g))
+                rhs.append(Network(i, [D[j], H[j]], ('fixed', b[i]), 0.5 * g))
+            rhs.append(Network(i, [Lap], ('fixed', b[i]), -g / prm.re))
     pen = {}
+    if fit:
+        return rhs, pen
     for i in range(2):
         for j in range(2):
             pen[(i, j)] = Network(i, [DT[i], D[j]], ('v', j), prm.mu * h * h)
@@ -214,6 +235,11 @@ def local_solve(d, v, rhs_nets, pen, prm, stats):
         return np.concatenate([y[0].reshape(-1), y[1].reshape(-1)])
 
     x0 = np.concatenate([v[0][d].reshape(-1), v[1][d].reshape(-1)])
+    if not pen:
+        # fit of B(b): the local matrix is the identity
+        v[0][d] = rhs[:sizes[0]].reshape(shape[0])
+        v[1][d] = rhs[sizes[0]:].reshape(shape[1])
+        return
     x, its, ok = cg(matvec, rhs, x0, prm.cg_rtol, prm.cg_maxit)
     v[0][d] = x[:sizes[0]].reshape(shape[0])
     v[1][d] = x[sizes[0]:].reshape(shape[1])
@@ -225,12 +251,29 @@ def local_solve(d, v, rhs_nets, pen, prm, stats):
 
 def project(a, b, h, prm, guess, stats=None):
     """argmin_v Theta(v; a, b, h) over MPS with the bonds of the guess
-    (App. B).  Returns the two MPS with the centre at site 0."""
+    (App. B).  Returns the two MPS with the centre at site 0.
+
+    rhs_mode 1 (explicit right-hand side): B(b) is first fitted as one
+    chi-bounded MPS w on the bonds of b (from the guess b, the same sweeps),
+    then Theta is minimised with the right-hand side a - h w."""
     if stats is None:
         stats = Stats()
-    n = len(a[0])
+    if prm.rhs_mode == 1:
+        w = sweep_fit(b, prm, [M.copy(b[0]), M.copy(b[1])])
+        return _sweep(a, None, h, prm, guess, stats, w=w)
+    return _sweep(a, b, h, prm, guess, stats)
+
+
+def sweep_fit(b, prm, guess):
+    """Least-squares fit of B(b) (Eq. MPS_momentum's convection and diffusion,
+    App. B) on the bonds of the guess by the one-site sweep."""
+    return _sweep(None, b, 0.0, prm, guess, Stats(), fit=True)
+
+
+def _sweep(a, b, h, prm, guess, stats, w=None, fit=False):
+    n = len(guess[0])
     v = [M.right_canonicalize(g) for g in guess]
-    rhs_nets, pen = build_networks(a, b, h, prm, n)
+    rhs_nets, pen = build_networks(a, b, h, prm, n, w=w, fit=fit)
     nets = rhs_nets + list(pen.values())
     for net in nets:
         net.init(v, n)

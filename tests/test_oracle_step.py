@@ -157,6 +157,47 @@ def test_rk1_rk2_full_rank_equal_grid_step(order):
         np.testing.assert_allclose(M.to_dense(new[i]), ref[i], atol=1e-11)
 
 
+def test_fit_of_B_full_rank_equals_grid_B():
+    n = 3
+    dx = 1.0 / (1 << n)
+    u = I.spectrum(n, 9, k0=2.0)
+    b = _mps_of(u, 64)
+    u = (M.to_dense(b[0]), M.to_dense(b[1]))
+    prm = S.Params(re=300.0, dt=1e-3, chi=64, dx=dx, max_sweeps=1)
+    w = S.sweep_fit(b, prm, [M.copy(b[0]), M.copy(b[1])])
+    ref = Dn.B_field(u[0], u[1], prm.re, dx)
+    for i in range(2):
+        np.testing.assert_allclose(M.to_dense(w[i]), ref[i], atol=1e-9 * np.abs(ref[i]).max())
+
+
+def test_explicit_rhs_rk4_full_rank_equals_grid_step():
+    n = 4
+    dx = 1.0 / (1 << n)
+    u = I.spectrum(n, 2, k0=3.0)
+    uc = _mps_of(u, 64)
+    u = (M.to_dense(uc[0]), M.to_dense(uc[1]))
+    prm = S.Params(re=1e3, dt=1e-3, chi=64, dx=dx, max_sweeps=1, rhs_mode=1)
+    new, _ = S.rk4_step(uc, prm)
+    ref = Dn.rk4_step(u, prm.dt, prm.re, prm.mu, dx)
+    for i in range(2):
+        np.testing.assert_allclose(M.to_dense(new[i]), ref[i], atol=1e-11)
+
+
+def test_explicit_rhs_close_to_implicit_when_truncated():
+    """Below full rank the fitted B differs from the exact projection by the
+    fit's truncation; both minimisers stay close on a smooth flow."""
+    n = 5
+    dx = 1.0 / (1 << n)
+    uc = _mps_of(I.decaying_jet(n), 8)
+    a = [M.scale(c, 0.25) for c in uc]
+    prm = S.Params(re=1e3, dt=1e-3, chi=8, dx=dx, max_sweeps=2)
+    imp = S.project(a, uc, 1e-3 / 6, prm, a)
+    prm.rhs_mode = 1
+    exp = S.project(a, uc, 1e-3 / 6, prm, a)
+    for i in range(2):
+        assert M.rel_l2(exp[i], imp[i]) < 1e-3
+
+
 def _isometry(v, i, d):
     """Dense matrix P_i mapping the centre tensor at site d to the state."""
     n = len(v[i])
