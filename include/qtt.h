@@ -109,6 +109,12 @@ typedef struct {
   int32_t lap_mode;   /* 0 = three-point D_j^2, 1 = D_j o D_j                 */
   int32_t prec;       /* QTT_PREC_*                                           */
   int32_t precond;    /* QTT_PC_*                                             */
+  int32_t rhs_mode;   /* 0: B(b) inside the local networks (App. B, Sec. II.C);
+                       * 1: explicit right-hand side: B(b) first fitted as one
+                       * chi-bounded MPS on the bonds of b (one-site sweep,
+                       * least squares, max_sweeps sweeps; cf. Sec. II.B on
+                       * compressing the Hadamard product), then every
+                       * minimisation sees a - h w through layer-free networks */
 } qtt_params;
 
 typedef struct {

@@ -89,6 +89,7 @@ struct Sweep {
   std::vector<Net> rhs;   // right-hand-side networks
   std::vector<Net> pen;   // penalty networks, index 2*i + j
   double mu_h2;
+  bool fit = false;       // fit of B(b): the local solution is the right-hand side
   double *tmp = nullptr, *Tpen = nullptr;
   int64_t tmp_size = 0;
   CGState *st = nullptr;
@@ -783,6 +784,18 @@ struct Sweep {
         q[k] = open_gemm(*grp[k], d, rev, grp[k]->T, rh[grp[k]->bra], grp[k]->coef);
       launch_gemms(cnt, q, grp[0]->f32s(), true);
     }
+    if (fit) {
+      // identity local matrix: the centres are the projected right-hand side
+      double *const dst[2] = {v[0].core(d), v[1].core(d)};
+      const double *const src[2] = {rhs, rhs + s0};
+      const int64_t len[2] = {s0, s1};
+      copy_pairs(c, 2, dst, src, len);
+      if (stats && c.timing) {
+        c.sync();
+        stats->phase_ms[2] += ms_since(t0);
+      }
+      return;
+    }
     auto load_guess = [&] {
       double *const dst[2] = {x, x + s0};
       const double *const src[2] = {v[0].core(d), v[1].core(d)};
@@ -1004,11 +1017,18 @@ void check_profile(const Mps &x, const char *what) {
 
 }  // namespace
 
-void project(Ctx &c, const Mps a[2], const Mps b[2], double h, const qtt_params &p, Mps v[2],
-             qtt_stats *st, int stage, StageCache *cache) {
+// one projection sweep.  Right-hand side: implicit (a and b: a_i - h B_i(b)
+// through the 8 convection and 2 diffusion networks), explicit (a and w:
+// a_i - h w_i through two layer-free networks), or fit (b only: B_i(b)
+// alone and no penalty, so the local solution is the projected right-hand
+// side, a least-squares fit of B(b) on the trial bonds)
+static void project_impl(Ctx &c, const Mps *a, const Mps *b, const Mps *w, double h,
+                         const qtt_params &p, Mps v[2], qtt_stats *st, int stage,
+                         StageCache *cache, bool fit) {
   const int n = v[0].n;
   for (int i = 0; i < 2; ++i) {
-    if (a[i].n != n || b[i].n != n || v[i].n != n) fail(QTT_E_SHAPE, "project: site counts differ");
+    if ((a && a[i].n != n) || (b && b[i].n != n) || (w && w[i].n != n) || v[i].n != n)
+      fail(QTT_E_SHAPE, "project: site counts differ");
     check_profile(v[i], "project: guess");
   }
   if (n < 2) fail(QTT_E_UNSUPPORTED, "project: n < 2");
@@ -1026,6 +1046,7 @@ void project(Ctx &c, const Mps a[2], const Mps b[2], double h, const qtt_params 
   S.v = v;
   S.stats = st;
   S.mu_h2 = p.mu * h * h;
+  S.fit = fit;
 
   const bool reuse = cache && cache->valid;
   if (reuse) {
@@ -1041,14 +1062,17 @@ void project(Ctx &c, const Mps a[2], const Mps b[2], double h, const qtt_params 
   }
 
   // site-reversed copies of the fixed MPS and the trial MPS
-  double *arev[2], *brev[2];
+  double *arev[2] = {nullptr, nullptr}, *brev[2] = {nullptr, nullptr};
+  double *wrev[2] = {nullptr, nullptr};
   for (int i = 0; i < 2; ++i) {
-    arev[i] = c.buf("sw_arev" + std::to_string(i), a[i].size());
-    brev[i] = c.buf("sw_brev" + std::to_string(i), b[i].size());
+    if (a) arev[i] = c.buf("sw_arev" + std::to_string(i), a[i].size());
+    if (b) brev[i] = c.buf("sw_brev" + std::to_string(i), b[i].size());
+    if (w) wrev[i] = c.buf("sw_wrev" + std::to_string(i), w[i].size());
     S.vrev[i] = c.buf("sw_vrev" + std::to_string(i), v[i].size());
     for (int d = 0; d < n; ++d) {
-      S.reverse_core(a[i], arev[i], d);
-      S.reverse_core(b[i], brev[i], d);
+      if (a) S.reverse_core(a[i], arev[i], d);
+      if (b) S.reverse_core(b[i], brev[i], d);
+      if (w) S.reverse_core(w[i], wrev[i], d);
       S.reverse_core(v[i], S.vrev[i], d);
     }
   }
@@ -1057,14 +1081,28 @@ void project(Ctx &c, const Mps a[2], const Mps b[2], double h, const qtt_params 
   const Mpo *D[2] = {D1.get(), D2.get()};
   const int conv_prec = p.prec;  // precision of the 8 convection networks
 
+  // weight of B_i(b) in the right-hand side: -h, or 1 when fitting it
+  const double g = fit ? 1.0 : -h;
   for (int i = 0; i < 2; ++i) {
-    Net ov;
-    ov.bra = i;
-    ov.nl = 0;
-    ov.ket = &a[i];
-    ov.ket_rev = arev[i];
-    ov.coef = 1.0;
-    S.rhs.push_back(ov);
+    if (a) {
+      Net ov;
+      ov.bra = i;
+      ov.nl = 0;
+      ov.ket = &a[i];
+      ov.ket_rev = arev[i];
+      ov.coef = 1.0;
+      S.rhs.push_back(ov);
+    }
+    if (w) {
+      Net ow;
+      ow.bra = i;
+      ow.nl = 0;
+      ow.ket = &w[i];
+      ow.ket_rev = wrev[i];
+      ow.coef = -h;
+      S.rhs.push_back(ow);
+      continue;
+    }
     for (int j = 0; j < 2; ++j)
       for (int form = 0; form < 2; ++form) {
         // form 0: b_j (.) D_j b_i ; form 1: D_j (b_j (.) b_i) ; weight -h/2
@@ -1082,7 +1120,7 @@ void project(Ctx &c, const Mps a[2], const Mps b[2], double h, const qtt_params 
         N.lay[1] = form == 0 ? Dl : H;
         N.ket = &b[i];
         N.ket_rev = brev[i];
-        N.coef = -0.5 * h;
+        N.coef = 0.5 * g;
         N.prec = conv_prec;
         S.rhs.push_back(N);
       }
@@ -1093,14 +1131,14 @@ void project(Ctx &c, const Mps a[2], const Mps b[2], double h, const qtt_params 
     df.lay[0].mpo = LAP.get();
     df.ket = &b[i];
     df.ket_rev = brev[i];
-    df.coef = h / p.re;
+    df.coef = -g / p.re;
     S.rhs.push_back(df);
   }
   std::shared_ptr<Mpo> PEN[2][2];
   for (int i = 0; i < 2; ++i)
     for (int j = 0; j < 2; ++j)
       PEN[i][j] = get_mpo(c, n, "P" + std::to_string(i + 1) + std::to_string(j + 1), p.dx, 0);
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < 2 && !fit; ++i)
     for (int j = 0; j < 2; ++j) {
       // <v_i| D_i^T D_j |v_j> with the two MPOs composed into one of bond 9
       Net N;
@@ -1123,7 +1161,7 @@ void project(Ctx &c, const Mps a[2], const Mps b[2], double h, const qtt_params 
   for (Net &N : S.rhs) all.push_back(&N);
   for (Net &N : S.pen) all.push_back(&N);
   S.alloc(all);
-  S.alloc_pen_tmp();
+  if (!fit) S.alloc_pen_tmp();
   {
     std::vector<Net *> r, q;
     for (Net &N : S.rhs) r.push_back(&N);
@@ -1203,6 +1241,38 @@ void project(Ctx &c, const Mps a[2], const Mps b[2], double h, const qtt_params 
   if (st && stage >= 0 && stage < 4) st->sweeps[stage] += sweeps;
   c.sync();
   if (S.warn) throw Error{S.warn, "project: warning"};
+}
+
+void project(Ctx &c, const Mps a[2], const Mps b[2], double h, const qtt_params &p, Mps v[2],
+             qtt_stats *st, int stage, StageCache *cache) {
+  if (p.rhs_mode != 1) {
+    project_impl(c, a, b, nullptr, h, p, v, st, stage, cache, false);
+    return;
+  }
+  // explicit right-hand side: B(b) fitted on the bonds of b from the guess b
+  // (the same sweeps), then the minimisation with a - h w; no stage cache
+  // (the w network changes from stage to stage)
+  Mps w[2];
+  for (int i = 0; i < 2; ++i) {
+    w[i] = b[i];
+    w[i].data = c.buf("rkx_w" + std::to_string(i), b[i].size());
+    w[i].capacity = b[i].size();
+    mps_copy(c, b[i], w[i]);
+  }
+  int warn = 0;
+  try {
+    project_impl(c, nullptr, b, nullptr, 0.0, p, w, nullptr, stage, nullptr, true);
+  } catch (Error &e) {
+    if (e.code <= 0) throw;
+    warn = e.code;
+  }
+  try {
+    project_impl(c, a, nullptr, w, h, p, v, st, stage, nullptr, false);
+  } catch (Error &e) {
+    if (e.code <= 0) throw;
+    warn = std::max(warn, e.code);
+  }
+  if (warn) throw Error{warn, "project: warning"};
 }
 
 // RK1 / RK2 schedules (App. B, Eqs. euler, midpoint_calc, full_calc): one

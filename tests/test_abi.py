@@ -43,12 +43,46 @@ def test_struct_layouts():
     # qtt_mps: int32 n, int32 bond[17], int64 capacity, pointer data
     assert ctypes.sizeof(qtt.c_mps) == 4 + 17 * 4 + 8 + 8
     assert qtt.c_mps.capacity.offset == 72
-    # qtt_params: 4 doubles, int32 (+pad), double, double, int32 (+pad), double, 4 int32
+    # qtt_params: 4 doubles, int32 (+pad), double, double, int32 (+pad), double, 5 int32 (+pad)
     assert qtt.c_params.svd_rtol.offset == 40
     assert qtt.c_params.sweep_rtol.offset == 64
-    assert ctypes.sizeof(qtt.c_params) == 88
+    assert qtt.c_params.rhs_mode.offset == 88
+    assert ctypes.sizeof(qtt.c_params) == 96
     assert qtt.c_stats.discarded_sq.offset == 40
     assert ctypes.sizeof(qtt.c_stats) == 40 + 8 + 64
+
+
+def test_struct_layouts_match_the_c_compiler(tmp_path):
+    """sizeof / offsetof of the header's structs as a C compiler lays them
+    out, against the binding's ctypes mirrors."""
+    import shutil
+    import subprocess
+    from paper_2406_17823_amd import qtt
+    cc = shutil.which('gcc') or shutil.which('cc')
+    if cc is None:
+        pytest.skip('no C compiler')
+    src = tmp_path / 'layout.c'
+    fields = {'qtt_params': [f[0] for f in qtt.c_params._fields_],
+              'qtt_stats': [f[0] for f in qtt.c_stats._fields_],
+              'qtt_mps': [f[0] for f in qtt.c_mps._fields_]}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "qtt.h"', 'int main(void) {']
+    for st, fs in fields.items():
+        lines.append(f'  printf("{st} %zu\\n", sizeof({st}));')
+        for f in fs:
+            lines.append(f'  printf("{st}.{f} %zu\\n", offsetof({st}, {f}));')
+    lines += ['  return 0;', '}']
+    src.write_text('\n'.join(lines) + '\n')
+    exe = tmp_path / 'layout'
+    subprocess.run([cc, '-std=c11', '-I', os.path.join(ROOT, 'include'), str(src), '-o', str(exe)],
+                   check=True)
+    out = dict(line.split() for line in subprocess.run([str(exe)], check=True,
+                                                        capture_output=True, text=True)
+               .stdout.splitlines())
+    for st, ct in (('qtt_params', qtt.c_params), ('qtt_stats', qtt.c_stats),
+                   ('qtt_mps', qtt.c_mps)):
+        assert int(out[st]) == ctypes.sizeof(ct), st
+        for f in fields[st]:
+            assert int(out[f'{st}.{f}']) == getattr(ct, f).offset, (st, f)
 
 
 def test_mps_size_no_device(lib):

@@ -281,6 +281,45 @@ def test_rk4_matches_oracle(Q, ctx, flow, n, chi):
         assert M.rel_l2(d[i].cores(), ref[i]) < TOL
 
 
+@pytest.mark.parametrize('flow,n,chi', [('jet', 5, 8), ('spectrum', 6, 16)])
+def test_project_explicit_rhs_matches_oracle(Q, ctx, flow, n, chi):
+    """rhs_mode 1: B(b) fitted as one chi-bounded MPS on the bonds of b, then
+    the minimisation with a - h w, against the oracle's same route."""
+    dx = 1.0 / (1 << n)
+    u = I.decaying_jet(n) if flow == 'jet' else I.spectrum(n, 2, k0=4.0)
+    b = _mps_pair(u, chi)
+    a = [M.scale(c, 0.25) for c in b]
+    h = 1e-3 / 3
+    prm = Q.params(re=1e3, dt=1e-3, chi=chi, dx=dx, max_sweeps=2, rhs_mode=1)
+    v = [dev(Q, c) for c in a]
+    rc, st = Q.project(ctx, [dev(Q, c) for c in a], [dev(Q, c) for c in b], h, prm, v)
+    assert rc == 0
+    ost = S.Stats()
+    ref = S.project(a, b, h, S.Params(re=1e3, dt=1e-3, chi=chi, dx=dx, max_sweeps=2,
+                                      rhs_mode=1), a, ost)
+    for i in range(2):
+        assert v[i].bonds == M.bonds(ref[i])
+        assert M.rel_l2(v[i].cores(), ref[i]) < TOL
+    assert st['cg_solves'] == ost.cg_solves
+    assert abs(st['cg_iters_total'] - ost.cg_iters_total) <= 2 * ost.cg_solves
+
+
+def test_rk4_explicit_rhs_matches_oracle(Q, ctx):
+    n, chi = 5, 8
+    dx = 1.0 / (1 << n)
+    uc = _mps_pair(I.shear_layer(n), chi)
+    cap = Q.mps_size(Q.canonical_bonds(n, chi))
+    d = [dev(Q, c, capacity=cap) for c in uc]
+    prm = Q.params(re=1e3, dt=1e-3, chi=chi, dx=dx, max_sweeps=1, rhs_mode=1)
+    rc, st = Q.rk4_step(ctx, d, prm)
+    assert rc == 0
+    ref, _ = S.rk4_step(uc, S.Params(re=1e3, dt=1e-3, chi=chi, dx=dx, max_sweeps=1,
+                                     rhs_mode=1))
+    for i in range(2):
+        assert d[i].bonds == M.bonds(ref[i])
+        assert M.rel_l2(d[i].cores(), ref[i]) < TOL
+
+
 @pytest.mark.parametrize('order,flow,n,chi', [(1, 'jet', 5, 8), (2, 'jet', 5, 8),
                                                (1, 'spectrum', 6, 16), (2, 'spectrum', 6, 16)])
 def test_rk1_rk2_match_oracle(Q, ctx, order, flow, n, chi):
@@ -327,6 +366,16 @@ def test_rk_step_bad_order(Q, ctx):
     prm = Q.params(re=1e3, dt=1e-3, chi=chi, dx=1.0 / (1 << n))
     with pytest.raises(Q.QttError) as e:
         Q.rk_step(ctx, d, prm, 3)
+    assert e.value.code == -1  # QTT_E_ARG
+
+
+def test_bad_rhs_mode(Q, ctx):
+    n, chi = 4, 4
+    uc = _mps_pair(I.shear_layer(n), chi)
+    d = [dev(Q, c) for c in uc]
+    prm = Q.params(re=1e3, dt=1e-3, chi=chi, dx=1.0 / (1 << n), rhs_mode=2)
+    with pytest.raises(Q.QttError) as e:
+        Q.project(ctx, d, d, 1e-3, prm, [dev(Q, c) for c in uc])
     assert e.value.code == -1  # QTT_E_ARG
 
 
