@@ -62,6 +62,11 @@ def parse():
                     help='also time the RK1 / RK2 schedules (e.g. "1,2") of every path from '
                          'the same state; reported under "schedules" with the relative L2 '
                          'difference to the float64 RK4 result after the same steps')
+    ap.add_argument('--explicit-rhs', type=int, default=0,
+                    help='also time RK4 with the explicit right-hand side (B(b) fitted as one '
+                         'chi-bounded MPS in this many sweeps, then the minimisations) for every '
+                         'path; reported under "explicit_rhs" with the difference to the '
+                         'float64 implicit step')
     ap.add_argument('--calib-copy-mib', type=int, default=0,
                     help='run one device-to-device copy of this many MiB before the timed '
                          'steps (reference dispatch for hardware byte counters)')
@@ -157,12 +162,13 @@ def main():
                  for c in range(2)]
     log('initial bonds', state[0].bonds, state[1].bonds, f'{time.perf_counter() - t0:.1f}s')
 
-    def prm_for(path):
+    def prm_for(path, rhs_mode=0, fit_sweeps=0):
         return Q.params(re=args.re, dt=args.dt, chi=chi, dx=dx,
                         cg_rtol=args.cg_rtol if path == 'f64' else args.mixed_cg_rtol,
                         cg_maxit=args.cg_maxit, max_sweeps=args.sweeps, svd_rtol=1e-12,
                         prec={'mixed': Q.PREC_F32, 'bf16x3': Q.PREC_BF16X3}.get(path, Q.PREC_F64),
-                        precond=args.precond if path != 'f64' else Q.PC_NONE)
+                        precond=args.precond if path != 'f64' else Q.PC_NONE, rhs_mode=rhs_mode,
+                        fit_sweeps=fit_sweeps)
 
     # spin-up: the jet starts with low QTT rank; the workload is the developed
     # flow whose bonds have reached chi (the paper times steps from t = 1)
@@ -271,6 +277,31 @@ def main():
         if 'f64' in finals:
             schedules['rk4_f64_bonds'] = [finals['f64'][0].bonds, finals['f64'][1].bonds]
 
+    explicit = None
+    if args.explicit_rhs:
+        explicit = {}
+        for path in paths:
+            prm = prm_for(path, rhs_mode=1, fit_sweeps=args.explicit_rhs)
+            w = [clone(Q, state[0]), clone(Q, state[1])]
+            Q.rk4_step(ctx, w, prm)  # untimed: workspace growth, graphs
+            del w
+            u = [clone(Q, state[0]), clone(Q, state[1])]
+            cg_total, cg_solves = 0, 0
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for _ in range(args.steps):
+                rc, st = Q.rk4_step(ctx, u, prm)
+                cg_total += st['cg_iters_total']
+                cg_solves += st['cg_solves']
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t1
+            r = dict(steps_per_s=args.steps / el, cg_iters_per_solve=cg_total / max(cg_solves, 1))
+            if 'f64' in finals:
+                r['rel_l2_vs_implicit_f64'] = max(rel_l2(Q, ctx, u[i], finals['f64'][i], chi)
+                                                  for i in range(2))
+            explicit[path] = r
+            log(f'explicit rhs {path}', r)
+
     # roofline of the dominant kernel of the timed (value) path
     ks = kstats[main_path]
 
@@ -337,6 +368,8 @@ def main():
                 roofline=roofline, cpu_baseline=cpu)
     if schedules is not None:
         line['schedules'] = schedules
+    if explicit is not None:
+        line['explicit_rhs'] = explicit
     print(json.dumps(line), flush=True)
     ctx.close()
 

@@ -115,6 +115,7 @@ typedef struct {
                        * least squares, max_sweeps sweeps; cf. Sec. II.B on
                        * compressing the Hadamard product), then every
                        * minimisation sees a - h w through layer-free networks */
+  int32_t fit_sweeps; /* rhs_mode 1: sweeps of the fit of B(b); 0 = max_sweeps  */
 } qtt_params;
 
 typedef struct {

@@ -32,7 +32,7 @@ one minimisation with a = b = u, h = dt; the midpoint method takes
 u_mid = argmin Theta(v; u, u, dt/2), then argmin Theta(v; u, u_mid, dt).
 Every minimisation starts from the guess v = u (the paper does not say).
 """
-from dataclasses import dataclass
+from dataclasses import dataclass, replace
 
 import numpy as np
 
@@ -54,6 +54,7 @@ class Params:
     lap_mode: int = 0          # 0: three-point D_j^2, 1: D_j o D_j
     svd_rtol: float = 1e-12    # relative singular-value cutoff in truncation
     rhs_mode: int = 0          # 0: B(b) inside the networks, 1: B(b) fitted first
+    fit_sweeps: int = 0        # sweeps of that fit (0: max_sweeps)
 
 
 @dataclass
@@ -267,6 +268,8 @@ def project(a, b, h, prm, guess, stats=None):
 def sweep_fit(b, prm, guess):
     """Least-squares fit of B(b) (Eq. MPS_momentum's convection and diffusion,
     App. B) on the bonds of the guess by the one-site sweep."""
+    if prm.fit_sweeps > 0:
+        prm = replace(prm, max_sweeps=prm.fit_sweeps)
     return _sweep(None, b, 0.0, prm, guess, Stats(), fit=True)
 
 

@@ -54,6 +54,7 @@ void check_params(const qtt_params *p) {
     qtt::fail(QTT_E_ARG, "params: cg_rtol >= 0, cg_maxit >= 1, max_sweeps >= 1");
   if (p->lap_mode != 0 && p->lap_mode != 1) qtt::fail(QTT_E_ARG, "params: lap_mode");
   if (p->rhs_mode != 0 && p->rhs_mode != 1) qtt::fail(QTT_E_ARG, "params: rhs_mode");
+  if (p->fit_sweeps < 0) qtt::fail(QTT_E_ARG, "params: fit_sweeps >= 0");
 }
 
 }  // namespace

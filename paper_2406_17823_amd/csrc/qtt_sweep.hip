@@ -1250,7 +1250,8 @@ void project(Ctx &c, const Mps a[2], const Mps b[2], double h, const qtt_params 
     return;
   }
   // explicit right-hand side: B(b) fitted on the bonds of b from the guess b
-  // (the same sweeps), then the minimisation with a - h w; no stage cache
+  // (fit_sweeps sweeps, else max_sweeps), then the minimisation with a - h w;
+  // no stage cache
   // (the w network changes from stage to stage)
   Mps w[2];
   for (int i = 0; i < 2; ++i) {
@@ -1259,9 +1260,11 @@ void project(Ctx &c, const Mps a[2], const Mps b[2], double h, const qtt_params 
     w[i].capacity = b[i].size();
     mps_copy(c, b[i], w[i]);
   }
+  qtt_params pf = p;
+  if (p.fit_sweeps > 0) pf.max_sweeps = p.fit_sweeps;
   int warn = 0;
   try {
-    project_impl(c, nullptr, b, nullptr, 0.0, p, w, nullptr, stage, nullptr, true);
+    project_impl(c, nullptr, b, nullptr, 0.0, pf, w, nullptr, stage, nullptr, true);
   } catch (Error &e) {
     if (e.code <= 0) throw;
     warn = e.code;

@@ -37,7 +37,7 @@ class c_params(ctypes.Structure):
                 ('cg_rtol', ctypes.c_double), ('cg_maxit', ctypes.c_int32),
                 ('sweep_rtol', ctypes.c_double), ('max_sweeps', ctypes.c_int32),
                 ('lap_mode', ctypes.c_int32), ('prec', ctypes.c_int32), ('precond', ctypes.c_int32),
-                ('rhs_mode', ctypes.c_int32)]
+                ('rhs_mode', ctypes.c_int32), ('fit_sweeps', ctypes.c_int32)]
 
 
 class c_stats(ctypes.Structure):
@@ -226,12 +226,12 @@ class MPO:
 
 def params(re, dt, chi, dx, mu=2.5e5, svd_rtol=1e-12, cg_rtol=1e-12, cg_maxit=1000,
            sweep_rtol=0.0, max_sweeps=2, lap_mode=0, prec=PREC_F64, precond=PC_NONE,
-           rhs_mode=0):
+           rhs_mode=0, fit_sweeps=0):
     p = c_params()
     p.re, p.dt, p.mu, p.dx, p.chi = re, dt, mu, dx, chi
     p.svd_rtol, p.cg_rtol, p.cg_maxit = svd_rtol, cg_rtol, cg_maxit
     p.sweep_rtol, p.max_sweeps, p.lap_mode = sweep_rtol, max_sweeps, lap_mode
-    p.prec, p.precond, p.rhs_mode = prec, precond, rhs_mode
+    p.prec, p.precond, p.rhs_mode, p.fit_sweeps = prec, precond, rhs_mode, fit_sweeps
     return p
 
 

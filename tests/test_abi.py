@@ -43,10 +43,11 @@ def test_struct_layouts():
     # qtt_mps: int32 n, int32 bond[17], int64 capacity, pointer data
     assert ctypes.sizeof(qtt.c_mps) == 4 + 17 * 4 + 8 + 8
     assert qtt.c_mps.capacity.offset == 72
-    # qtt_params: 4 doubles, int32 (+pad), double, double, int32 (+pad), double, 5 int32 (+pad)
+    # qtt_params: 4 doubles, int32 (+pad), double, double, int32 (+pad), double, 6 int32
     assert qtt.c_params.svd_rtol.offset == 40
     assert qtt.c_params.sweep_rtol.offset == 64
     assert qtt.c_params.rhs_mode.offset == 88
+    assert qtt.c_params.fit_sweeps.offset == 92
     assert ctypes.sizeof(qtt.c_params) == 96
     assert qtt.c_stats.discarded_sq.offset == 40
     assert ctypes.sizeof(qtt.c_stats) == 40 + 8 + 64

@@ -281,8 +281,9 @@ def test_rk4_matches_oracle(Q, ctx, flow, n, chi):
         assert M.rel_l2(d[i].cores(), ref[i]) < TOL
 
 
-@pytest.mark.parametrize('flow,n,chi', [('jet', 5, 8), ('spectrum', 6, 16)])
-def test_project_explicit_rhs_matches_oracle(Q, ctx, flow, n, chi):
+@pytest.mark.parametrize('flow,n,chi,fit', [('jet', 5, 8, 0), ('spectrum', 6, 16, 0),
+                                            ('jet', 5, 8, 1)])
+def test_project_explicit_rhs_matches_oracle(Q, ctx, flow, n, chi, fit):
     """rhs_mode 1: B(b) fitted as one chi-bounded MPS on the bonds of b, then
     the minimisation with a - h w, against the oracle's same route."""
     dx = 1.0 / (1 << n)
@@ -290,13 +291,13 @@ def test_project_explicit_rhs_matches_oracle(Q, ctx, flow, n, chi):
     b = _mps_pair(u, chi)
     a = [M.scale(c, 0.25) for c in b]
     h = 1e-3 / 3
-    prm = Q.params(re=1e3, dt=1e-3, chi=chi, dx=dx, max_sweeps=2, rhs_mode=1)
+    prm = Q.params(re=1e3, dt=1e-3, chi=chi, dx=dx, max_sweeps=2, rhs_mode=1, fit_sweeps=fit)
     v = [dev(Q, c) for c in a]
     rc, st = Q.project(ctx, [dev(Q, c) for c in a], [dev(Q, c) for c in b], h, prm, v)
     assert rc == 0
     ost = S.Stats()
     ref = S.project(a, b, h, S.Params(re=1e3, dt=1e-3, chi=chi, dx=dx, max_sweeps=2,
-                                      rhs_mode=1), a, ost)
+                                      rhs_mode=1, fit_sweeps=fit), a, ost)
     for i in range(2):
         assert v[i].bonds == M.bonds(ref[i])
         assert M.rel_l2(v[i].cores(), ref[i]) < TOL
