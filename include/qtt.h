@@ -188,6 +188,22 @@ int qtt_to_dense(qtt_ctx *ctx, const qtt_mps *x, double *grid);
 int qtt_from_dense(qtt_ctx *ctx, const double *grid, int32_t n, int32_t chi, double svd_rtol,
                    qtt_mps *out);
 
+/* Bond dimension needed per bipartition (the paper's MPS compression
+ * efficiency analysis, Eq. epsilon; chi = max_l chi_l): for the dense grid
+ * (device, N x N, x1-major, float64, N = 2^n, 2 <= n <= 13) as the quantics
+ * state of n sites, counts[l-1] (host, n-1 entries) receives chi_l(eps), the
+ * least number of Schmidt values of bipartition l (sites 0..l-1 against
+ * l..n-1) whose discarded tail keeps that bipartition's relative L2 error
+ * within eps: sqrt(sum_{k >= chi} s_k^2) <= eps sqrt(sum_k s_k^2); at least 1,
+ * 0 for a zero field.  The spectra come from the sequential decomposition of
+ * qtt_from_dense (Gram eigenvalues: singular values below 1e-7 sigma_max are
+ * dropped, bonds capped at chi_cap between cuts), so counts are exact while
+ * chi_cap exceeds them and eps is well above 1e-7.  Errors: QTT_E_ARG for
+ * null pointers, chi_cap < 1 or eps < 0; QTT_E_UNSUPPORTED for n outside
+ * 2..13. */
+int qtt_schmidt_counts(qtt_ctx *ctx, const double *grid, int32_t n, double eps, int32_t chi_cap,
+                       int32_t *counts);
+
 /* One Euler minimisation (App. B, Eq. Theta; Eqs. first/second, big_LS):
  *   v = argmin Theta(v; a, b, h)
  * over MPS v_1, v_2 with the bonds of the guess v (in: guess, out: result,

@@ -251,6 +251,17 @@ int qtt_from_dense(qtt_ctx *ctx, const double *grid, int32_t n, int32_t chi, dou
   });
 }
 
+int qtt_schmidt_counts(qtt_ctx *ctx, const double *grid, int32_t n, double eps, int32_t chi_cap,
+                       int32_t *counts) {
+  return guard(ctx, [&] {
+    if (!grid || !counts || chi_cap < 1 || !(eps >= 0.0))
+      qtt::fail(QTT_E_ARG, "schmidt_counts: bad arguments");
+    if (n < 2 || n > 13) qtt::fail(QTT_E_UNSUPPORTED, "schmidt_counts: n must be 2..13");
+    ctx->c.register_user(grid, ((size_t)1 << (2 * n)) * 8);
+    qtt::schmidt_counts(ctx->c, grid, n, eps, chi_cap, counts);
+  });
+}
+
 int qtt_project(qtt_ctx *ctx, const qtt_mps *a, const qtt_mps *b, double h, const qtt_params *p,
                 qtt_mps *v, qtt_stats *stats) {
   return guard(ctx, [&] {

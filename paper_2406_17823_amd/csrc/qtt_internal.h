@@ -345,7 +345,12 @@ void mps_apply_mpo(Ctx &c, const Mpo &W, const Mps &x, Mps &y);
 void mps_hadamard(Ctx &c, const Mps &a, const Mps &b, Mps &y);
 double mps_inner(Ctx &c, const Mps &x, const Mps &y);
 void mps_to_dense(Ctx &c, const Mps &x, double *grid);
-void mps_from_dense(Ctx &c, const double *grid, int n, int chi, double rtol, Mps &out);
+// spectra (optional): the squared singular values of every cut k = 1..n-1
+// as the sequential decomposition meets them (before that cut's truncation)
+void mps_from_dense(Ctx &c, const double *grid, int n, int chi, double rtol, Mps &out,
+                    std::vector<std::vector<double>> *spectra = nullptr);
+// chi_l(eps) of every bipartition l = 1..n-1 of a dense grid (counts, host)
+void schmidt_counts(Ctx &c, const double *grid, int n, double eps, int cap, int32_t *counts);
 void mps_copy(Ctx &c, const Mps &src, Mps &dst);
 void mps_right_canonicalize(Ctx &c, std::vector<Mps *> xs);
 

@@ -3,6 +3,7 @@
 #include "qtt_internal.h"
 
 #include <algorithm>
+#include <functional>
 #include <cmath>
 #include <sstream>
 
@@ -469,7 +470,8 @@ void mps_truncate(Ctx &c, std::vector<Mps *> ys, int chi, double rtol, double *d
 // ---------------------------------------------------------------- input compression
 constexpr double FROM_DENSE_FLOOR = 1e-7;
 
-void mps_from_dense(Ctx &c, const double *grid, int n, int chi, double rtol, Mps &out) {
+void mps_from_dense(Ctx &c, const double *grid, int n, int chi, double rtol, Mps &out,
+                    std::vector<std::vector<double>> *spectra) {
   if (n < 1 || n > 13) fail(QTT_E_ARG, "from_dense: n out of range");
   const int64_t N2 = (int64_t)1 << (2 * n);
   double *M0 = c.buf("fd_M0", N2);
@@ -511,6 +513,11 @@ void mps_from_dense(Ctx &c, const double *grid, int n, int chi, double rtol, Mps
     if (m > (int)Sh.size()) Sh.resize(m);
     HIPC(hipMemcpyAsync(Sh.data(), S, sizeof(double) * m, hipMemcpyDeviceToHost, c.stream));
     c.sync();
+    if (spectra) {
+      std::vector<double> s2(m);
+      for (int j = 0; j < m; ++j) s2[j] = std::max(Sh[j], 0.0);
+      spectra->push_back(std::move(s2));
+    }
     // eigenvalues of G are sigma^2; the Gram route resolves sigma only down
     // to ~1e-8 sigma_max, so the cutoff is at least FROM_DENSE_FLOOR
     int keep = std::min(std::min(chi, struct_bound(n, k + 1)), m);
@@ -552,6 +559,45 @@ void mps_from_dense(Ctx &c, const double *grid, int n, int chi, double rtol, Mps
                       c.stream));
   c.sync();
   out = res;
+}
+
+// Bond dimension chi_l(eps) of every bipartition (the paper's MPS compression
+// efficiency analysis, Eq. epsilon): the least number of Schmidt values of
+// bipartition l whose discarded tail keeps that bipartition's relative L2
+// error within eps, from the squared singular values the sequential
+// decomposition meets at each cut (truncated to cap between cuts, values below
+// 1e-7 sigma_max dropped, as the input compression does)
+void schmidt_counts(Ctx &c, const double *grid, int n, double eps, int cap, int32_t *counts) {
+  if (n < 2 || n > 13) fail(QTT_E_ARG, "schmidt_counts: n must be 2..13");
+  if (cap < 1 || !(eps >= 0.0)) fail(QTT_E_ARG, "schmidt_counts: cap >= 1, eps >= 0");
+  Mps out;
+  out.n = n;
+  out.bond[0] = out.bond[n] = 1;
+  for (int k = 1; k < n; ++k) out.bond[k] = std::min<int64_t>(cap, struct_bound(n, k));
+  out.capacity = out.size();
+  out.data = c.buf("sc_out", out.capacity);
+  std::vector<std::vector<double>> spectra;
+  mps_from_dense(c, grid, n, cap, 0.0, out, &spectra);
+  if ((int)spectra.size() != n - 1) fail(QTT_E_UNSUPPORTED, "schmidt_counts: spectra");
+  for (int k = 0; k < n - 1; ++k) {
+    std::vector<double> s2 = spectra[k];
+    std::sort(s2.begin(), s2.end(), std::greater<double>());
+    double total = 0.0;
+    for (double v : s2) total += v;
+    if (total == 0.0) {
+      counts[k] = 0;
+      continue;
+    }
+    // least c with sum_{j >= c} s2_j <= eps^2 total, at least 1
+    double tail = 0.0;
+    int cnt = (int)s2.size();
+    for (int j = (int)s2.size() - 1; j >= 0; --j) {
+      tail += s2[j];
+      if (tail > eps * eps * total) break;
+      cnt = j;
+    }
+    counts[k] = std::max(1, cnt);
+  }
 }
 
 }  // namespace qtt

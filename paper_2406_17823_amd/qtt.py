@@ -62,7 +62,7 @@ SYMBOLS = ['qtt_kernel_timing', 'qtt_kernel_stats_read', 'qtt_ctx_create', 'qtt_
            'qtt_mpo_derivative', 'qtt_add', 'qtt_truncate', 'qtt_apply_mpo', 'qtt_hadamard',
            'qtt_inner', 'qtt_to_dense', 'qtt_from_dense', 'qtt_project', 'qtt_rk4_step',
            'qtt_precond_config', 'qtt_precond_info', 'qtt_precond_weights', 'qtt_precond_grad',
-           'qtt_rk4_step_batched', 'qtt_rk_step']
+           'qtt_rk4_step_batched', 'qtt_rk_step', 'qtt_schmidt_counts']
 
 _lib = None
 
@@ -95,6 +95,7 @@ def lib():
                               ctypes.POINTER(c_stats)]),
         'qtt_rk4_step': (I32, [P, pm, ctypes.POINTER(c_params), ctypes.POINTER(c_stats)]),
         'qtt_rk_step': (I32, [P, pm, ctypes.POINTER(c_params), I32, ctypes.POINTER(c_stats)]),
+        'qtt_schmidt_counts': (I32, [P, P, I32, ctypes.c_double, I32, ctypes.POINTER(I32)]),
         'qtt_kernel_timing': (I32, [P, I32, I32]),
         'qtt_kernel_stats_read': (I32, [P, I32, ctypes.POINTER(c_kstats)]),
         'qtt_precond_config': (I32, [P, I32, D, ctypes.c_uint64, I32]),
@@ -355,6 +356,20 @@ def rk_step(ctx, u, prm, order):
     u[0].take(U[0])
     u[1].take(U[1])
     return rc, st.as_dict()
+
+
+def schmidt_counts(ctx, grid, eps, chi_cap=256):
+    """chi_l(eps) of every bipartition of a dense N x N float64 device grid
+    (list of n - 1 ints)."""
+    N = grid.shape[0]
+    n = N.bit_length() - 1
+    if tuple(grid.shape) != (N, N) or (1 << n) != N or grid.dtype != torch.float64:
+        raise ValueError('schmidt_counts: N x N float64 grid with N a power of two')
+    g = grid.contiguous()
+    out = (ctypes.c_int32 * (n - 1))()
+    ctx.check(lib().qtt_schmidt_counts(ctx.h, ctypes.c_void_p(g.data_ptr()), n, float(eps),
+                                       int(chi_cap), out), 'schmidt_counts')
+    return list(out)
 
 
 def rk4_step_batched(ctx, flows, prms, workers=0):
