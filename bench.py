@@ -67,6 +67,10 @@ def parse():
                          'chi-bounded MPS in this many sweeps, then the minimisations) for every '
                          'path; reported under "explicit_rhs" with the difference to the '
                          'float64 implicit step')
+    ap.add_argument('--schmidt', type=float, default=0.0,
+                    help='also run the bond-dimension analysis chi_l(eps) at this eps on the '
+                         'jet and spectrum initial fields and the developed state (GPU), with '
+                         'the CPU oracle timed on the jet field; reported under "schmidt"')
     ap.add_argument('--calib-copy-mib', type=int, default=0,
                     help='run one device-to-device copy of this many MiB before the timed '
                          'steps (reference dispatch for hardware byte counters)')
@@ -123,12 +127,17 @@ def cpu_sample(uc, chi, re, dt):
     for net in rhs + list(pen.values()):
         net.init(v, n)
     t = time.perf_counter() - t0
+    return t, threads_used()
+
+
+def threads_used():
+    """Host threads the oracle's BLAS calls can use."""
     try:
         cores = len(os.sched_getaffinity(0))
     except Exception:
         cores = os.cpu_count()
     threads = int(os.environ.get('OMP_NUM_THREADS', cores))
-    return t, min(threads, cores)
+    return min(threads, cores)
 
 
 def main():
@@ -326,6 +335,35 @@ def main():
                     flops_per_launch=flops_per_launch,
                     kernel_share=round(est_time(dom) / (results[main_path]['seconds'] * 1e3), 3))
 
+    schmidt = None
+    if args.schmidt > 0.0:
+        eps = args.schmidt
+        fields = {}
+        dj, dt_ = I.decaying_jet(n), I.spectrum(n, 2, k0=8.0)
+        for c in range(2):
+            fields[f'jet u{c + 1}'] = torch.from_numpy(dj[c]).cuda()
+            fields[f'spectrum u{c + 1}'] = torch.from_numpy(dt_[c]).cuda()
+            fields[f'developed state u{c + 1}'] = Q.to_dense(ctx, state[c])
+        schmidt = {'eps': eps, 'chi_cap': 256}
+        for name, g in fields.items():
+            Q.schmidt_counts(ctx, g, eps, chi_cap=256)  # untimed: workspace growth
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            cnt = Q.schmidt_counts(ctx, g, eps, chi_cap=256)
+            torch.cuda.synchronize()
+            schmidt[name] = dict(counts=cnt, chi=max(cnt),
+                                 gpu_ms=round(1e3 * (time.perf_counter() - t1), 2))
+            log('schmidt', name, schmidt[name])
+        # the oracle's definition (one dense SVD per unfolding) on the jet's u1
+        from oracle import schmidt as Sc
+        t1 = time.perf_counter()
+        ref = Sc.schmidt_counts(dj[0], eps)
+        t_cpu = time.perf_counter() - t1
+        cores = threads_used()
+        schmidt['cpu_oracle'] = dict(field='jet u1', seconds=round(t_cpu, 3), cores=cores,
+                                     counts_agree=(ref == schmidt['jet u1']['counts']))
+        log('schmidt oracle', schmidt['cpu_oracle'])
+
     cpu = None
     if args.cpu_sample:
         # GPU time of the same sample (stage-1 environment build), phase-timed
@@ -370,6 +408,8 @@ def main():
         line['schedules'] = schedules
     if explicit is not None:
         line['explicit_rhs'] = explicit
+    if schmidt is not None:
+        line['schmidt'] = schmidt
     print(json.dumps(line), flush=True)
     ctx.close()
 
