@@ -16,6 +16,8 @@ sweep   environments, local linear systems, CG, the one-site variational sweep
 dense   brute-force full-grid step: circulant finite differences, the penalty
         solve in closed form per Fourier mode, RK4
 mlp     float64 forward/backward of the learned block preconditioner
+schmidt Schmidt spectra per bipartition and the bond dimension chi_l(eps)
+dns     dense DNS reference (App. D), fidelity and TKE spectrum
 
 Parity status of each function is stated in its docstring; a function without
 an independent pin says "parity unpinned".
