@@ -204,6 +204,47 @@ int qtt_from_dense(qtt_ctx *ctx, const double *grid, int32_t n, int32_t chi, dou
 int qtt_schmidt_counts(qtt_ctx *ctx, const double *grid, int32_t n, double eps, int32_t chi_cap,
                        int32_t *counts);
 
+/* Dense direct numerical simulation used to verify the tensor-network solver
+ * (App. D).  Fields u1, u2 are device float64 grids, N x N, x1-major
+ * (u[i1 * N + i2] = u(i1 dx, i2 dx)), N = 2^n, 3 <= n <= 11, dx = 1/N, on
+ * the periodic unit square; the caller owns them.  Derivatives are the
+ * eighth-order central stencils (offsets 1..4); the convection is the
+ * skew-symmetric form -1/2 sum_j (u_j d_j u_i + d_j(u_j u_i)), the diffusion
+ * (1/Re)(d_11 + d_22) u_i.
+ *
+ * qtt_dns_rhs: f = C + D at u (f1, f2: device, N x N, distinct from u).
+ * qtt_dns_project: in place, the divergence-free part by the Fourier
+ *   projection of Eq. projection, u^ - kappa (kappa . u^) / |kappa|^2 for
+ *   kappa != 0 with integer wavenumbers and the Nyquist component of kappa
+ *   taken as 0 (the mean flow is kept).
+ * qtt_dns_step: `steps` steps in place of the explicit Euler scheme
+ *   u <- P(u + dt (C + D)) (order 1) or its RK4 extension with every stage
+ *   velocity and the final combination projected (order 4).
+ * Errors: QTT_E_ARG for null pointers, re <= 0 or NaN, dt not finite,
+ * steps < 0 or order not 1 or 4; QTT_E_UNSUPPORTED for n outside 3..11. */
+int qtt_dns_rhs(qtt_ctx *ctx, const double *u1, const double *u2, double *f1, double *f2,
+                int32_t n, double re);
+int qtt_dns_project(qtt_ctx *ctx, double *u1, double *u2, int32_t n);
+int qtt_dns_step(qtt_ctx *ctx, double *u1, double *u2, int32_t n, double re, double dt,
+                 int32_t order, int32_t steps);
+
+/* Fidelity of Eq. fidelity between two fields of len float64 values (device,
+ * any layout, the same for both): *F (host) = <a|b>^2 / (||a||^2 ||b||^2);
+ * 0 when either norm is 0.  Errors: QTT_E_ARG for null pointers or len < 1. */
+int qtt_fidelity(qtt_ctx *ctx, const double *a, const double *b, int64_t len, double *F);
+
+/* Turbulent kinetic energy spectrum (Eqs. TKE): u' = u - mean (mean1,
+ * mean2: device N x N fields, or both null for u' = u), u'^ = FFT(u') / N^2,
+ * E(k1, k2) = 1/2 (|u1'^|^2 + |u2'^|^2), and E[k] (host, nshell entries)
+ * the sum over the integer wavenumbers with round(|kappa|) = k, k = 0 ..
+ * nshell - 1, nshell = round(sqrt(2) N / 2) + 1 (qtt_tke_shells).  Layout of
+ * u as for the DNS; 3 <= n <= 11.  Errors: QTT_E_ARG for null fields, a single
+ * null mean, a null E or nshell different from qtt_tke_shells(n);
+ * QTT_E_UNSUPPORTED for n outside 3..11. */
+int32_t qtt_tke_shells(int32_t n);
+int qtt_tke_spectrum(qtt_ctx *ctx, const double *u1, const double *u2, const double *mean1,
+                     const double *mean2, int32_t n, double *E, int32_t nshell);
+
 /* One Euler minimisation (App. B, Eq. Theta; Eqs. first/second, big_LS):
  *   v = argmin Theta(v; a, b, h)
  * over MPS v_1, v_2 with the bonds of the guess v (in: guess, out: result,

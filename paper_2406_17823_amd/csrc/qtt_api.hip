@@ -3,6 +3,7 @@
 // qtt::Error to the return code (message kept for qtt_last_error).
 #include "qtt_internal.h"
 
+#include <cmath>
 #include <cstdlib>
 #include <cstring>
 #include <sstream>
@@ -259,6 +260,85 @@ int qtt_schmidt_counts(qtt_ctx *ctx, const double *grid, int32_t n, double eps, 
     if (n < 2 || n > 13) qtt::fail(QTT_E_UNSUPPORTED, "schmidt_counts: n must be 2..13");
     ctx->c.register_user(grid, ((size_t)1 << (2 * n)) * 8);
     qtt::schmidt_counts(ctx->c, grid, n, eps, chi_cap, counts);
+  });
+}
+
+int qtt_dns_rhs(qtt_ctx *ctx, const double *u1, const double *u2, double *f1, double *f2,
+                int32_t n, double re) {
+  return guard(ctx, [&] {
+    if (!u1 || !u2 || !f1 || !f2 || !(re > 0.0)) qtt::fail(QTT_E_ARG, "dns_rhs: bad arguments");
+    if (n < 3 || n > 11) qtt::fail(QTT_E_UNSUPPORTED, "dns_rhs: n must be 3..11");
+    const size_t bytes = ((size_t)1 << (2 * n)) * 8;
+    for (const double *p : {u1, u2, (const double *)f1, (const double *)f2})
+      ctx->c.register_user(p, bytes);
+    qtt::dns_rhs(ctx->c, u1, u2, f1, f2, n, re);
+    ctx->c.sync();
+  });
+}
+
+int qtt_dns_project(qtt_ctx *ctx, double *u1, double *u2, int32_t n) {
+  return guard(ctx, [&] {
+    if (!u1 || !u2) qtt::fail(QTT_E_ARG, "dns_project: bad arguments");
+    if (n < 3 || n > 11) qtt::fail(QTT_E_UNSUPPORTED, "dns_project: n must be 3..11");
+    const size_t bytes = ((size_t)1 << (2 * n)) * 8;
+    ctx->c.register_user(u1, bytes);
+    ctx->c.register_user(u2, bytes);
+    qtt::dns_project(ctx->c, u1, u2, n);
+    ctx->c.sync();
+  });
+}
+
+int qtt_dns_step(qtt_ctx *ctx, double *u1, double *u2, int32_t n, double re, double dt,
+                 int32_t order, int32_t steps) {
+  return guard(ctx, [&] {
+    if (!u1 || !u2 || !(re > 0.0) || !std::isfinite(dt) || steps < 0 ||
+        (order != 1 && order != 4))
+      qtt::fail(QTT_E_ARG, "dns_step: bad arguments");
+    if (n < 3 || n > 11) qtt::fail(QTT_E_UNSUPPORTED, "dns_step: n must be 3..11");
+    const size_t bytes = ((size_t)1 << (2 * n)) * 8;
+    ctx->c.register_user(u1, bytes);
+    ctx->c.register_user(u2, bytes);
+    qtt::dns_step(ctx->c, u1, u2, n, re, dt, order, steps);
+    ctx->c.sync();
+  });
+}
+
+int qtt_fidelity(qtt_ctx *ctx, const double *a, const double *b, int64_t len, double *F) {
+  return guard(ctx, [&] {
+    if (!a || !b || !F || len < 1) qtt::fail(QTT_E_ARG, "fidelity: bad arguments");
+    ctx->c.register_user(a, (size_t)len * 8);
+    ctx->c.register_user(b, (size_t)len * 8);
+    double *d = ctx->c.buf("fidelity_dots", 3);
+    qtt::fidelity(ctx->c, a, b, len, d);
+    double h[3];
+    HIPC(hipMemcpyAsync(h, d, sizeof(h), hipMemcpyDeviceToHost, ctx->c.stream));
+    ctx->c.sync();
+    *F = (h[1] > 0.0 && h[2] > 0.0) ? (h[0] * h[0]) / (h[1] * h[2]) : 0.0;
+  });
+}
+
+int32_t qtt_tke_shells(int32_t n) {
+  if (n < 3 || n > 11) return 0;
+  return qtt::tke_shells(n);
+}
+
+int qtt_tke_spectrum(qtt_ctx *ctx, const double *u1, const double *u2, const double *mean1,
+                     const double *mean2, int32_t n, double *E, int32_t nshell) {
+  return guard(ctx, [&] {
+    if (!u1 || !u2 || !E || (!mean1) != (!mean2)) qtt::fail(QTT_E_ARG, "tke_spectrum: bad arguments");
+    if (n < 3 || n > 11) qtt::fail(QTT_E_UNSUPPORTED, "tke_spectrum: n must be 3..11");
+    if (nshell != qtt::tke_shells(n)) qtt::fail(QTT_E_ARG, "tke_spectrum: nshell must be qtt_tke_shells(n)");
+    const size_t bytes = ((size_t)1 << (2 * n)) * 8;
+    ctx->c.register_user(u1, bytes);
+    ctx->c.register_user(u2, bytes);
+    if (mean1) {
+      ctx->c.register_user(mean1, bytes);
+      ctx->c.register_user(mean2, bytes);
+    }
+    double *d = ctx->c.buf("tke_out", nshell);
+    qtt::dns_tke(ctx->c, u1, u2, mean1, mean2, n, d);
+    HIPC(hipMemcpyAsync(E, d, (size_t)nshell * 8, hipMemcpyDeviceToHost, ctx->c.stream));
+    ctx->c.sync();
   });
 }
 

@@ -351,6 +351,14 @@ void mps_from_dense(Ctx &c, const double *grid, int n, int chi, double rtol, Mps
                     std::vector<std::vector<double>> *spectra = nullptr);
 // chi_l(eps) of every bipartition l = 1..n-1 of a dense grid (counts, host)
 void schmidt_counts(Ctx &c, const double *grid, int n, double eps, int cap, int32_t *counts);
+// dense DNS reference, fidelity and TKE spectrum (k_dns.hip)
+void dns_rhs(Ctx &c, const double *u1, const double *u2, double *f1, double *f2, int n, double re);
+void dns_project(Ctx &c, double *u1, double *u2, int n);
+void dns_step(Ctx &c, double *u1, double *u2, int n, double re, double dt, int order, int steps);
+int tke_shells(int n);
+void dns_tke(Ctx &c, const double *u1, const double *u2, const double *m1, const double *m2, int n,
+             double *E_dev);
+void fidelity(Ctx &c, const double *a, const double *b, int64_t len, double *out_dev3);
 void mps_copy(Ctx &c, const Mps &src, Mps &dst);
 void mps_right_canonicalize(Ctx &c, std::vector<Mps *> xs);
 

@@ -62,7 +62,8 @@ SYMBOLS = ['qtt_kernel_timing', 'qtt_kernel_stats_read', 'qtt_ctx_create', 'qtt_
            'qtt_mpo_derivative', 'qtt_add', 'qtt_truncate', 'qtt_apply_mpo', 'qtt_hadamard',
            'qtt_inner', 'qtt_to_dense', 'qtt_from_dense', 'qtt_project', 'qtt_rk4_step',
            'qtt_precond_config', 'qtt_precond_info', 'qtt_precond_weights', 'qtt_precond_grad',
-           'qtt_rk4_step_batched', 'qtt_rk_step', 'qtt_schmidt_counts']
+           'qtt_rk4_step_batched', 'qtt_rk_step', 'qtt_schmidt_counts', 'qtt_dns_rhs',
+           'qtt_dns_project', 'qtt_dns_step', 'qtt_fidelity', 'qtt_tke_shells', 'qtt_tke_spectrum']
 
 _lib = None
 
@@ -96,6 +97,12 @@ def lib():
         'qtt_rk4_step': (I32, [P, pm, ctypes.POINTER(c_params), ctypes.POINTER(c_stats)]),
         'qtt_rk_step': (I32, [P, pm, ctypes.POINTER(c_params), I32, ctypes.POINTER(c_stats)]),
         'qtt_schmidt_counts': (I32, [P, P, I32, ctypes.c_double, I32, ctypes.POINTER(I32)]),
+        'qtt_dns_rhs': (I32, [P, P, P, P, P, I32, ctypes.c_double]),
+        'qtt_dns_project': (I32, [P, P, P, I32]),
+        'qtt_dns_step': (I32, [P, P, P, I32, ctypes.c_double, ctypes.c_double, I32, I32]),
+        'qtt_fidelity': (I32, [P, P, P, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)]),
+        'qtt_tke_shells': (I32, [I32]),
+        'qtt_tke_spectrum': (I32, [P, P, P, P, P, I32, ctypes.POINTER(ctypes.c_double), I32]),
         'qtt_kernel_timing': (I32, [P, I32, I32]),
         'qtt_kernel_stats_read': (I32, [P, I32, ctypes.POINTER(c_kstats)]),
         'qtt_precond_config': (I32, [P, I32, D, ctypes.c_uint64, I32]),
@@ -370,6 +377,67 @@ def schmidt_counts(ctx, grid, eps, chi_cap=256):
     ctx.check(lib().qtt_schmidt_counts(ctx.h, ctypes.c_void_p(g.data_ptr()), n, float(eps),
                                        int(chi_cap), out), 'schmidt_counts')
     return list(out)
+
+
+def _grid_n(what, *gs):
+    N = gs[0].shape[0]
+    n = N.bit_length() - 1
+    for g in gs:
+        if (tuple(g.shape) != (N, N) or (1 << n) != N or g.dtype != torch.float64
+                or not g.is_cuda or not g.is_contiguous()):
+            raise ValueError(f'{what}: contiguous N x N float64 device grids, N a power of two')
+    return n
+
+
+def _vp(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def dns_rhs(ctx, u1, u2, re):
+    """C + D of the DNS at (u1, u2): returns two new grids."""
+    n = _grid_n('dns_rhs', u1, u2)
+    f1, f2 = torch.empty_like(u1), torch.empty_like(u2)
+    ctx.check(lib().qtt_dns_rhs(ctx.h, _vp(u1), _vp(u2), _vp(f1), _vp(f2), n, float(re)),
+              'dns_rhs')
+    return f1, f2
+
+
+def dns_project(ctx, u1, u2):
+    """Divergence-free projection of (u1, u2), in place."""
+    n = _grid_n('dns_project', u1, u2)
+    ctx.check(lib().qtt_dns_project(ctx.h, _vp(u1), _vp(u2), n), 'dns_project')
+
+
+def dns_step(ctx, u1, u2, re, dt, order=4, steps=1):
+    """`steps` DNS steps (order 1: Euler, 4: RK4) of (u1, u2), in place."""
+    n = _grid_n('dns_step', u1, u2)
+    ctx.check(lib().qtt_dns_step(ctx.h, _vp(u1), _vp(u2), n, float(re), float(dt), int(order),
+                                 int(steps)), 'dns_step')
+
+
+def fidelity(ctx, a, b):
+    """<a|b>^2 / (||a||^2 ||b||^2) of two float64 device tensors of one size."""
+    if a.numel() != b.numel() or a.dtype != torch.float64 or b.dtype != torch.float64:
+        raise ValueError('fidelity: two float64 device tensors of one size')
+    a, b = a.contiguous(), b.contiguous()
+    F = ctypes.c_double()
+    ctx.check(lib().qtt_fidelity(ctx.h, _vp(a), _vp(b), a.numel(), ctypes.byref(F)), 'fidelity')
+    return F.value
+
+
+def tke_shells(n):
+    return int(lib().qtt_tke_shells(int(n)))
+
+
+def tke_spectrum(ctx, u1, u2, mean1=None, mean2=None):
+    """E(k), k = 0 .. tke_shells(n) - 1, of u - mean (list of floats)."""
+    gs = [u1, u2] + ([mean1, mean2] if mean1 is not None else [])
+    n = _grid_n('tke_spectrum', *gs)
+    S = tke_shells(n)
+    E = (ctypes.c_double * max(S, 1))()
+    ctx.check(lib().qtt_tke_spectrum(ctx.h, _vp(u1), _vp(u2), _vp(mean1), _vp(mean2), n, E, S),
+              'tke_spectrum')
+    return list(E)[:S]
 
 
 def rk4_step_batched(ctx, flows, prms, workers=0):
