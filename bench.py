@@ -71,6 +71,11 @@ def parse():
                     help='also run the bond-dimension analysis chi_l(eps) at this eps on the '
                          'jet and spectrum initial fields and the developed state (GPU), with '
                          'the CPU oracle timed on the jet field; reported under "schmidt"')
+    ap.add_argument('--dns', type=int, default=0,
+                    help='also time this many RK4 steps of the dense DNS reference on the '
+                         'decaying jet at the same size, Re and dt (GPU), compare it with the '
+                         'tensor-network state at the same time by fidelity and TKE spectrum, '
+                         'and time one step of the CPU oracle; reported under "dns"')
     ap.add_argument('--calib-copy-mib', type=int, default=0,
                     help='run one device-to-device copy of this many MiB before the timed '
                          'steps (reference dispatch for hardware byte counters)')
@@ -335,6 +340,56 @@ def main():
                     flops_per_launch=flops_per_launch,
                     kernel_share=round(est_time(dom) / (results[main_path]['seconds'] * 1e3), 3))
 
+    dns = None
+    if args.dns > 0:
+        import numpy as np
+        from oracle import dns as Dn
+        N = 1 << n
+        dj = I.decaying_jet(n)
+
+        def jet():
+            return [torch.from_numpy(np.ascontiguousarray(dj[c], dtype=np.float64)).cuda()
+                    for c in range(2)]
+        g = jet()
+        Q.dns_step(ctx, g[0], g[1], args.re, args.dt, order=4, steps=1)  # untimed: workspace
+        g = jet()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        Q.dns_step(ctx, g[0], g[1], args.re, args.dt, order=4, steps=args.dns)
+        torch.cuda.synchronize()
+        t_dns = time.perf_counter() - t1
+        # HBM bytes per grid point of one RK4 step as the kernels move them:
+        # stage kernels 64 + 3 x 80, four projections of 240 (seven passes)
+        bpp = 64 + 3 * 80 + 4 * 240
+        dns = dict(workload=f'decaying jet {N} x {N}, RK4, Re {args.re:g}, dt {args.dt:g}',
+                   steps=args.dns, ms_per_step=round(1e3 * t_dns / args.dns, 3),
+                   steps_per_s=round(args.dns / t_dns, 2), bytes_per_step=bpp * N * N,
+                   achieved_GBps=round(bpp * N * N * args.dns / t_dns / 1e9, 1))
+        log('dns', dns)
+        if not args.load_state:
+            # the tensor-network state is spin + warm-up steps after the jet
+            k = spin + args.warmup
+            g = jet()
+            Q.dns_step(ctx, g[0], g[1], args.re, args.dt, order=4, steps=k)
+            cmp = dict(steps=k, time=k * args.dt)
+            for c in range(2):
+                qd = Q.to_dense(ctx, state[c])
+                cmp[f'fidelity_u{c + 1}'] = Q.fidelity(ctx, g[c], qd)
+            Ed = np.array(Q.tke_spectrum(ctx, g[0], g[1]))
+            Eq = np.array(Q.tke_spectrum(ctx, Q.to_dense(ctx, state[0]), Q.to_dense(ctx, state[1])))
+            shells = [1, 4, 16, 64, 256, 1024]
+            cmp['tke_shells'] = [s_ for s_ in shells if s_ < len(Ed)]
+            cmp['tke_dns'] = [float(Ed[s_]) for s_ in cmp['tke_shells']]
+            cmp['tke_qis'] = [float(Eq[s_]) for s_ in cmp['tke_shells']]
+            dns['vs_tensor_network'] = cmp
+            log('dns vs tensor network', cmp)
+        # the oracle's RK4 step on the host, one step from the jet
+        t1 = time.perf_counter()
+        Dn.rk4_step([np.asarray(dj[0]), np.asarray(dj[1])], args.dt, args.re, 1.0 / N)
+        dns['cpu_oracle'] = dict(seconds_per_step=round(time.perf_counter() - t1, 2),
+                                 cores=threads_used())
+        log('dns oracle', dns['cpu_oracle'])
+
     schmidt = None
     if args.schmidt > 0.0:
         eps = args.schmidt
@@ -410,6 +465,8 @@ def main():
         line['explicit_rhs'] = explicit
     if schmidt is not None:
         line['schmidt'] = schmidt
+    if dns is not None:
+        line['dns'] = dns
     print(json.dumps(line), flush=True)
     ctx.close()
 
