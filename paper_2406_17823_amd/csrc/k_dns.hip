@@ -110,8 +110,24 @@ __global__ __launch_bounds__(256) void k_dns_stage(StageArgs A) {
   }
 }
 
+__device__ inline double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ inline double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ inline double2 cmul(double2 a, double2 w) {
+  return make_double2(a.x * w.x - a.y * w.y, a.x * w.y + a.y * w.x);
+}
+
+// twiddle table of one transform length: tw[k] = exp(-2 pi i k / N), k < N/2
+__global__ void k_twiddles(double2 *tw, int n) {
+  const int N = 1 << n;
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < N / 2; k += gridDim.x * blockDim.x) {
+    double sn, cs;
+    sincospi(2.0 * k / N, &sn, &cs);
+    tw[k] = make_double2(cs, -sn);
+  }
+}
+
 // One radix-2 transform per row, in LDS: bit-reversed load, log2 N
-// butterfly stages, natural-order result.  IN: 0 packed complex, 1 two real
+// butterfly stages (fused in pairs), natural-order result.  IN: 0 packed complex, 1 two real
 // fields (minus optional means) packed as re + i im.  OUT: 0 packed complex,
 // 1 two real fields (re, im) times scale, 2 the row's TKE shell partials.
 template <int IN, int OUT>
@@ -119,16 +135,16 @@ __global__ __launch_bounds__(256) void k_fft_rows(const double2 *zin, const doub
                                                   const double *rb, const double *ma,
                                                   const double *mb, double2 *zout, double *oa,
                                                   double *ob, double scale, double *part,
-                                                  int nshell, int n, int inverse) {
+                                                  int nshell, int n, int inverse,
+                                                  const double2 *twg) {
   extern __shared__ double2 sm[];
   const int N = 1 << n, H = N >> 1;
   double2 *s = sm, *tw = sm + N;
   const int64_t base = (int64_t)blockIdx.x * N;
-  const double sg = inverse ? 1.0 : -1.0;
+  // twg[k] = exp(-2 pi i k / N); the inverse takes the conjugate
   for (int k = threadIdx.x; k < H; k += blockDim.x) {
-    double sn, cs;
-    sincospi(2.0 * k / N, &sn, &cs);
-    tw[k] = make_double2(cs, sg * sn);
+    const double2 w = twg[k];
+    tw[k] = make_double2(w.x, inverse ? -w.y : w.y);
   }
   for (int j = threadIdx.x; j < N; j += blockDim.x) {
     double2 v;
@@ -141,14 +157,38 @@ __global__ __launch_bounds__(256) void k_fft_rows(const double2 *zin, const doub
     s[__brev((unsigned)j) >> (32 - n)] = v;
   }
   __syncthreads();
-  for (int half = 1, ts = H; half < N; half <<= 1, ts >>= 1) {
+  int half = 1;
+  if (n & 1) {  // odd n: one radix-2 stage first
     for (int t = threadIdx.x; t < H; t += blockDim.x) {
+      const double2 x = s[2 * t], y = s[2 * t + 1];
+      s[2 * t] = cadd(x, y);
+      s[2 * t + 1] = csub(x, y);
+    }
+    __syncthreads();
+    half = 2;
+  }
+  // pairs of radix-2 stages (spans half and 2 half) fused in registers on
+  // the four elements i, i + half, i + 2 half, i + 3 half: the same
+  // operations as two separate stages, one LDS round trip and one barrier
+  for (; half < N; half <<= 2) {
+    const int sa = N / (2 * half), sb = N / (4 * half);
+    for (int t = threadIdx.x; t < (N >> 2); t += blockDim.x) {
       const int pos = t & (half - 1);
-      const int i = ((t - pos) << 1) + pos, j = i + half;
-      const double2 w = tw[pos * ts], x = s[i], y = s[j];
-      const double2 yw = make_double2(y.x * w.x - y.y * w.y, y.x * w.y + y.y * w.x);
-      s[i] = make_double2(x.x + yw.x, x.y + yw.y);
-      s[j] = make_double2(x.x - yw.x, x.y - yw.y);
+      const int i = ((t - pos) << 2) + pos;
+      double2 a0 = s[i], a1 = s[i + half], a2 = s[i + 2 * half], a3 = s[i + 3 * half];
+      const double2 wa = tw[pos * sa];
+      double2 b = cmul(a1, wa);
+      a1 = csub(a0, b);
+      a0 = cadd(a0, b);
+      b = cmul(a3, wa);
+      a3 = csub(a2, b);
+      a2 = cadd(a2, b);
+      b = cmul(a2, tw[pos * sb]);
+      const double2 c = cmul(a3, tw[(pos + half) * sb]);
+      s[i] = cadd(a0, b);
+      s[i + 2 * half] = csub(a0, b);
+      s[i + half] = cadd(a1, c);
+      s[i + 3 * half] = csub(a1, c);
     }
     __syncthreads();
   }
@@ -262,6 +302,7 @@ void check_n(int n, const char *what) {
 struct DnsBufs {
   double *w1, *w2, *acc1, *acc2;
   double2 *Z, *T;
+  double2 *tw;  // twiddles of length N, written at every call
 };
 
 DnsBufs dns_bufs(Ctx &c, int n) {
@@ -273,14 +314,19 @@ DnsBufs dns_bufs(Ctx &c, int n) {
   b.acc2 = c.buf("dns_acc2", NN);
   b.Z = (double2 *)c.buf("dns_z", 2 * NN);
   b.T = (double2 *)c.buf("dns_t", 2 * NN);
+  b.tw = (double2 *)c.buf("dns_tw", (int64_t)1 << n);
+  c.check_range(b.tw, 0, ((int64_t)1 << (n - 1)) - 1, 16, "twiddles");
+  hipLaunchKernelGGL(k_twiddles, dim3(((1 << (n - 1)) + 255) / 256), dim3(256), 0, c.stream, b.tw, n);
+  HIPC(hipGetLastError());
   return b;
 }
 
 template <int IN, int OUT>
 void fft_rows(Ctx &c, int n, const double2 *zin, const double *ra, const double *rb,
               const double *ma, const double *mb, double2 *zout, double *oa, double *ob,
-              double scale, double *part, int nshell, int inverse) {
+              double scale, double *part, int nshell, int inverse, const double2 *tw) {
   const int N = 1 << n;
+  c.check_range(tw, 0, N / 2 - 1, 16, "fft twiddles");
   const int64_t NN = (int64_t)N * N;
   if (IN == 0) c.check_range(zin, 0, NN - 1, 16, "fft in");
   if (IN == 1) {
@@ -298,7 +344,7 @@ void fft_rows(Ctx &c, int n, const double2 *zin, const double *ra, const double 
   const size_t lds = (size_t)(N + N / 2) * sizeof(double2);
   const int threads = std::min(256, std::max(64, N / 2));
   hipLaunchKernelGGL((k_fft_rows<IN, OUT>), dim3(N), dim3(threads), lds, c.stream, zin, ra, rb, ma,
-                     mb, zout, oa, ob, scale, part, nshell, n, inverse);
+                     mb, zout, oa, ob, scale, part, nshell, n, inverse, tw);
   HIPC(hipGetLastError());
 }
 
@@ -316,19 +362,19 @@ void project_packed(Ctx &c, int n, DnsBufs &b, double *o1, double *o2) {
   const int N = 1 << n;
   const int64_t NN = (int64_t)N * N;
   fft_rows<0, 0>(c, n, b.Z, nullptr, nullptr, nullptr, nullptr, b.Z, nullptr, nullptr, 1.0,
-                 nullptr, 0, 0);
+                 nullptr, 0, 0, b.tw);
   transpose(c, n, b.Z, b.T);
   fft_rows<0, 0>(c, n, b.T, nullptr, nullptr, nullptr, nullptr, b.T, nullptr, nullptr, 1.0,
-                 nullptr, 0, 0);
+                 nullptr, 0, 0, b.tw);
   c.check_range(b.T, 0, NN - 1, 16, "project in");
   c.check_range(b.Z, 0, NN - 1, 16, "project out");
   hipLaunchKernelGGL(k_dns_project, dim3(blocks_for(NN)), dim3(256), 0, c.stream, b.T, b.Z, n);
   HIPC(hipGetLastError());
   fft_rows<0, 0>(c, n, b.Z, nullptr, nullptr, nullptr, nullptr, b.Z, nullptr, nullptr, 1.0,
-                 nullptr, 0, 1);
+                 nullptr, 0, 1, b.tw);
   transpose(c, n, b.Z, b.T);
   fft_rows<0, 1>(c, n, b.T, nullptr, nullptr, nullptr, nullptr, nullptr, o1, o2,
-                 1.0 / (double)NN, nullptr, 0, 1);
+                 1.0 / (double)NN, nullptr, 0, 1, b.tw);
 }
 
 void stage(Ctx &c, int n, StageArgs A) {
@@ -389,22 +435,22 @@ void dns_project(Ctx &c, double *u1, double *u2, int n) {
   check_n(n, "dns_project");
   DnsBufs b = dns_bufs(c, n);
   fft_rows<1, 0>(c, n, nullptr, u1, u2, nullptr, nullptr, b.Z, nullptr, nullptr, 1.0, nullptr, 0,
-                 0);
+                 0, b.tw);
   // continue from the row-transformed pack: transpose, rows, project, back
   const int N = 1 << n;
   const int64_t NN = (int64_t)N * N;
   transpose(c, n, b.Z, b.T);
   fft_rows<0, 0>(c, n, b.T, nullptr, nullptr, nullptr, nullptr, b.T, nullptr, nullptr, 1.0,
-                 nullptr, 0, 0);
+                 nullptr, 0, 0, b.tw);
   c.check_range(b.T, 0, NN - 1, 16, "project in");
   c.check_range(b.Z, 0, NN - 1, 16, "project out");
   hipLaunchKernelGGL(k_dns_project, dim3(blocks_for(NN)), dim3(256), 0, c.stream, b.T, b.Z, n);
   HIPC(hipGetLastError());
   fft_rows<0, 0>(c, n, b.Z, nullptr, nullptr, nullptr, nullptr, b.Z, nullptr, nullptr, 1.0,
-                 nullptr, 0, 1);
+                 nullptr, 0, 1, b.tw);
   transpose(c, n, b.Z, b.T);
   fft_rows<0, 1>(c, n, b.T, nullptr, nullptr, nullptr, nullptr, nullptr, u1, u2,
-                 1.0 / (double)NN, nullptr, 0, 1);
+                 1.0 / (double)NN, nullptr, 0, 1, b.tw);
 }
 
 void dns_step(Ctx &c, double *u1, double *u2, int n, double re, double dt, int order,
@@ -455,10 +501,10 @@ void dns_tke(Ctx &c, const double *u1, const double *u2, const double *m1, const
   const int N = 1 << n, S = tke_shells(n);
   DnsBufs b = dns_bufs(c, n);
   double *part = c.buf("dns_shell_part", (int64_t)N * S);
-  fft_rows<1, 0>(c, n, nullptr, u1, u2, m1, m2, b.Z, nullptr, nullptr, 1.0, nullptr, 0, 0);
+  fft_rows<1, 0>(c, n, nullptr, u1, u2, m1, m2, b.Z, nullptr, nullptr, 1.0, nullptr, 0, 0, b.tw);
   transpose(c, n, b.Z, b.T);
   fft_rows<0, 2>(c, n, b.T, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 1.0,
-                 part, S, 0);
+                 part, S, 0, b.tw);
   c.check_range(E_dev, 0, S - 1, 8, "tke out");
   const double NN = (double)N * (double)N;
   hipLaunchKernelGGL(k_shell_reduce, dim3((S + 63) / 64), dim3(256), 0, c.stream, part, N, S,
