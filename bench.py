@@ -76,6 +76,11 @@ def parse():
                          'decaying jet at the same size, Re and dt (GPU), compare it with the '
                          'tensor-network state at the same time by fidelity and TKE spectrum, '
                          'and time one step of the CPU oracle; reported under "dns"')
+    ap.add_argument('--crossover', type=int, default=0,
+                    help='also time one RK4 step of the tensor-network path (mixed and float64, '
+                         'chi = 64) and of the dense DNS on the random-phase spectrum field for '
+                         'n = 6 .. this value (at most 11), the runtime comparison over grid '
+                         'sizes; reported under "crossover"')
     ap.add_argument('--calib-copy-mib', type=int, default=0,
                     help='run one device-to-device copy of this many MiB before the timed '
                          'steps (reference dispatch for hardware byte counters)')
@@ -390,6 +395,43 @@ def main():
                                  cores=threads_used())
         log('dns oracle', dns['cpu_oracle'])
 
+    cross = None
+    if args.crossover > 0:
+        import numpy as np
+        chi_x = 64
+        cross = dict(chi=chi_x, field='random-phase spectrum (k0 = 8), compressed to chi',
+                     rows=[])
+        for nn in range(6, min(11, args.crossover) + 1):
+            Nn = 1 << nn
+            f = I.spectrum(nn, 2, k0=8.0)
+            capn = Q.mps_size(Q.canonical_bonds(nn, chi_x))
+            row = dict(n=nn)
+            for path in ('mixed', 'f64'):
+                pr = Q.params(re=args.re, dt=args.dt, chi=chi_x, dx=1.0 / Nn,
+                              cg_rtol=args.cg_rtol if path == 'f64' else args.mixed_cg_rtol,
+                              cg_maxit=args.cg_maxit, max_sweeps=args.sweeps, svd_rtol=1e-12,
+                              prec=Q.PREC_F32 if path == 'mixed' else Q.PREC_F64)
+                st_ = [Q.from_dense(ctx, torch.from_numpy(np.ascontiguousarray(f[c])).cuda(), chi_x,
+                                    1e-12, capacity=capn) for c in range(2)]
+                Q.rk4_step(ctx, st_, pr)  # untimed
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                for _ in range(2):
+                    Q.rk4_step(ctx, st_, pr)
+                torch.cuda.synchronize()
+                row[f'qis_{path}_ms'] = round(1e3 * (time.perf_counter() - t1) / 2, 2)
+                row['bonds_max'] = max(max(st_[0].bonds), max(st_[1].bonds))
+            g = [torch.from_numpy(np.ascontiguousarray(f[c])).cuda() for c in range(2)]
+            Q.dns_step(ctx, g[0], g[1], args.re, args.dt, order=4, steps=1)
+            torch.cuda.synchronize()
+            reps = 50
+            t1 = time.perf_counter()
+            Q.dns_step(ctx, g[0], g[1], args.re, args.dt, order=4, steps=reps)
+            torch.cuda.synchronize()
+            row['dns_ms'] = round(1e3 * (time.perf_counter() - t1) / reps, 4)
+            cross['rows'].append(row)
+            log('crossover', row)
+
     schmidt = None
     if args.schmidt > 0.0:
         eps = args.schmidt
@@ -467,6 +509,8 @@ def main():
         line['schmidt'] = schmidt
     if dns is not None:
         line['dns'] = dns
+    if cross is not None:
+        line['crossover'] = cross
     print(json.dumps(line), flush=True)
     ctx.close()
 
