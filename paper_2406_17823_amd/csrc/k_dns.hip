@@ -139,13 +139,15 @@ __global__ __launch_bounds__(256) void k_fft_rows(const double2 *zin, const doub
                                                   const double2 *twg) {
   extern __shared__ double2 sm[];
   const int N = 1 << n, H = N >> 1;
-  double2 *s = sm, *tw = sm + N;
+  double2 *s = sm;
   const int64_t base = (int64_t)blockIdx.x * N;
-  // twg[k] = exp(-2 pi i k / N); the inverse takes the conjugate
-  for (int k = threadIdx.x; k < H; k += blockDim.x) {
+  // twg[k] = exp(-2 pi i k / N), read through the caches (every block reads
+  // the same table); the inverse takes the conjugate
+  const double tsg = inverse ? -1.0 : 1.0;
+  auto tw = [&](int k) {
     const double2 w = twg[k];
-    tw[k] = make_double2(w.x, inverse ? -w.y : w.y);
-  }
+    return make_double2(w.x, tsg * w.y);
+  };
   for (int j = threadIdx.x; j < N; j += blockDim.x) {
     double2 v;
     if (IN == 0) {
@@ -176,15 +178,15 @@ __global__ __launch_bounds__(256) void k_fft_rows(const double2 *zin, const doub
       const int pos = t & (half - 1);
       const int i = ((t - pos) << 2) + pos;
       double2 a0 = s[i], a1 = s[i + half], a2 = s[i + 2 * half], a3 = s[i + 3 * half];
-      const double2 wa = tw[pos * sa];
+      const double2 wa = tw(pos * sa);
       double2 b = cmul(a1, wa);
       a1 = csub(a0, b);
       a0 = cadd(a0, b);
       b = cmul(a3, wa);
       a3 = csub(a2, b);
       a2 = cadd(a2, b);
-      b = cmul(a2, tw[pos * sb]);
-      const double2 c = cmul(a3, tw[(pos + half) * sb]);
+      b = cmul(a2, tw(pos * sb));
+      const double2 c = cmul(a3, tw((pos + half) * sb));
       s[i] = cadd(a0, b);
       s[i + 2 * half] = csub(a0, b);
       s[i + half] = cadd(a1, c);
@@ -341,7 +343,7 @@ void fft_rows(Ctx &c, int n, const double2 *zin, const double *ra, const double 
     c.check_range(ob, 0, NN - 1, 8, "fft out im");
   }
   if (OUT == 2) c.check_range(part, 0, (int64_t)N * nshell - 1, 8, "fft shell partials");
-  const size_t lds = (size_t)(N + N / 2) * sizeof(double2);
+  const size_t lds = (size_t)N * sizeof(double2);
   const int threads = std::min(256, std::max(64, N / 2));
   hipLaunchKernelGGL((k_fft_rows<IN, OUT>), dim3(N), dim3(threads), lds, c.stream, zin, ra, rb, ma,
                      mb, zout, oa, ob, scale, part, nshell, n, inverse, tw);
