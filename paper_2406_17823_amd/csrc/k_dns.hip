@@ -126,6 +126,36 @@ __global__ void k_twiddles(double2 *tw, int n) {
   }
 }
 
+// R consecutive radix-2 decimation-in-time stages starting at span `half`,
+// in registers: thread t takes the 2^R elements i + m half of one group;
+// stage r pairs m and m + 2^r (bit r of m clear) with the twiddle of the
+// element's position q in its group of 2^(r+1) half, exp(-+2 pi i q / (2^(r+1) half)).
+template <int R>
+__device__ inline void fused_stages(double2 *s, const double2 *twg, double tsg, int N, int half) {
+  constexpr int E = 1 << R;
+  for (int t = threadIdx.x; t < (N >> R); t += blockDim.x) {
+    const int pos = t & (half - 1);
+    const int i = ((t - pos) << R) + pos;
+    double2 a[E];
+#pragma unroll
+    for (int m = 0; m < E; ++m) a[m] = s[i + m * half];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int span = 1 << r, stride = N / ((2 << r) * half);
+#pragma unroll
+      for (int m = 0; m < E; ++m) {
+        if (m & span) continue;
+        const double2 w0 = twg[(pos + (m & (span - 1)) * half) * stride];
+        const double2 b = cmul(a[m + span], make_double2(w0.x, tsg * w0.y));
+        a[m + span] = csub(a[m], b);
+        a[m] = cadd(a[m], b);
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < E; ++m) s[i + m * half] = a[m];
+  }
+}
+
 // One radix-2 transform per row, in LDS: bit-reversed load, log2 N
 // butterfly stages (fused in pairs), natural-order result.  IN: 0 packed complex, 1 two real
 // fields (minus optional means) packed as re + i im.  OUT: 0 packed complex,
@@ -144,10 +174,6 @@ __global__ __launch_bounds__(256) void k_fft_rows(const double2 *zin, const doub
   // twg[k] = exp(-2 pi i k / N), read through the caches (every block reads
   // the same table); the inverse takes the conjugate
   const double tsg = inverse ? -1.0 : 1.0;
-  auto tw = [&](int k) {
-    const double2 w = twg[k];
-    return make_double2(w.x, tsg * w.y);
-  };
   for (int j = threadIdx.x; j < N; j += blockDim.x) {
     double2 v;
     if (IN == 0) {
@@ -159,40 +185,17 @@ __global__ __launch_bounds__(256) void k_fft_rows(const double2 *zin, const doub
     s[__brev((unsigned)j) >> (32 - n)] = v;
   }
   __syncthreads();
-  int half = 1;
-  if (n & 1) {  // odd n: one radix-2 stage first
-    for (int t = threadIdx.x; t < H; t += blockDim.x) {
-      const double2 x = s[2 * t], y = s[2 * t + 1];
-      s[2 * t] = cadd(x, y);
-      s[2 * t + 1] = csub(x, y);
-    }
+  // groups of R radix-2 stages (spans half .. 2^(R-1) half) in registers on
+  // the 2^R elements i + m half: the operations of R separate stages, one
+  // LDS round trip and one barrier per group (R = 3, 3, 3, 2 for n = 11)
+  for (int half = 1, rem = n; rem > 0;) {
+    const int R = (rem == 4 || rem == 2) ? 2 : (rem >= 3 ? 3 : 1);
+    if (R == 3) fused_stages<3>(s, twg, tsg, N, half);
+    else if (R == 2) fused_stages<2>(s, twg, tsg, N, half);
+    else fused_stages<1>(s, twg, tsg, N, half);
     __syncthreads();
-    half = 2;
-  }
-  // pairs of radix-2 stages (spans half and 2 half) fused in registers on
-  // the four elements i, i + half, i + 2 half, i + 3 half: the same
-  // operations as two separate stages, one LDS round trip and one barrier
-  for (; half < N; half <<= 2) {
-    const int sa = N / (2 * half), sb = N / (4 * half);
-    for (int t = threadIdx.x; t < (N >> 2); t += blockDim.x) {
-      const int pos = t & (half - 1);
-      const int i = ((t - pos) << 2) + pos;
-      double2 a0 = s[i], a1 = s[i + half], a2 = s[i + 2 * half], a3 = s[i + 3 * half];
-      const double2 wa = tw(pos * sa);
-      double2 b = cmul(a1, wa);
-      a1 = csub(a0, b);
-      a0 = cadd(a0, b);
-      b = cmul(a3, wa);
-      a3 = csub(a2, b);
-      a2 = cadd(a2, b);
-      b = cmul(a2, tw(pos * sb));
-      const double2 c = cmul(a3, tw((pos + half) * sb));
-      s[i] = cadd(a0, b);
-      s[i + 2 * half] = csub(a0, b);
-      s[i + half] = cadd(a1, c);
-      s[i + 3 * half] = csub(a1, c);
-    }
-    __syncthreads();
+    half <<= R;
+    rem -= R;
   }
   if (OUT == 0) {
     for (int j = threadIdx.x; j < N; j += blockDim.x) zout[base + j] = s[j];
