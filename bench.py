@@ -154,7 +154,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f'bench.py runs on one GPU only; --gpus {args.gpus} is not supported '
-              '(the QTT step is not sharded across GPUs in this build)', flush=True)
+              '(the QTT step is not sharded across GPUs)', flush=True)
         sys.exit(2)
     import torch
     from paper_2406_17823_amd import inputs as I

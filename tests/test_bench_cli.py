@@ -1,0 +1,22 @@
+"""Command-line contract of bench.py that needs no GPU."""
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused_with_a_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, 'bench.py'), '--gpus', '2'],
+                       capture_output=True, text=True, timeout=120, cwd=ROOT)
+    assert r.returncode == 2
+    assert 'one GPU' in (r.stdout + r.stderr)
+
+
+def test_help_lists_the_optional_legs():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, 'bench.py'), '--help'],
+                       capture_output=True, text=True, timeout=120, cwd=ROOT)
+    assert r.returncode == 0
+    for opt in ('--steps', '--warmup', '--schedules', '--explicit-rhs', '--schmidt', '--dns',
+                '--crossover'):
+        assert opt in r.stdout
