@@ -816,7 +816,7 @@ struct Sweep {
     int iters = st_host->iters;
     bool converged = st_host->converged;
     if (pre) {
-      // float64 judge: the true residual of the PCG result decides; plain CG
+      // float64 check: the true residual of the PCG result decides; plain CG
       // continues from it (from the guess after a non-finite result) when it
       // misses the tolerance
       if (!(st_host->rr_new == st_host->rr_new)) load_guess();

@@ -87,7 +87,7 @@ def test_pcg_reaches_the_cg_solution(Q):
         prm = Q.params(re=1e3, dt=2e-3, chi=chi, dx=dx, max_sweeps=2, cg_rtol=1e-12,
                        precond=pc)
         rc, st, v = _project(Q, ctx, a, b, h, prm)
-        assert rc in (0, 3), rc  # 3: the float64 judge ran plain CG after PCG
+        assert rc in (0, 3), rc  # 3: the float64 check ran plain CG after PCG
         assert st['cg_maxit_hits'] == 0
         out[pc] = v
     ref = S.project(a, b, h, S.Params(re=1e3, dt=2e-3, chi=chi, dx=dx, max_sweeps=2), a,
