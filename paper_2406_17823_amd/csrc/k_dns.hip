@@ -14,7 +14,10 @@
 //   tiled transpose, rows again; the projector u^ - kappa (kappa . u^) /
 //   |kappa|^2 separates the two real fields from Z(k) and conj Z(-k); the
 //   Nyquist component of kappa is 0, so the projected pair is again the
-//   transform of two real fields and the inverse unpacks it exactly.
+//   transform of two real fields and the inverse unpacks it exactly.  The
+//   second forward row transform, the projector and the first inverse row
+//   transform run in one kernel on the rows k2 and -k2 (five passes over
+//   the spectrum per projection).
 // * TKE shells: |u1^|^2 + |u2^|^2 summed over k and -k equals |Z(k)|^2 +
 //   |Z(-k)|^2, so the shell sum of E is sum |Z(k)|^2 / (2 N^4); partial
 //   sums per row and shell, reduced per shell in a fixed order.
@@ -255,28 +258,102 @@ __global__ __launch_bounds__(256) void k_transpose_c(const double2 *in, double2 
 
 // Projector on the transposed spectrum T[k2][k1] of the packed pair,
 // written to out (out of place: each output reads the mirror mode -k).
-__global__ void k_dns_project(const double2 *T, double2 *out, int n) {
+// Projected Z(k) from A = Z(k) and M = Z(-k) of the packed pair, kappa = (k1, k2)
+__device__ inline double2 proj_mode(double2 A, double2 M, double k1, double k2) {
+  const double kk = k1 * k1 + k2 * k2;
+  if (kk == 0.0) return A;
+  const double2 B = make_double2(M.x, -M.y);  // conj Z(-k)
+  const double2 a1 = make_double2(0.5 * (A.x + B.x), 0.5 * (A.y + B.y));  // u1^
+  const double2 a2 = make_double2(0.5 * (A.y - B.y), -0.5 * (A.x - B.x)); // u2^
+  const double2 sc = make_double2((k1 * a1.x + k2 * a2.x) / kk, (k1 * a1.y + k2 * a2.y) / kk);
+  const double2 p1 = make_double2(a1.x - k1 * sc.x, a1.y - k1 * sc.y);
+  const double2 p2 = make_double2(a2.x - k2 * sc.x, a2.y - k2 * sc.y);
+  return make_double2(p1.x - p2.y, p1.y + p2.x);
+}
+
+// signed wavenumber of an FFT index, the Nyquist index as 0
+__device__ inline double wn(int idx, int N) {
+  const int H = N >> 1;
+  return idx == H ? 0.0 : (double)(idx < H ? idx : idx - N);
+}
+
+// Rows r and N - r (one row when they coincide) of the half-transformed
+// packed pair, T[k2][i1]: forward transforms along i1, the projector on
+// every pair of modes (k, -k), which both lie in these rows, an in-place
+// bit-reversal permutation and the inverse transforms; written to out in
+// the same layout.  Replaces a row-transform pass, the projector pass and
+// a second row-transform pass.
+__global__ __launch_bounds__(256) void k_fft_project_pair(const double2 *T, double2 *out, int n,
+                                                          const double2 *twg) {
+  extern __shared__ double2 sm[];
   const int N = 1 << n, H = N >> 1, mask = N - 1;
-  const int64_t NN = (int64_t)N * N;
-  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < NN;
-       idx += (int64_t)gridDim.x * blockDim.x) {
-    const int row = (int)(idx >> n), col = (int)(idx & mask);
-    const double k2 = row == H ? 0.0 : (double)(row < H ? row : row - N);
-    const double k1 = col == H ? 0.0 : (double)(col < H ? col : col - N);
-    const double2 A = T[idx];
-    const double kk = k1 * k1 + k2 * k2;
-    if (kk == 0.0) {
-      out[idx] = A;
-      continue;
+  const int r0 = blockIdx.x, r1 = (N - r0) & mask;
+  const bool two = r0 != r1;
+  double2 *s0 = sm, *s1 = two ? sm + N : sm;
+  for (int j = threadIdx.x; j < N; j += blockDim.x) {
+    const int jr = __brev((unsigned)j) >> (32 - n);
+    s0[jr] = T[(int64_t)r0 * N + j];
+    if (two) s1[jr] = T[(int64_t)r1 * N + j];
+  }
+  __syncthreads();
+  for (int q = 0; q < (two ? 2 : 1); ++q) {
+    double2 *s = q ? s1 : s0;
+    for (int half = 1, rem = n; rem > 0;) {
+      const int R = (rem == 4 || rem == 2) ? 2 : (rem >= 3 ? 3 : 1);
+      if (R == 3) fused_stages<3>(s, twg, 1.0, N, half);
+      else if (R == 2) fused_stages<2>(s, twg, 1.0, N, half);
+      else fused_stages<1>(s, twg, 1.0, N, half);
+      __syncthreads();
+      half <<= R;
+      rem -= R;
     }
-    const double2 Bc = T[(int64_t)((N - row) & mask) * N + ((N - col) & mask)];
-    const double2 B = make_double2(Bc.x, -Bc.y);  // conj Z(-k)
-    const double2 a1 = make_double2(0.5 * (A.x + B.x), 0.5 * (A.y + B.y));  // u1^
-    const double2 a2 = make_double2(0.5 * (A.y - B.y), -0.5 * (A.x - B.x)); // u2^
-    const double2 sc = make_double2((k1 * a1.x + k2 * a2.x) / kk, (k1 * a1.y + k2 * a2.y) / kk);
-    const double2 p1 = make_double2(a1.x - k1 * sc.x, a1.y - k1 * sc.y);
-    const double2 p2 = make_double2(a2.x - k2 * sc.x, a2.y - k2 * sc.y);
-    out[idx] = make_double2(p1.x - p2.y, p1.y + p2.x);
+  }
+  // projector: each thread owns a mode and its mirror (reads and writes
+  // only that pair)
+  const double k2a = wn(r0, N), k2b = wn(r1, N);
+  if (two) {
+    for (int c = threadIdx.x; c < N; c += blockDim.x) {
+      const int m = (N - c) & mask;
+      const double2 A = s0[c], M = s1[m];
+      s0[c] = proj_mode(A, M, wn(c, N), k2a);
+      s1[m] = proj_mode(M, A, wn(m, N), k2b);
+    }
+  } else {
+    for (int c = threadIdx.x; c <= H; c += blockDim.x) {
+      const int m = (N - c) & mask;
+      const double2 A = s0[c], M = s0[m];
+      s0[c] = proj_mode(A, M, wn(c, N), k2a);
+      if (m != c) s0[m] = proj_mode(M, A, wn(m, N), k2a);
+    }
+  }
+  __syncthreads();
+  for (int q = 0; q < (two ? 2 : 1); ++q) {
+    double2 *s = q ? s1 : s0;
+    for (int j = threadIdx.x; j < N; j += blockDim.x) {
+      const int jr = __brev((unsigned)j) >> (32 - n);
+      if (j < jr) {
+        const double2 t = s[j];
+        s[j] = s[jr];
+        s[jr] = t;
+      }
+    }
+  }
+  __syncthreads();
+  for (int q = 0; q < (two ? 2 : 1); ++q) {
+    double2 *s = q ? s1 : s0;
+    for (int half = 1, rem = n; rem > 0;) {
+      const int R = (rem == 4 || rem == 2) ? 2 : (rem >= 3 ? 3 : 1);
+      if (R == 3) fused_stages<3>(s, twg, -1.0, N, half);
+      else if (R == 2) fused_stages<2>(s, twg, -1.0, N, half);
+      else fused_stages<1>(s, twg, -1.0, N, half);
+      __syncthreads();
+      half <<= R;
+      rem -= R;
+    }
+  }
+  for (int j = threadIdx.x; j < N; j += blockDim.x) {
+    out[(int64_t)r0 * N + j] = s0[j];
+    if (two) out[(int64_t)r1 * N + j] = s1[j];
   }
 }
 
@@ -363,20 +440,25 @@ void transpose(Ctx &c, int n, const double2 *in, double2 *out) {
 }
 
 // Z (packed u1* + i u2*) -> divergence-free (o1, o2); Z and T are clobbered.
+void project_pair(Ctx &c, int n, DnsBufs &b) {
+  const int N = 1 << n;
+  const int64_t NN = (int64_t)N * N;
+  c.check_range(b.T, 0, NN - 1, 16, "project in");
+  c.check_range(b.Z, 0, NN - 1, 16, "project out");
+  c.check_range(b.tw, 0, N / 2 - 1, 16, "project twiddles");
+  hipLaunchKernelGGL(k_fft_project_pair, dim3(N / 2 + 1), dim3(256), (size_t)2 * N * sizeof(double2),
+                     c.stream, b.T, b.Z, n, b.tw);
+  HIPC(hipGetLastError());
+}
+
+// Z (packed u1* + i u2*) -> divergence-free (o1, o2); Z and T are clobbered.
 void project_packed(Ctx &c, int n, DnsBufs &b, double *o1, double *o2) {
   const int N = 1 << n;
   const int64_t NN = (int64_t)N * N;
   fft_rows<0, 0>(c, n, b.Z, nullptr, nullptr, nullptr, nullptr, b.Z, nullptr, nullptr, 1.0,
                  nullptr, 0, 0, b.tw);
   transpose(c, n, b.Z, b.T);
-  fft_rows<0, 0>(c, n, b.T, nullptr, nullptr, nullptr, nullptr, b.T, nullptr, nullptr, 1.0,
-                 nullptr, 0, 0, b.tw);
-  c.check_range(b.T, 0, NN - 1, 16, "project in");
-  c.check_range(b.Z, 0, NN - 1, 16, "project out");
-  hipLaunchKernelGGL(k_dns_project, dim3(blocks_for(NN)), dim3(256), 0, c.stream, b.T, b.Z, n);
-  HIPC(hipGetLastError());
-  fft_rows<0, 0>(c, n, b.Z, nullptr, nullptr, nullptr, nullptr, b.Z, nullptr, nullptr, 1.0,
-                 nullptr, 0, 1, b.tw);
+  project_pair(c, n, b);
   transpose(c, n, b.Z, b.T);
   fft_rows<0, 1>(c, n, b.T, nullptr, nullptr, nullptr, nullptr, nullptr, o1, o2,
                  1.0 / (double)NN, nullptr, 0, 1, b.tw);
@@ -439,20 +521,12 @@ void dns_rhs(Ctx &c, const double *u1, const double *u2, double *f1, double *f2,
 void dns_project(Ctx &c, double *u1, double *u2, int n) {
   check_n(n, "dns_project");
   DnsBufs b = dns_bufs(c, n);
-  fft_rows<1, 0>(c, n, nullptr, u1, u2, nullptr, nullptr, b.Z, nullptr, nullptr, 1.0, nullptr, 0,
-                 0, b.tw);
-  // continue from the row-transformed pack: transpose, rows, project, back
   const int N = 1 << n;
   const int64_t NN = (int64_t)N * N;
+  fft_rows<1, 0>(c, n, nullptr, u1, u2, nullptr, nullptr, b.Z, nullptr, nullptr, 1.0, nullptr, 0,
+                 0, b.tw);
   transpose(c, n, b.Z, b.T);
-  fft_rows<0, 0>(c, n, b.T, nullptr, nullptr, nullptr, nullptr, b.T, nullptr, nullptr, 1.0,
-                 nullptr, 0, 0, b.tw);
-  c.check_range(b.T, 0, NN - 1, 16, "project in");
-  c.check_range(b.Z, 0, NN - 1, 16, "project out");
-  hipLaunchKernelGGL(k_dns_project, dim3(blocks_for(NN)), dim3(256), 0, c.stream, b.T, b.Z, n);
-  HIPC(hipGetLastError());
-  fft_rows<0, 0>(c, n, b.Z, nullptr, nullptr, nullptr, nullptr, b.Z, nullptr, nullptr, 1.0,
-                 nullptr, 0, 1, b.tw);
+  project_pair(c, n, b);
   transpose(c, n, b.Z, b.T);
   fft_rows<0, 1>(c, n, b.T, nullptr, nullptr, nullptr, nullptr, nullptr, u1, u2,
                  1.0 / (double)NN, nullptr, 0, 1, b.tw);
