@@ -364,8 +364,8 @@ def main():
         torch.cuda.synchronize()
         t_dns = time.perf_counter() - t1
         # HBM bytes per grid point of one RK4 step as the kernels move them:
-        # stage kernels 64 + 3 x 80, four projections of 240 (seven passes)
-        bpp = 64 + 3 * 80 + 4 * 240
+        # stage kernels 64 + 3 x 80, four projections of five 32-byte passes
+        bpp = 64 + 3 * 80 + 4 * 160
         dns = dict(workload=f'decaying jet {N} x {N}, RK4, Re {args.re:g}, dt {args.dt:g}',
                    steps=args.dns, ms_per_step=round(1e3 * t_dns / args.dns, 3),
                    steps_per_s=round(args.dns / t_dns, 2), bytes_per_step=bpp * N * N,
