@@ -134,9 +134,10 @@ __global__ void k_twiddles(double2 *tw, int n) {
 // stage r pairs m and m + 2^r (bit r of m clear) with the twiddle of the
 // element's position q in its group of 2^(r+1) half, exp(-+2 pi i q / (2^(r+1) half)).
 template <int R>
-__device__ inline void fused_stages(double2 *s, const double2 *twg, double tsg, int N, int half) {
+__device__ inline void fused_stages(double2 *s, const double2 *twg, double tsg, int N, int half,
+                                    int tid, int nth) {
   constexpr int E = 1 << R;
-  for (int t = threadIdx.x; t < (N >> R); t += blockDim.x) {
+  for (int t = tid; t < (N >> R); t += nth) {
     const int pos = t & (half - 1);
     const int i = ((t - pos) << R) + pos;
     double2 a[E];
@@ -193,9 +194,9 @@ __global__ __launch_bounds__(256) void k_fft_rows(const double2 *zin, const doub
   // LDS round trip and one barrier per group (R = 3, 3, 3, 2 for n = 11)
   for (int half = 1, rem = n; rem > 0;) {
     const int R = (rem == 4 || rem == 2) ? 2 : (rem >= 3 ? 3 : 1);
-    if (R == 3) fused_stages<3>(s, twg, tsg, N, half);
-    else if (R == 2) fused_stages<2>(s, twg, tsg, N, half);
-    else fused_stages<1>(s, twg, tsg, N, half);
+    if (R == 3) fused_stages<3>(s, twg, tsg, N, half, threadIdx.x, blockDim.x);
+    else if (R == 2) fused_stages<2>(s, twg, tsg, N, half, threadIdx.x, blockDim.x);
+    else fused_stages<1>(s, twg, tsg, N, half, threadIdx.x, blockDim.x);
     __syncthreads();
     half <<= R;
     rem -= R;
@@ -283,7 +284,7 @@ __device__ inline double wn(int idx, int N) {
 // bit-reversal permutation and the inverse transforms; written to out in
 // the same layout.  Replaces a row-transform pass, the projector pass and
 // a second row-transform pass.
-__global__ __launch_bounds__(256) void k_fft_project_pair(const double2 *T, double2 *out, int n,
+__global__ __launch_bounds__(512) void k_fft_project_pair(const double2 *T, double2 *out, int n,
                                                           const double2 *twg) {
   extern __shared__ double2 sm[];
   const int N = 1 << n, H = N >> 1, mask = N - 1;
@@ -296,17 +297,21 @@ __global__ __launch_bounds__(256) void k_fft_project_pair(const double2 *T, doub
     if (two) s1[jr] = T[(int64_t)r1 * N + j];
   }
   __syncthreads();
-  for (int q = 0; q < (two ? 2 : 1); ++q) {
-    double2 *s = q ? s1 : s0;
-    for (int half = 1, rem = n; rem > 0;) {
-      const int R = (rem == 4 || rem == 2) ? 2 : (rem >= 3 ? 3 : 1);
-      if (R == 3) fused_stages<3>(s, twg, 1.0, N, half);
-      else if (R == 2) fused_stages<2>(s, twg, 1.0, N, half);
-      else fused_stages<1>(s, twg, 1.0, N, half);
-      __syncthreads();
-      half <<= R;
-      rem -= R;
+  // the two rows are transformed concurrently, each by half of the workgroup
+  const int hq = threadIdx.x >= (blockDim.x >> 1), htid = threadIdx.x - hq * (blockDim.x >> 1);
+  const int hn = blockDim.x >> 1;
+  double2 *sq = hq ? s1 : s0;
+  const bool act = two || hq == 0;
+  for (int half = 1, rem = n; rem > 0;) {
+    const int R = (rem == 4 || rem == 2) ? 2 : (rem >= 3 ? 3 : 1);
+    if (act) {
+      if (R == 3) fused_stages<3>(sq, twg, 1.0, N, half, htid, hn);
+      else if (R == 2) fused_stages<2>(sq, twg, 1.0, N, half, htid, hn);
+      else fused_stages<1>(sq, twg, 1.0, N, half, htid, hn);
     }
+    __syncthreads();
+    half <<= R;
+    rem -= R;
   }
   // projector: each thread owns a mode and its mirror (reads and writes
   // only that pair)
@@ -339,17 +344,16 @@ __global__ __launch_bounds__(256) void k_fft_project_pair(const double2 *T, doub
     }
   }
   __syncthreads();
-  for (int q = 0; q < (two ? 2 : 1); ++q) {
-    double2 *s = q ? s1 : s0;
-    for (int half = 1, rem = n; rem > 0;) {
-      const int R = (rem == 4 || rem == 2) ? 2 : (rem >= 3 ? 3 : 1);
-      if (R == 3) fused_stages<3>(s, twg, -1.0, N, half);
-      else if (R == 2) fused_stages<2>(s, twg, -1.0, N, half);
-      else fused_stages<1>(s, twg, -1.0, N, half);
-      __syncthreads();
-      half <<= R;
-      rem -= R;
+  for (int half = 1, rem = n; rem > 0;) {
+    const int R = (rem == 4 || rem == 2) ? 2 : (rem >= 3 ? 3 : 1);
+    if (act) {
+      if (R == 3) fused_stages<3>(sq, twg, -1.0, N, half, htid, hn);
+      else if (R == 2) fused_stages<2>(sq, twg, -1.0, N, half, htid, hn);
+      else fused_stages<1>(sq, twg, -1.0, N, half, htid, hn);
     }
+    __syncthreads();
+    half <<= R;
+    rem -= R;
   }
   for (int j = threadIdx.x; j < N; j += blockDim.x) {
     out[(int64_t)r0 * N + j] = s0[j];
@@ -446,7 +450,7 @@ void project_pair(Ctx &c, int n, DnsBufs &b) {
   c.check_range(b.T, 0, NN - 1, 16, "project in");
   c.check_range(b.Z, 0, NN - 1, 16, "project out");
   c.check_range(b.tw, 0, N / 2 - 1, 16, "project twiddles");
-  hipLaunchKernelGGL(k_fft_project_pair, dim3(N / 2 + 1), dim3(256), (size_t)2 * N * sizeof(double2),
+  hipLaunchKernelGGL(k_fft_project_pair, dim3(N / 2 + 1), dim3(512), (size_t)2 * N * sizeof(double2),
                      c.stream, b.T, b.Z, n, b.tw);
   HIPC(hipGetLastError());
 }
