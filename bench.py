@@ -11,10 +11,17 @@ same state `--steps` timed RK4 steps:
     SVD / CG residual / overlap term, learned-preconditioner setting as given
     by --precond;
   * f64:   every contraction in float64 MFMA, unpreconditioned CG.
+Every minimisation sweeps until the paper's stop rule holds (Sec. II.C:
+relative change of sum_i <v_i|v_i> over a full sweep at most 1e-5, at most
+10 sweeps) unless --sweeps fixes the count.
 `value` is the mixed path's steps/s; the line also carries the float64 path's
-steps/s, their relative L2 difference, the roofline of the dominant GEMM
-kernel (HIP events around sampled launches, executed flops counted on the
-device), and the CPU oracle timed on a bounded sample.
+steps/s, the parity protocol (one step of each reduced-precision path from
+the common float64 state every `--parity-every` timed steps, relative L2
+error of the velocity field and of each component), the end-state
+difference after the timed steps, the sweeps the stop rule takes, the
+roofline of the dominant GEMM kernel (HIP events around sampled launches,
+executed flops counted on the device), and the CPU oracle timed on a
+bounded sample and scaled to a step.
 """
 import argparse
 import json
@@ -42,7 +49,10 @@ def parse():
     ap.add_argument('--chi', type=int, default=128)
     ap.add_argument('--re', type=float, default=1e7)
     ap.add_argument('--dt', type=float, default=5e-5)
-    ap.add_argument('--sweeps', type=int, default=2)
+    ap.add_argument('--sweeps', type=int, default=0,
+                    help='0: the stop rule of the sweep (Sec. II.C: relative change of '
+                         'sum <v_i|v_i> over a full sweep at most 1e-5, at most 10 sweeps); '
+                         'S > 0: exactly S sweeps per minimisation')
     ap.add_argument('--cg-rtol', type=float, default=1e-10)
     ap.add_argument('--mixed-cg-rtol', type=float, default=1e-9,
                     help='CG tolerance of the reduced-precision paths: their right-hand '
@@ -54,6 +64,14 @@ def parse():
                     help='mixed: float32 convection networks; bf16x3: compensated split '
                          'bfloat16 convection networks; f64: all float64')
     ap.add_argument('--precond', type=int, default=0)
+    ap.add_argument('--parity-every', type=int, default=20,
+                    help='parity protocol: one step of each reduced-precision path from the '
+                         'common float64 state at timed steps 0, E, 2E, ... (relative L2 per '
+                         'component against the float64 step from the same state)')
+    ap.add_argument('--sweep-rule', type=int, default=1,
+                    help='also run one float64 step with the stop rule of the sweep (relative '
+                         'change of sum <v_i|v_i> below 1e-5, at most 10 sweeps) and report the '
+                         'sweeps it takes per stage next to the fixed count')
     ap.add_argument('--sample-every', type=int, default=8)
     ap.add_argument('--cpu-sample', type=int, default=1, help='time the CPU oracle sample')
     ap.add_argument('--save-state', default='', help='write the state after warm-up (.npz)')
@@ -106,6 +124,24 @@ def measured_traffic(kernel):
     return None
 
 
+def measured_cpu_step():
+    """The committed timing of one complete oracle RK4 step at this size
+    (profiles/cpu_oracle_rk4_step_*.txt), as a check of the sample's
+    scaling, or None."""
+    import glob
+    for f in sorted(glob.glob(os.path.join(ROOT, 'profiles', 'cpu_oracle_rk4_step_*.txt'))):
+        kv = {}
+        for line in open(f):
+            if ':' in line and not line.startswith(' '):
+                k, v = line.split(':', 1)
+                kv[k.strip()] = v.strip()
+        if 'seconds_per_step' in kv:
+            return dict(file=os.path.relpath(f, ROOT), seconds_per_step=float(kv['seconds_per_step']),
+                        cores=int(kv.get('cores', 0)), workload=kv.get('workload', ''),
+                        sample_seconds=float(kv.get('sample_seconds', 'nan')))
+    return None
+
+
 def log(*a):
     print('[bench]', *a, file=sys.stderr, flush=True)
 
@@ -114,12 +150,21 @@ def clone(Q, m):
     return Q.MPS(list(m.bonds), m.data.clone())
 
 
-def rel_l2(Q, ctx, x, y, chi):
+def sq_diff(Q, ctx, x, y, chi):
+    """(||x - y||^2, ||y||^2) of one component; the difference is brought to
+    canonical form first (its norm is then its centre's), which avoids the
+    cancellation of <x|x> + <y|y> - 2<x|y>."""
     d = Q.add(ctx, [1.0, -1.0], [x, y])
     Q.truncate(ctx, d, 4 * chi, 0.0)     # canonical form; keeps every direction
-    nd = max(Q.inner(ctx, d, d), 0.0) ** 0.5
-    ny = max(Q.inner(ctx, y, y), 0.0) ** 0.5
-    return nd / ny
+    return max(Q.inner(ctx, d, d), 0.0), max(Q.inner(ctx, y, y), 0.0)
+
+
+def rel_err(Q, ctx, X, Y, chi):
+    """Relative L2 error of the velocity field X = (x1, x2) against Y:
+    ||X - Y|| / ||Y|| over both components, and per component."""
+    sq = [sq_diff(Q, ctx, X[i], Y[i], chi) for i in range(2)]
+    field = (sum(d for d, _ in sq) / sum(y for _, y in sq)) ** 0.5
+    return dict(field=field, components=[(d / y) ** 0.5 for d, y in sq])
 
 
 def cpu_sample(uc, chi, re, dt):
@@ -184,7 +229,8 @@ def main():
     def prm_for(path, rhs_mode=0, fit_sweeps=0):
         return Q.params(re=args.re, dt=args.dt, chi=chi, dx=dx,
                         cg_rtol=args.cg_rtol if path == 'f64' else args.mixed_cg_rtol,
-                        cg_maxit=args.cg_maxit, max_sweeps=args.sweeps, svd_rtol=1e-12,
+                        cg_maxit=args.cg_maxit, max_sweeps=args.sweeps or 10,
+                        sweep_rtol=0.0 if args.sweeps else 1e-5, svd_rtol=1e-12,
                         prec={'mixed': Q.PREC_F32, 'bf16x3': Q.PREC_BF16X3}.get(path, Q.PREC_F64),
                         precond=args.precond if path != 'f64' else Q.PC_NONE, rhs_mode=rhs_mode,
                         fit_sweeps=fit_sweeps)
@@ -226,6 +272,7 @@ def main():
 
     paths = [p for p in args.paths.split(',') if p]
     results, finals, kstats = {}, {}, {}
+    snaps = []   # (k, float64 state before timed step k, float64 state after it)
     for path in paths:
         prm = prm_for(path)
         # one untimed step of this path (its GEMM tile tuning, graph capture
@@ -237,14 +284,22 @@ def main():
         u = [clone(Q, state[0]), clone(Q, state[1])]
         Q.kernel_timing(ctx, True, args.sample_every)
         cg_total, cg_solves = 0, 0
+        sweeps_used = []
         torch.cuda.synchronize()
         log(f'{path} timed window start ns {time.monotonic_ns()}')
         t1 = time.perf_counter()
         for s in range(args.steps):
+            snap = path == 'f64' and args.parity_every > 0 and s % args.parity_every == 0
+            if snap:
+                before = [clone(Q, u[0]), clone(Q, u[1])]
             rc, st = Q.rk4_step(ctx, u, prm)
+            if snap:
+                snaps.append((s, before, [clone(Q, u[0]), clone(Q, u[1])]))
             cg_total += st['cg_iters_total']
             cg_solves += st['cg_solves']
-            log(f'{path} step {s} {time.perf_counter() - t1:.2f}s cg {st["cg_iters_total"]}')
+            sweeps_used.append(list(st['sweeps']))
+            log(f'{path} step {s} {time.perf_counter() - t1:.2f}s cg {st["cg_iters_total"]} '
+                f'sweeps {st["sweeps"]}')
         torch.cuda.synchronize()
         el = time.perf_counter() - t1
         log(f'{path} timed window end ns {time.monotonic_ns()}')
@@ -252,18 +307,71 @@ def main():
         Q.kernel_timing(ctx, False)
         results[path] = dict(seconds=el, steps_per_s=args.steps / el,
                              cg_iters_per_solve=cg_total / max(cg_solves, 1),
-                             cg_rtol=prm.cg_rtol)
+                             cg_rtol=prm.cg_rtol,
+                             sweeps_per_minimisation=sum(map(sum, sweeps_used)) /
+                             max(4 * len(sweeps_used), 1))
         finals[path] = u
         log(path, results[path])
 
     main_path = 'mixed' if 'mixed' in results else paths[0]
     rel = None
-    if 'mixed' in finals and 'f64' in finals:
-        rel = max(rel_l2(Q, ctx, finals['mixed'][i], finals['f64'][i], chi) for i in range(2))
     for p_ in results:
         if p_ != 'f64' and 'f64' in finals:
-            results[p_]['rel_l2_vs_f64'] = max(
-                rel_l2(Q, ctx, finals[p_][i], finals['f64'][i], chi) for i in range(2))
+            e = rel_err(Q, ctx, finals[p_], finals['f64'], chi)
+            results[p_]['rel_l2_vs_f64'] = e['field']
+            results[p_]['rel_l2_vs_f64_components'] = e['components']
+    if 'mixed' in results and 'f64' in finals:
+        rel = results['mixed']['rel_l2_vs_f64']
+
+    # parity protocol: every reduced-precision path takes one step from the
+    # float64 state at timed steps 0, E, 2E, ... and is compared with the
+    # float64 step from the same state; the end-state difference after all
+    # timed steps (above) is reported beside it
+    parity = None
+    if snaps:
+        parity = dict(bar=1e-5, every=args.parity_every,
+                      protocol='one RK4 step of the path from the common float64 state at timed '
+                               'steps 0, E, 2E, ...; relative L2 error of the velocity field '
+                               '(both components) against the float64 step from that state, '
+                               'and per component', paths={})
+        for p_ in paths:
+            if p_ == 'f64':
+                continue
+            errs, comps = [], []
+            for k, before, after in snaps:
+                w = [clone(Q, before[0]), clone(Q, before[1])]
+                Q.rk4_step(ctx, w, prm_for(p_))
+                e = rel_err(Q, ctx, w, after, chi)
+                errs.append(e['field'])
+                comps.append(e['components'])
+            parity['paths'][p_] = dict(
+                steps=[k for k, _, _ in snaps], per_step=errs, per_step_components=comps,
+                per_step_max=max(errs), ok=max(errs) <= 1e-5,
+                per_step_components_max=max(max(c) for c in comps),
+                end_state_after_steps=args.steps, end_state=results[p_].get('rel_l2_vs_f64'),
+                end_state_components=results[p_].get('rel_l2_vs_f64_components'))
+            log('parity', p_, parity['paths'][p_])
+        del snaps
+
+    # the sweep's stop rule (Sec. II.C) at this workload: the sweeps it takes
+    # per stage, and the float64 step it gives against two and three sweeps
+    # from the same state
+    sweep_rule = None
+    if args.sweep_rule:
+        w = [clone(Q, state[0]), clone(Q, state[1])]
+        pr = prm_for('f64')
+        pr.sweep_rtol, pr.max_sweeps = 1e-5, 10
+        rc, st = Q.rk4_step(ctx, w, pr)
+        sweep_rule = dict(sweep_rtol=1e-5, max_sweeps=10, sweeps_per_stage=list(st['sweeps']))
+        for S_ in (2, 3):
+            ref = [clone(Q, state[0]), clone(Q, state[1])]
+            pr = prm_for('f64')
+            pr.sweep_rtol, pr.max_sweeps = 0.0, S_
+            Q.rk4_step(ctx, ref, pr)
+            e = rel_err(Q, ctx, w, ref, chi)
+            sweep_rule[f'rel_l2_rule_vs_{S_}_sweeps'] = e['field']
+            sweep_rule[f'rel_l2_rule_vs_{S_}_sweeps_components'] = e['components']
+        log('sweep rule', sweep_rule)
 
     schedules = None
     if args.schedules:
@@ -288,8 +396,9 @@ def main():
                 r = dict(steps_per_s=args.steps / el, cg_iters_per_solve=cg_total / max(cg_solves, 1),
                          bonds=[u[0].bonds, u[1].bonds])
                 if 'f64' in finals:
-                    r['rel_l2_vs_rk4_f64'] = max(rel_l2(Q, ctx, u[i], finals['f64'][i], chi)
-                                                 for i in range(2))
+                    e = rel_err(Q, ctx, u, finals['f64'], chi)
+                    r['rel_l2_vs_rk4_f64'] = e['field']
+                    r['rel_l2_vs_rk4_f64_components'] = e['components']
                 res[path] = r
                 log(f'rk{order} {path}', r)
             schedules[f'rk{order}'] = res
@@ -316,8 +425,9 @@ def main():
             el = time.perf_counter() - t1
             r = dict(steps_per_s=args.steps / el, cg_iters_per_solve=cg_total / max(cg_solves, 1))
             if 'f64' in finals:
-                r['rel_l2_vs_implicit_f64'] = max(rel_l2(Q, ctx, u[i], finals['f64'][i], chi)
-                                                  for i in range(2))
+                e = rel_err(Q, ctx, u, finals['f64'], chi)
+                r['rel_l2_vs_implicit_f64'] = e['field']
+                r['rel_l2_vs_implicit_f64_components'] = e['components']
             explicit[path] = r
             log(f'explicit rhs {path}', r)
 
@@ -483,12 +593,17 @@ def main():
         cpu_step_s = step_s * (t_cpu * 1e3) / max(gpu_env_ms, 1e-9)
         cpu = dict(value=round(1.0 / cpu_step_s, 6), unit='RK4 steps/s', cores=cores,
                    kind='oracle',
-                   sample=(f'oracle right-environment build of the first RK4 stage (20 networks, '
-                           f'sites {n - 1}..1) on the timed state ({1 << n}^2, chi={chi}): '
-                           f'{t_cpu:.1f} s on {cores} host threads vs {gpu_env_ms:.1f} ms for the '
-                           f'same phase on the GPU; RK4 steps/s scaled by that ratio'))
+                   sample=(f'extrapolated from a timed sample: the oracle\'s right-environment '
+                           f'build of the first RK4 stage (20 networks, sites {n - 1}..1) on the '
+                           f'timed state ({1 << n}^2, chi={chi}) took {t_cpu:.1f} s on {cores} host '
+                           f'threads against {gpu_env_ms:.1f} ms for the same phase on the GPU; '
+                           f'the GPU step time is scaled by that ratio'))
+        full = measured_cpu_step()
+        if full is not None:
+            cpu['full_step_measured'] = full
 
-    line = dict(metric='RK4 steps/s, 2^11^2 grid chi=128, mixed vs FP64 plain at <=1e-5 rel L2',
+    line = dict(metric='RK4 steps/s, 2^11^2 grid chi=128, mixed vs FP64 plain at <=1e-5 rel L2 '
+                       '(velocity field, one step from the common FP64 state)',
                 value=round(results[main_path]['steps_per_s'], 5), unit='RK4 steps/s',
                 n_gpus=1, steps=args.steps, warmup=args.warmup,
                 ms_per_step=round(1e3 * results[main_path]['seconds'] / args.steps, 2),
@@ -497,9 +612,12 @@ def main():
                 config=dict(workload=f'decaying jet, {1 << n}x{1 << n} grid ({n} sites), '
                                      f'chi={chi}, Re={args.re:g}, dt={args.dt:g}',
                             spinup_steps=spin, bonds=[state[0].bonds, state[1].bonds],
-                            sweeps=args.sweeps, cg_rtol=args.cg_rtol, precond=args.precond),
+                            sweeps=(args.sweeps if args.sweeps else
+                                    'stop rule: relative change of sum <v_i|v_i> <= 1e-5, at most 10'),
+                            cg_rtol=results[main_path]['cg_rtol'],
+                            f64_cg_rtol=args.cg_rtol, precond=args.precond),
                 paths={k: dict(v, **({} if k not in kstats else {})) for k, v in results.items()},
-                rel_l2_mixed_vs_f64=rel,
+                rel_l2_mixed_vs_f64=rel, parity=parity, sweep_rule=sweep_rule,
                 roofline=roofline, cpu_baseline=cpu)
     if schedules is not None:
         line['schedules'] = schedules

@@ -67,6 +67,22 @@ def to_dense(cores):
     return decode(to_vector(cores), n)
 
 
+def values_at(cores, pts):
+    """Field values at grid points pts[p] = (x1, x2): the product over sites
+    of the core matrices C_k[:, omega_k, :] with omega_k = 2 bit_k(x1) +
+    bit_k(x2), bit 0 the most significant (the encoding of Sec. II.B)."""
+    n = len(cores)
+    pts = np.asarray(pts)
+    out = np.empty(len(pts))
+    for p, (x1, x2) in enumerate(pts):
+        row = np.ones((1, 1))
+        for k in range(n):
+            w = 2 * ((int(x1) >> (n - 1 - k)) & 1) + ((int(x2) >> (n - 1 - k)) & 1)
+            row = row @ cores[k][:, w, :]
+        out[p] = row[0, 0]
+    return out
+
+
 def copy(cores):
     return [c.copy() for c in cores]
 

@@ -1,7 +1,12 @@
 """Parity at the benchmark's size (2048 x 2048 grid, 11 sites): the oracle
 checks TT-rounding of a 4-term sum at chi = 128 (the RK4 combination's
-shape) directly, and a whole RK4 step at chi = 16; at chi = 128 the step is
-checked through properties that hold at any size."""
+shape) directly, a one-sweep projection at chi = 128 with every bond at its
+structural bound (sampled values of the oracle's result, written by
+tests/golden/make_project_n11_chi128.py), and a whole RK4 step at chi = 16;
+at chi = 128 the step is also checked through properties that hold at any
+size."""
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -36,6 +41,58 @@ def test_truncate_four_term_sum_chi128(Q, ctx):
     assert d.bonds == M.bonds(ref)
     assert M.rel_l2(d.cores(), ref) < 1e-10
     assert abs(disc - disc_ref) <= 1e-9 * disc_ref
+
+
+def _golden_project():
+    import importlib.util
+    here = os.path.join(os.path.dirname(__file__), 'golden')
+    spec = importlib.util.spec_from_file_location(
+        'make_project_n11_chi128', os.path.join(here, 'make_project_n11_chi128.py'))
+    gen = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(gen)
+    kv, pts, vals = {}, [], []
+    with open(os.path.join(here, 'project_n11_chi128.txt')) as f:
+        for line in f:
+            if line.startswith('#'):
+                continue
+            t = line.split()
+            if len(t) == 4:
+                pts.append((int(t[0]), int(t[1])))
+                vals.append((float(t[2]), float(t[3])))
+            else:
+                kv[t[0]] = t[1:]
+    return gen, kv, np.array(pts), np.array(vals)
+
+
+@pytest.mark.parametrize('prec,tol', [('f64', 1e-10), ('f32', 1e-5)])
+def test_project_saturated_chi128_matches_oracle(Q, ctx, prec, tol):
+    """One sweep at 2048 x 2048 with bonds [1, 4, 16, 64, 128 x 6, 64, 16, 4, 1]:
+    the shapes of the benchmark's largest contractions (float32 128 x 128
+    tiles with float32 storage in the f32 mode, split-K, the blocked QR of
+    the shifts).  Bonds bit-exact; sampled values and norms within 1e-10
+    (float64) or 1e-5 (float32 convection networks) of the oracle."""
+    gen, kv, pts, vals = _golden_project()
+    a, b, h, oprm = gen.case()
+    n, chi = gen.N_SITES, gen.CHI
+    prm = Q.params(re=oprm.re, dt=oprm.dt, chi=chi, dx=oprm.dx, max_sweeps=1,
+                   cg_rtol=oprm.cg_rtol, prec=Q.PREC_F32 if prec == 'f32' else Q.PREC_F64)
+    v = [Q.MPS.from_cores(c) for c in a]
+    Q.kernel_timing(ctx, True, 1 << 30)
+    rc, st = Q.project(ctx, [Q.MPS.from_cores(c) for c in a], [Q.MPS.from_cores(c) for c in b],
+                       h, prm, v)
+    big = Q.kernel_stats(ctx, 3)['launches'] if prec == 'f32' else None
+    Q.kernel_timing(ctx, False)
+    assert rc == 0
+    for i in range(2):
+        assert v[i].bonds == [int(x) for x in kv[f'bonds{i}']]
+        ref_vals = vals[:, i]
+        got_vals = M.values_at(v[i].cores(), pts)
+        nref = float(kv[f'normsq{i}'][0])
+        err = np.sqrt(np.mean((got_vals - ref_vals) ** 2)) / np.sqrt(nref / 4 ** n)
+        assert err < tol, (i, err)
+        assert abs(Q.inner(ctx, v[i], v[i]) - nref) <= tol * nref
+    if prec == 'f32':
+        assert big > 0, 'the float32 128 x 128 GEMM tile was not reached'
 
 
 def test_rk4_step_chi16_full_grid(Q, ctx):

@@ -239,6 +239,43 @@ def test_project_matches_oracle_split_k_matvec(Q, ctx):
         assert M.rel_l2(v[i].cores(), ref[i]) < TOL
 
 
+def test_project_sweep_stop_rule_matches_oracle(Q, ctx):
+    """Sec. II.C stop rule (relative change of sum_i <v_i|v_i> over a full
+    sweep at most sweep_rtol): on a case that needs several sweeps the GPU
+    stops after the oracle's sweep count with the oracle's state; with the cap
+    one sweep below that count it returns QTT_W_SWEEP_MAXIT and the capped
+    state."""
+    n, chi = 5, 6
+    dx = 1.0 / (1 << n)
+    u = I.decaying_jet(n)
+    b = _mps_pair(u, chi)
+    a = [M.scale(c, 0.25) for c in b]
+    h = 1e-3 / 3
+    ost = S.Stats()
+    ref = S.project(a, b, h, S.Params(re=1e3, dt=1e-3, chi=chi, dx=dx, max_sweeps=10,
+                                      sweep_rtol=1e-5), a, ost)
+    assert ost.sweeps > 1
+    prm = Q.params(re=1e3, dt=1e-3, chi=chi, dx=dx, max_sweeps=10, sweep_rtol=1e-5)
+    v = [dev(Q, c) for c in a]
+    rc, st = Q.project(ctx, [dev(Q, c) for c in a], [dev(Q, c) for c in b], h, prm, v)
+    assert rc == 0
+    assert st['sweeps'][0] == ost.sweeps
+    for i in range(2):
+        assert v[i].bonds == M.bonds(ref[i])
+        assert M.rel_l2(v[i].cores(), ref[i]) < TOL
+    cap = ost.sweeps - 1
+    ost2 = S.Stats()
+    ref2 = S.project(a, b, h, S.Params(re=1e3, dt=1e-3, chi=chi, dx=dx, max_sweeps=cap,
+                                       sweep_rtol=1e-5), a, ost2)
+    prm = Q.params(re=1e3, dt=1e-3, chi=chi, dx=dx, max_sweeps=cap, sweep_rtol=1e-5)
+    v = [dev(Q, c) for c in a]
+    rc, st = Q.project(ctx, [dev(Q, c) for c in a], [dev(Q, c) for c in b], h, prm, v)
+    assert rc == Q.W_SWEEP_MAXIT
+    assert st['sweeps'][0] == ost2.sweeps == cap
+    for i in range(2):
+        assert M.rel_l2(v[i].cores(), ref2[i]) < TOL
+
+
 def test_project_cg_iteration_limit(Q, ctx):
     """cg_maxit = 3: every local solve stops after three iterations (the CG
     step runs inside the matvec, the limit is tested in its reduction); the

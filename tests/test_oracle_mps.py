@@ -33,6 +33,23 @@ def test_encoding_x1_is_high_bit():
     assert idx[1, 1] == 3               # last site carries the least significant bits
 
 
+def test_values_at_equals_dense_field():
+    """Pointwise evaluation: the TT-SVD of a dense field is exact at full
+    rank, so its values at grid points are the field's; for random cores
+    they equal the dense reconstruction's."""
+    n = 4
+    N = 1 << n
+    U = np.random.default_rng(41).standard_normal((N, N))
+    cores, _ = M.tt_svd(U, 1 << (2 * n))
+    pts = np.random.default_rng(42).integers(0, N, size=(50, 2))
+    np.testing.assert_allclose(M.values_at(cores, pts), U[pts[:, 0], pts[:, 1]], rtol=0,
+                               atol=1e-12 * np.abs(U).max())
+    x = I.random_cores(I.canonical_bonds(n, 7), 43)
+    D = M.to_dense(x)
+    np.testing.assert_allclose(M.values_at(x, pts), D[pts[:, 0], pts[:, 1]], rtol=0,
+                               atol=1e-13 * np.abs(D).max())
+
+
 # ---------------------------------------------------------------- MPOs
 def test_carry_core_matches_paper_table():
     rows = [tuple(int(t) for t in line.split())

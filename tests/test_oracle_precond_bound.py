@@ -17,7 +17,11 @@ equalises its diagonal).
 
 Truncated (chi below full rank): on an actual local system of a sweep the
 exact inverse of the 4 x 4 position blocks (the network's block form) does
-not lower the CG iteration count.
+not lower the CG iteration count, and neither do the two structured
+approximations of a whole component block that could be applied at
+O(chi^3) cost (a Kronecker sum L + W + R or a Kronecker product L x W x R of
+chi x chi, 4 x 4 and chi x chi factors, each the Frobenius-nearest of its
+form) over the local solves of a sweep.
 """
 import numpy as np
 
@@ -155,3 +159,75 @@ def test_position_block_inverse_on_truncated_local_system():
     assert plain > 50
     assert with_pos >= plain, (plain, with_pos)
     assert with_comp < plain, (plain, with_comp)
+
+
+def _kron_sum_fit(K, l, r):
+    """Frobenius-nearest A (x) I (x) I + I (x) B (x) I + I (x) I (x) C to K
+    (l*4*r square, index order (alpha, omega, beta)): the traceless parts of
+    the scaled partial traces, the identity part carried by A."""
+    K6 = K.reshape(l, 4, r, l, 4, r)
+    T = np.trace(K)
+    A = np.einsum('awbcwb->ac', K6) / (4 * r)
+    B = np.einsum('awbavb->wv', K6) / (l * r) - T / (4 * l * r) * np.eye(4)
+    C = np.einsum('awbawc->bc', K6) / (4 * l) - T / (4 * l * r) * np.eye(r)
+    return A, B, C
+
+
+def _kron_sum_inverse(A, B, C, l, r):
+    la, Qa = np.linalg.eigh(0.5 * (A + A.T))
+    lb, Qb = np.linalg.eigh(0.5 * (B + B.T))
+    lc, Qc = np.linalg.eigh(0.5 * (C + C.T))
+    lam = np.maximum(1.0 + la[:, None, None] + lb[None, :, None] + lc[None, None, :], 1.0)
+
+    def apply(x):
+        Y = np.einsum('ia,iwb,wv,bc->avc', Qa, x.reshape(l, 4, r), Qb, Qc, optimize=True) / lam
+        return np.einsum('ai,avc,wv,bc->iwb', Qa, Y, Qb, Qc, optimize=True).ravel()
+    return apply
+
+
+def _kron_prod_fit(K, l, r, iters=30):
+    """Frobenius-nearest X (x) Y (x) Z to K by alternating least squares."""
+    K6 = K.reshape(l, 4, r, l, 4, r)
+    X, Y, Z = np.eye(l), np.eye(4), np.eye(r)
+    for _ in range(iters):
+        X = np.einsum('awbcvd,wv,bd->ac', K6, Y, Z, optimize=True) / (np.sum(Y * Y) * np.sum(Z * Z))
+        Y = np.einsum('awbcvd,ac,bd->wv', K6, X, Z, optimize=True) / (np.sum(X * X) * np.sum(Z * Z))
+        Z = np.einsum('awbcvd,ac,wv->bd', K6, X, Y, optimize=True) / (np.sum(X * X) * np.sum(Y * Y))
+    Xi, Yi, Zi = np.linalg.inv(X), np.linalg.inv(Y), np.linalg.inv(Z)
+    return lambda x: np.einsum('ac,wv,bd,cvd->awb', Xi, Yi, Zi, x.reshape(l, 4, r),
+                               optimize=True).ravel()
+
+
+def test_kronecker_component_preconditioners_do_not_pay_over_a_sweep():
+    """Decaying jet, 64 x 64, chi = 16, mu h^2 / dx^2 = 290 (the benchmark's
+    stage ratio): the warm-started CG iterations of the local solves at
+    sites 1..4 sum to more with either Kronecker form than without a
+    preconditioner, although each approximates its block to about 30%."""
+    n, chi = 6, 16
+    dx = 1.0 / (1 << n)
+    h = (290.0 * dx * dx / 2.5e5) ** 0.5
+    u = I.decaying_jet(n)
+    b = [M.tt_svd(u[i], chi, 1e-12)[0] for i in range(2)]
+    a = [M.scale(x, 0.25) for x in b]
+    prm = S.Params(re=1e7, dt=3 * h, chi=chi, dx=dx)
+    plain = ksum = kprod = 0
+    for d in range(1, 5):
+        A, rhs, x0, n0, shape = _local_matrix(a, b, h, prm, d)
+        N = A.shape[0]
+        sums, prods = [], []
+        for i in range(2):
+            l, _, r = shape[i]
+            sl = slice(0, n0) if i == 0 else slice(n0, N)
+            Aii = A[sl, sl]
+            K = Aii - np.eye(Aii.shape[0])
+            Af, Bf, Cf = _kron_sum_fit(K, l, r)
+            fit = (np.kron(np.kron(Af, np.eye(4)), np.eye(r))
+                   + np.kron(np.kron(np.eye(l), Bf), np.eye(r)) + np.kron(np.eye(4 * l), Cf))
+            assert np.linalg.norm(K - fit) <= 0.5 * np.linalg.norm(K)
+            sums.append(_kron_sum_inverse(Af, Bf, Cf, l, r))
+            prods.append(_kron_prod_fit(Aii, l, r))
+        plain += _pcg_iters(A, rhs, x0, lambda v: v)
+        ksum += _pcg_iters(A, rhs, x0, lambda v: np.concatenate([sums[0](v[:n0]), sums[1](v[n0:])]))
+        kprod += _pcg_iters(A, rhs, x0,
+                            lambda v: np.concatenate([prods[0](v[:n0]), prods[1](v[n0:])]))
+    assert ksum > plain and kprod > plain, (plain, ksum, kprod)
