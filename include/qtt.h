@@ -175,6 +175,22 @@ int qtt_hadamard(qtt_ctx *ctx, const qtt_mps *a, const qtt_mps *b, int32_t chi,
 /* <x|y> (host result). */
 int qtt_inner(qtt_ctx *ctx, const qtt_mps *x, const qtt_mps *y, double *out);
 
+/* <x|y> for callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): no context, no
+ * allocation.  The same contraction as qtt_inner, with its workspace in a
+ * fixed 3 MiB device array of the library (one copy per device, held until
+ * the process ends).  hip_stream: the stream to enqueue on (NULL: the null
+ * stream), on the current device; x, y: caller-owned device MPS as for
+ * qtt_inner; out: device pointer to one double, written asynchronously
+ * (valid once the stream has reached the call's end).  Every bond product
+ * x.bond[s] * y.bond[s] and x.bond[s] * y.bond[s+1] must be <= 65536
+ * (both bonds <= 256 suffices), else QTT_E_CAPACITY; malformed descriptors,
+ * a null out or differing site counts give QTT_E_ARG, a launch failure
+ * QTT_E_HIP.  All calls on one device share the workspace: calls that
+ * overlap on one device (other streams or host threads) race and must be
+ * serialised by the caller. */
+int qtt_inner_noalloc(void *hip_stream, const qtt_mps *x, const qtt_mps *y, double *out);
+
 /* Dense grid (device, N x N, x1-major, float64) of an MPS, n <= 13. */
 int qtt_to_dense(qtt_ctx *ctx, const qtt_mps *x, double *grid);
 

@@ -63,7 +63,8 @@ SYMBOLS = ['qtt_kernel_timing', 'qtt_kernel_stats_read', 'qtt_ctx_create', 'qtt_
            'qtt_inner', 'qtt_to_dense', 'qtt_from_dense', 'qtt_project', 'qtt_rk4_step',
            'qtt_precond_config', 'qtt_precond_info', 'qtt_precond_weights', 'qtt_precond_grad',
            'qtt_rk4_step_batched', 'qtt_rk_step', 'qtt_schmidt_counts', 'qtt_dns_rhs',
-           'qtt_dns_project', 'qtt_dns_step', 'qtt_fidelity', 'qtt_tke_shells', 'qtt_tke_spectrum']
+           'qtt_dns_project', 'qtt_dns_step', 'qtt_fidelity', 'qtt_tke_shells', 'qtt_tke_spectrum',
+           'qtt_inner_noalloc']
 
 _lib = None
 
@@ -90,6 +91,7 @@ def lib():
         'qtt_apply_mpo': (I32, [P, pmo, pm, I32, D, pm, pd]),
         'qtt_hadamard': (I32, [P, pm, pm, I32, D, pm, pd]),
         'qtt_inner': (I32, [P, pm, pm, pd]),
+        'qtt_inner_noalloc': (I32, [P, pm, pm, P]),
         'qtt_to_dense': (I32, [P, pm, P]),
         'qtt_from_dense': (I32, [P, P, I32, I32, D, pm]),
         'qtt_project': (I32, [P, pm, pm, D, ctypes.POINTER(c_params), pm,
@@ -304,6 +306,19 @@ def inner(ctx, x, y):
     ctx.check(lib().qtt_inner(ctx.h, ctypes.byref(xs), ctypes.byref(ys), ctypes.byref(out)),
               'inner')
     return out.value
+
+
+def inner_noalloc(x, y, out, stream=None):
+    """<x|y> into the device float64 tensor `out` (one element) without
+    allocation, enqueued on `stream` (default: torch's current stream);
+    returns the C return code (0, or QTT_E_* below zero)."""
+    if out.dtype != torch.float64 or not out.is_cuda or out.numel() < 1:
+        raise ValueError('inner_noalloc: out must be a float64 device tensor')
+    if stream is None:
+        stream = torch.cuda.current_stream(out.device)
+    xs, ys = x.struct(), y.struct()
+    return lib().qtt_inner_noalloc(ctypes.c_void_p(stream.cuda_stream), ctypes.byref(xs),
+                                   ctypes.byref(ys), ctypes.c_void_p(out.data_ptr()))
 
 
 def to_dense(ctx, x):
