@@ -47,6 +47,11 @@ def parse():
                          '-1: until the largest bond of both components reaches chi (at most 16)')
     ap.add_argument('--n', type=int, default=11)
     ap.add_argument('--chi', type=int, default=128)
+    ap.add_argument('--field', default='jet', choices=['jet', 'spectrum'],
+                    help='initial field: the decaying jet (App. C) or the random-phase '
+                         'spectrum E(k) ~ k^4 exp(-2 (k/k0)^2) (seeded, divergence-free)')
+    ap.add_argument('--k0', type=float, default=16.0)
+    ap.add_argument('--seed', type=int, default=5)
     ap.add_argument('--re', type=float, default=1e7)
     ap.add_argument('--dt', type=float, default=5e-5)
     ap.add_argument('--sweeps', type=int, default=0,
@@ -99,6 +104,20 @@ def parse():
                          'chi = 64) and of the dense DNS on the random-phase spectrum field for '
                          'n = 6 .. this value (at most 11), the runtime comparison over grid '
                          'sizes; reported under "crossover"')
+    ap.add_argument('--learned', type=int, default=0,
+                    help='also time this many RK4 steps of the mixed path with the learned '
+                         'preconditioner (trained on-line on the solves\' own local systems, '
+                         '--learned-train Adam steps per solve) from the same state; reported '
+                         'under "learned" with CG iterations, fallbacks and the difference to '
+                         'the float64 path')
+    ap.add_argument('--learned-train', type=int, default=4)
+    ap.add_argument('--batch', type=int, default=0,
+                    help='also time this many RK4 steps of the batch of 64 independent flows '
+                         'of uneven size (grids 2^8..2^11, chi 16..128, shear layers and '
+                         'random-phase spectra, Re 1e4..1e6, dt = 0.2 / N, float32 convection '
+                         'networks), batched on worker streams against one flow after another; '
+                         'reported under "batch" in flow-steps/s')
+    ap.add_argument('--batch-workers', type=int, default=8)
     ap.add_argument('--calib-copy-mib', type=int, default=0,
                     help='run one device-to-device copy of this many MiB before the timed '
                          'steps (reference dispatch for hardware byte counters)')
@@ -221,7 +240,7 @@ def main():
             state.append(st_)
         args.spinup = 0
     else:
-        u0 = I.decaying_jet(n)
+        u0 = I.decaying_jet(n) if args.field == 'jet' else I.spectrum(n, args.seed, k0=args.k0)
         state = [Q.from_dense(ctx, torch.from_numpy(u0[c]).cuda(), chi, 1e-12, capacity=cap)
                  for c in range(2)]
     log('initial bonds', state[0].bonds, state[1].bonds, f'{time.perf_counter() - t0:.1f}s')
@@ -372,6 +391,85 @@ def main():
             sweep_rule[f'rel_l2_rule_vs_{S_}_sweeps'] = e['field']
             sweep_rule[f'rel_l2_rule_vs_{S_}_sweeps_components'] = e['components']
         log('sweep rule', sweep_rule)
+
+    learned = None
+    if args.learned > 0:
+        Q.precond_config(ctx, args.learned_train, 2e-3, 9, reset=True)
+        prm = prm_for('mixed')
+        prm.precond = Q.PC_LEARNED
+        u = [clone(Q, state[0]), clone(Q, state[1])]
+        cg_total, cg_solves, fb = 0, 0, 0
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.learned):
+            rc, st = Q.rk4_step(ctx, u, prm)
+            cg_total += st['cg_iters_total']
+            cg_solves += st['cg_solves']
+            fb += st['fallbacks']
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t1
+        info = Q.precond_info(ctx)
+        learned = dict(steps=args.learned, steps_per_s=args.learned / el,
+                       cg_iters_per_solve=cg_total / max(cg_solves, 1), fallbacks=fb,
+                       train_per_solve=args.learned_train, probe_loss_first=info['first_loss'],
+                       probe_loss_last=info['last_loss'],
+                       plain_mixed_cg_iters_per_solve=results.get('mixed', {}).get('cg_iters_per_solve'),
+                       plain_f64_steps_per_s=results.get('f64', {}).get('steps_per_s'))
+        if 'f64' in finals and args.learned == args.steps:
+            e = rel_err(Q, ctx, u, finals['f64'], chi)
+            learned['rel_l2_vs_f64'] = e['field']
+            learned['rel_l2_vs_f64_components'] = e['components']
+        Q.precond_config(ctx, 0, 2e-3, 9)
+        log('learned', learned)
+
+    batch = None
+    if args.batch > 0:
+        import numpy as np
+        specs = I.batch_flows()
+        states, prms = [], []
+        for f in specs:
+            nf = f['n']
+            g = (I.shear_layer(nf) if f['kind'] == 'shear' else
+                 I.spectrum(nf, f['seed'], k0=8.0))
+            capf = Q.mps_size(Q.canonical_bonds(nf, f['chi']))
+            states.append([Q.from_dense(ctx, torch.from_numpy(np.ascontiguousarray(g[c])).cuda(),
+                                        f['chi'], 1e-12, capacity=capf) for c in range(2)])
+            prms.append(Q.params(re=f['re'], dt=f['dt'], chi=f['chi'], dx=1.0 / (1 << nf),
+                                 cg_rtol=args.mixed_cg_rtol, cg_maxit=args.cg_maxit,
+                                 max_sweeps=10, sweep_rtol=1e-5, svd_rtol=1e-12,
+                                 prec=Q.PREC_F32))
+        # untimed: one batched step grows every worker's workspace; the timed
+        # runs start from the states after it
+        Q.rk4_step_batched(ctx, states, prms, args.batch_workers)
+        seq = [[clone(Q, x[0]), clone(Q, x[1])] for x in states]
+        for f in range(len(seq)):
+            Q.rk4_step(ctx, seq[f], prms[f])   # untimed: the main context's workspace
+        seq = [[clone(Q, x[0]), clone(Q, x[1])] for x in states]
+        bat = [[clone(Q, x[0]), clone(Q, x[1])] for x in states]
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.batch):
+            for f in range(len(seq)):
+                Q.rk4_step(ctx, seq[f], prms[f])
+        torch.cuda.synchronize()
+        t_seq = time.perf_counter() - t1
+        t1 = time.perf_counter()
+        for _ in range(args.batch):
+            Q.rk4_step_batched(ctx, bat, prms, args.batch_workers)
+        torch.cuda.synchronize()
+        t_bat = time.perf_counter() - t1
+        same = all(bat[f][i].bonds == seq[f][i].bonds and
+                   torch.equal(bat[f][i].data[:bat[f][i].size], seq[f][i].data[:seq[f][i].size])
+                   for f in range(len(seq)) for i in range(2))
+        nfl = len(seq)
+        batch = dict(flows=nfl, steps=args.batch, workers=args.batch_workers,
+                     flow_steps_per_s_batched=nfl * args.batch / t_bat,
+                     flow_steps_per_s_sequential=nfl * args.batch / t_seq,
+                     speedup=t_seq / t_bat, bitwise_equal_to_single_calls=same,
+                     grids=sorted({1 << f['n'] for f in specs}),
+                     chis=sorted({f['chi'] for f in specs}))
+        log('batch', batch)
+        del states, seq, bat
 
     schedules = None
     if args.schedules:
@@ -602,14 +700,16 @@ def main():
         if full is not None:
             cpu['full_step_measured'] = full
 
-    line = dict(metric='RK4 steps/s, 2^11^2 grid chi=128, mixed vs FP64 plain at <=1e-5 rel L2 '
+    field = ('decaying jet' if args.field == 'jet' else
+             f'random-phase spectrum (k0 = {args.k0:g}, seed {args.seed})')
+    line = dict(metric=f'RK4 steps/s, 2^{n}^2 grid chi={chi}, mixed vs FP64 plain at <=1e-5 rel L2 '
                        '(velocity field, one step from the common FP64 state)',
                 value=round(results[main_path]['steps_per_s'], 5), unit='RK4 steps/s',
                 n_gpus=1, steps=args.steps, warmup=args.warmup,
                 ms_per_step=round(1e3 * results[main_path]['seconds'] / args.steps, 2),
                 higher_is_better=True, scaling='weak', vs_baseline=None,
                 dtype='f32' if main_path == 'mixed' else 'f64', data='synthetic',
-                config=dict(workload=f'decaying jet, {1 << n}x{1 << n} grid ({n} sites), '
+                config=dict(workload=f'{field}, {1 << n}x{1 << n} grid ({n} sites), '
                                      f'chi={chi}, Re={args.re:g}, dt={args.dt:g}',
                             spinup_steps=spin, bonds=[state[0].bonds, state[1].bonds],
                             sweeps=(args.sweeps if args.sweeps else
@@ -619,6 +719,10 @@ def main():
                 paths={k: dict(v, **({} if k not in kstats else {})) for k, v in results.items()},
                 rel_l2_mixed_vs_f64=rel, parity=parity, sweep_rule=sweep_rule,
                 roofline=roofline, cpu_baseline=cpu)
+    if learned is not None:
+        line['learned'] = learned
+    if batch is not None:
+        line['batch'] = batch
     if schedules is not None:
         line['schedules'] = schedules
     if explicit is not None:

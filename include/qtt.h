@@ -33,6 +33,7 @@
  *                   shape and keep the faster (results are unchanged)
  *   QTT_TIMING=1    host-timed phase statistics in qtt_stats.phase_ms
  *   QTT_VERBOSE=1   per-call diagnostics on stderr
+ *   QTT_SVD_MAX_SWEEPS=k  outer-sweep cap of the Jacobi SVDs (default 40)
  *
  * Errors
  *   0 = success, > 0 = warning (result valid), < 0 = error (outputs
@@ -56,6 +57,9 @@ enum {
   QTT_W_CG_MAXIT = 1,          /* a local CG solve stopped at cg_maxit          */
   QTT_W_SWEEP_MAXIT = 2,       /* the sweep stopped at max_sweeps (sweep_rtol>0) */
   QTT_W_PRECOND_FALLBACK = 3,  /* the learned preconditioner was rejected        */
+  QTT_W_SVD_MAXIT = 4,         /* a Jacobi SVD of a truncation stopped at its
+                                  sweep cap (QTT_SVD_MAX_SWEEPS, default 40) with
+                                  rotations pending; its factors were used      */
   QTT_E_ARG = -1,
   QTT_E_SHAPE = -2,
   QTT_E_CAPACITY = -3,

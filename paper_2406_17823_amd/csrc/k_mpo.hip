@@ -4,38 +4,18 @@
 // where p runs over the bra and outer-layer bonds and q over the inner-layer
 // and ket bonds.  The finite-difference cores are sparse (12 of 144 entries
 // of the bond-3 derivative core, at most 144 of 1296 of a composed bond-9
-// penalty core), so this is an HBM-streaming step: one thread per output
-// element, which sums the few non-zeros of its output column (compressed
-// columns built on the host once per MPO); q is the fastest index so loads
-// and stores are unit-stride across a wave.
+// penalty core), so this is an HBM-streaming step: each thread owns V
+// consecutive q of one output row (p, w_out m'), sums the few non-zeros of
+// that output column (compressed columns built on the host once per MPO)
+// with V-wide vector loads of the input rows, and stores V outputs; q is the
+// fastest index so loads and stores are unit-stride across a wave.  The row
+// index costs two integer divisions per V elements (the per-element form
+// spent more time in index arithmetic than in memory traffic).
 #include "qtt_internal.h"
 
 namespace qtt {
 
 namespace {
-
-// TS: storage type of the tensors (float64, or float32 for the convection
-// networks of the mixed mode); the sums run in float64
-template <typename TS, typename IT>
-__global__ __launch_bounds__(256) void k_mpo_csc(const TS *T, TS *Tout, const int *colptr,
-                                                 const int *rowidx, const double *val, int KI,
-                                                 int KO, IT post, IT total, const int *skip) {
-  if (skip && *skip) return;
-  // IT: 32-bit index arithmetic whenever the tensor fits (the divisions per
-  // element are the kernel's main ALU cost)
-  for (IT idx = blockIdx.x * (IT)blockDim.x + threadIdx.x; idx < total;
-       idx += (IT)gridDim.x * blockDim.x) {
-    const IT q = idx % post;
-    const IT t = idx / post;
-    const int o = (int)(t % (IT)KO);
-    const IT p = t / (IT)KO;
-    const TS *src = T + (int64_t)p * KI * post + q;
-    double s = 0.0;
-    const int e = colptr[o + 1];
-    for (int z = colptr[o]; z < e; ++z) s += val[z] * (double)src[(int64_t)rowidx[z] * post];
-    Tout[idx] = (TS)s;
-  }
-}
 
 struct MJob {
   const void *T;
@@ -51,8 +31,58 @@ struct MJobs {
   MJob j[4];
 };
 
-// up to four layers (one per job) in one launch; each workgroup serves one
-// job (selected from the block index, so the job's fields are uniform)
+template <typename TS, int V> struct VecOf;
+template <> struct VecOf<float, 4> { typedef float __attribute__((ext_vector_type(4))) type; };
+template <> struct VecOf<double, 2> { typedef double __attribute__((ext_vector_type(2))) type; };
+
+// up to four layers in one launch, V consecutive q per thread (post % V == 0,
+// tensors aligned to V elements, pre * KO * post < 2^31); the same float64
+// sums in the same order as the scalar form, so results are bitwise equal
+template <typename TS, int V>
+__global__ __launch_bounds__(256) void k_mpo_rows_grouped(MJobs J, const int *skip) {
+  if (skip && *skip) return;
+  typedef typename VecOf<TS, V>::type VT;
+  int ji = 0;
+#pragma unroll
+  for (int i = 1; i < 4; ++i)
+    if (i < J.nj && blockIdx.x >= J.j[i].blk0) ji = i;
+  const MJob &M = J.j[ji];
+  const unsigned qv = (unsigned)(M.post / V);
+  const unsigned nvec = (unsigned)(M.total / V);
+  const int KI = M.KI, KO = M.KO;
+  const unsigned post = (unsigned)M.post;
+  const TS *T = static_cast<const TS *>(M.T);
+  TS *Tout = static_cast<TS *>(M.Tout);
+  for (unsigned idx = (blockIdx.x - M.blk0) * 256u + threadIdx.x; idx < nvec;
+       idx += M.nblk * 256u) {
+    const unsigned row = idx / qv;
+    const unsigned qi = idx - row * qv;
+    const unsigned p = row / (unsigned)KO;
+    const int o = (int)(row - p * (unsigned)KO);
+    const TS *src = T + (size_t)p * KI * post + (size_t)qi * V;
+    double s[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) s[v] = 0.0;
+    const int end = M.colptr[o + 1];
+    for (int z = M.colptr[o]; z < end; ++z) {
+      const double w = M.val[z];
+      const VT x = *reinterpret_cast<const VT *>(src + (size_t)M.rowidx[z] * post);
+#pragma unroll
+      for (int v = 0; v < V; ++v) s[v] += w * (double)x[v];
+    }
+    VT y;
+#pragma unroll
+    for (int v = 0; v < V; ++v) y[v] = (TS)s[v];
+    *reinterpret_cast<VT *>(Tout + (size_t)row * post + (size_t)qi * V) = y;
+  }
+}
+
+// scalar form (rows not a multiple of the vector width, unaligned tensors or
+// 64-bit indices): one output element per thread; up to four layers (one
+// per job) in one launch, each workgroup serving one job (selected from the
+// block index, so the job's fields are uniform).  TS: storage type of the
+// tensors (float64, or float32 for the convection networks of the mixed
+// mode); the sums run in float64
 template <typename TS, typename IT>
 __global__ __launch_bounds__(256) void k_mpo_csc_grouped(MJobs J, const int *skip) {
   if (skip && *skip) return;
@@ -86,6 +116,17 @@ void mpo_layer_grouped(Ctx &c, int nj, const MpoJob *jobs, const int *skip, bool
   MJobs J{};
   int64_t blocks = 0, biggest = 0;
   const size_t es = f32 ? sizeof(float) : sizeof(double);
+  // vector width of the row form: every job's rows a multiple of it and its
+  // tensors aligned to it
+  const int V = f32 ? 4 : 2;
+  bool vec = true;
+  for (int i = 0; i < nj; ++i) {
+    const MpoJob &s = jobs[i];
+    if (s.pre <= 0 || s.post <= 0) continue;
+    if (s.post % V || reinterpret_cast<uintptr_t>(s.T) % (V * es) ||
+        reinterpret_cast<uintptr_t>(s.Tout) % (V * es))
+      vec = false;
+  }
   for (int i = 0; i < nj; ++i) {
     const MpoJob &s = jobs[i];
     if (s.pre <= 0 || s.post <= 0) continue;
@@ -104,12 +145,23 @@ void mpo_layer_grouped(Ctx &c, int nj, const MpoJob *jobs, const int *skip, bool
     m.post = s.post;
     m.total = s.pre * KO * s.post;
     m.blk0 = (unsigned)blocks;
-    m.nblk = (unsigned)std::min<int64_t>((m.total + 255) / 256, 32768);
+    const int64_t per = vec ? m.total / V : m.total;
+    m.nblk = (unsigned)std::min<int64_t>((per + 255) / 256, 32768);
     blocks += m.nblk;
-    biggest = std::max(biggest, m.total + (int64_t)m.nblk * 256);
+    biggest = std::max(biggest, m.total + (int64_t)m.nblk * 256 * (vec ? V : 1));
   }
   if (blocks <= 0) return;
   const bool small = biggest < ((int64_t)1 << 31);
+  if (vec && small) {
+    if (f32)
+      hipLaunchKernelGGL((k_mpo_rows_grouped<float, 4>), dim3((unsigned)blocks), dim3(256), 0,
+                         c.stream, J, skip);
+    else
+      hipLaunchKernelGGL((k_mpo_rows_grouped<double, 2>), dim3((unsigned)blocks), dim3(256), 0,
+                         c.stream, J, skip);
+    HIPC(hipGetLastError());
+    return;
+  }
   if (f32 && small)
     hipLaunchKernelGGL((k_mpo_csc_grouped<float, unsigned>), dim3((unsigned)blocks), dim3(256), 0,
                        c.stream, J, skip);
@@ -128,33 +180,8 @@ void mpo_layer_grouped(Ctx &c, int nj, const MpoJob *jobs, const int *skip, bool
 void mpo_layer(Ctx &c, const double *T, double *Tout, const Mpo &W, int site, bool rev,
                int64_t pre, int mi, int mo, int64_t post, const int *skip, bool f32) {
   if (pre <= 0 || post <= 0) return;
-  const int KI = 4 * mi, KO = 4 * mo;
-  const size_t es = f32 ? sizeof(float) : sizeof(double);
-  c.check_range(T, 0, pre * KI * post - 1, es, "mpo_layer in");
-  c.check_range(Tout, 0, pre * KO * post - 1, es, "mpo_layer out");
-  const MpoCsc &z = W.csc[rev ? 1 : 0];
-  const int *cp = z.colptr + z.cp_off[site];
-  const int *ri = z.rowidx + z.nz_off[site];
-  const double *vv = z.val + z.nz_off[site];
-  const int64_t total = pre * KO * post;
-  int64_t g = (total + 255) / 256;
-  if (g > 131072) g = 131072;
-  const bool small = total + (int64_t)g * 256 < ((int64_t)1 << 31);
-  const float *Tf = reinterpret_cast<const float *>(T);
-  float *Tof = reinterpret_cast<float *>(Tout);
-  if (f32 && small)
-    hipLaunchKernelGGL((k_mpo_csc<float, unsigned>), dim3((unsigned)g), dim3(256), 0, c.stream, Tf,
-                       Tof, cp, ri, vv, KI, KO, (unsigned)post, (unsigned)total, skip);
-  else if (f32)
-    hipLaunchKernelGGL((k_mpo_csc<float, int64_t>), dim3((unsigned)g), dim3(256), 0, c.stream, Tf,
-                       Tof, cp, ri, vv, KI, KO, post, total, skip);
-  else if (small)
-    hipLaunchKernelGGL((k_mpo_csc<double, unsigned>), dim3((unsigned)g), dim3(256), 0, c.stream, T,
-                       Tout, cp, ri, vv, KI, KO, (unsigned)post, (unsigned)total, skip);
-  else
-    hipLaunchKernelGGL((k_mpo_csc<double, int64_t>), dim3((unsigned)g), dim3(256), 0, c.stream, T,
-                       Tout, cp, ri, vv, KI, KO, post, total, skip);
-  HIPC(hipGetLastError());
+  const MpoJob j{T, Tout, &W, site, rev, pre, post, mi, mo};
+  mpo_layer_grouped(c, 1, &j, skip, f32);
 }
 
 }  // namespace qtt

@@ -950,7 +950,8 @@ void svd_jacobi_group(Ctx &c, int count, const ConstMatView *A, const MatView *U
     for (int i = 0; i < cnt; ++i)
       if (!B.d[i].single) rounds = std::max(rounds, B.d[i].nb + (B.d[i].nb & 1) - 1);
     int sweeps_run = 0;
-    for (int sweep = 0; sweep < 40; ++sweep) {
+    bool converged = false;
+    for (int sweep = 0; sweep < c.svd_max_sweeps; ++sweep) {
       ++sweeps_run;
       for (int r = 0; r < rounds; ++r) {
         // workgroups of this round per matrix
@@ -986,9 +987,15 @@ void svd_jacobi_group(Ctx &c, int count, const ConstMatView *A, const MatView *U
       c.sync();
       bool done = true;
       for (int i = 0; i < cnt; ++i) done = done && (cnt_host[i] == 0);
-      if (done) break;
+      if (done) {
+        converged = true;
+        break;
+      }
       HIPC(hipMemsetAsync(cnt_dev, 0, cnt * sizeof(int), c.stream));
     }
+    // rotations still pending at the cap: the factors are used as they are
+    // and the call reports QTT_W_SVD_MAXIT
+    if (!converged) c.warn = std::max(c.warn, (int)QTT_W_SVD_MAXIT);
     if (sv_verbose())
       std::fprintf(stderr, "[qtt] svd %dx%d (+%d) sweeps %d rounds/sweep %d gram %d\n", B.d[0].m,
                    B.d[0].n, cnt - 1, sweeps_run, rounds, gram_nc);

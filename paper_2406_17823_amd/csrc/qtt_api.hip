@@ -23,15 +23,17 @@ int guard(qtt_ctx *ctx, F &&f) {
   if (!ctx) return QTT_E_ARG;
   ctx->c.err.clear();
   ctx->c.clear_user();
+  ctx->c.warn = 0;
   try {
     HIPC(hipSetDevice(ctx->c.device));
     if (ctx->c.own_stream) HIPC(hipStreamSynchronize(nullptr));
     f();
-    return QTT_OK;
+    if (ctx->c.warn) ctx->c.err = "warning raised inside the call (see the return code)";
+    return ctx->c.warn;
   } catch (qtt::Error &e) {
     ctx->c.err = e.msg;
     (void)hipGetLastError();
-    if (e.code > 0) return e.code;
+    if (e.code > 0) return std::max(e.code, ctx->c.warn);
     // leave the stream idle before reporting
     hipStreamSynchronize(ctx->c.stream);
     return e.code;
@@ -96,6 +98,8 @@ int qtt_ctx_create(qtt_ctx **out, int device, void *hip_stream) {
   c->c.autotune = (at && at[0] == '1');
   const char *gs = std::getenv("QTT_GEMM_STATS");
   c->c.shape_stats = (gs && gs[0] == '1');
+  const char *sv = std::getenv("QTT_SVD_MAX_SWEEPS");
+  if (sv && std::atoi(sv) > 0) c->c.svd_max_sweeps = std::atoi(sv);
   *out = c;
   return QTT_OK;
 }
@@ -444,6 +448,7 @@ int qtt_rk4_step_batched(qtt_ctx *ctx, int32_t nflows, qtt_mps *u, const qtt_par
         for (int f = w; f < nflows; f += W) {
           wc.err.clear();
           wc.clear_user();
+          wc.warn = 0;
           try {
             reg(wc, u[2 * f]);
             reg(wc, u[2 * f + 1]);
@@ -459,6 +464,7 @@ int qtt_rk4_step_batched(qtt_ctx *ctx, int32_t nflows, qtt_mps *u, const qtt_par
             }
             qtt::to_c(um[0], &u[2 * f]);
             qtt::to_c(um[1], &u[2 * f + 1]);
+            codes[f] = std::max(codes[f], wc.warn);
           } catch (qtt::Error &e) {
             codes[f] = e.code;
             msgs[f] = e.msg;

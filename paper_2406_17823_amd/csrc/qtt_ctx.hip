@@ -146,6 +146,7 @@ std::unique_ptr<Ctx> make_worker(const Ctx &parent) {
   // wide synchronisation); eager CG chunks give the same results
   w->use_graphs = false;
   w->autotune = parent.autotune;
+  w->svd_max_sweeps = parent.svd_max_sweeps;
   return w;
 }
 

@@ -152,6 +152,12 @@ struct Ctx {
   std::map<int, int> cg_hist;
   // per-shape GEMM timing (QTT_GEMM_STATS=1), printed when the context ends
   bool shape_stats = false;
+  // outer sweeps of a Jacobi SVD before it stops with rotations still pending
+  // (QTT_SVD_MAX_SWEEPS, default 40); hitting the cap sets the warning below
+  int svd_max_sweeps = 40;
+  // warning raised below the entry point (QTT_W_SVD_MAXIT); cleared at the
+  // start of every call and returned when the call otherwise succeeds
+  int warn = 0;
   struct ShapeRec {
     int64_t calls = 0;
     double ms = 0.0, flops = 0.0;

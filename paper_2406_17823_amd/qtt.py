@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_HERE, 'libqtt.so')
 
 PREC_F64, PREC_F32, PREC_BF16X3 = 0, 1, 2
 PC_NONE, PC_BLOCK_JACOBI, PC_LEARNED = 0, 1, 2
-W_CG_MAXIT, W_SWEEP_MAXIT, W_PRECOND_FALLBACK = 1, 2, 3
+W_CG_MAXIT, W_SWEEP_MAXIT, W_PRECOND_FALLBACK, W_SVD_MAXIT = 1, 2, 3, 4
 ERRORS = {-1: 'QTT_E_ARG', -2: 'QTT_E_SHAPE', -3: 'QTT_E_CAPACITY', -4: 'QTT_E_HIP',
           -5: 'QTT_E_NAN', -6: 'QTT_E_UNSUPPORTED'}
 

@@ -149,3 +149,40 @@ def test_rk4_chi128_properties(Q, ctx):
     e0 = sum(Q.inner(ctx, x, x) for x in base)
     e1 = sum(Q.inner(ctx, x, x) for x in runs['f64a'])
     assert e1 <= e0 * (1 + 1e-6)
+
+
+def test_rk4_largest_instance_properties(Q, ctx):
+    """8192 x 8192 (13 sites), chi = 256, random-phase spectrum with k0 = 16
+    (seed 5), Re = 1e7, dt = 2e-5: one RK4 step in float64 and with float32
+    convection networks from the same state.  Bonds within min(chi, 4^k,
+    4^(13-k)); the float32 step within 1e-5 relative L2 of the float64 step
+    (velocity field); kinetic energy not growing beyond the time-stepping
+    error."""
+    n, chi = 13, 256
+    dx = 1.0 / (1 << n)
+    u = I.spectrum(n, 5, k0=16.0)
+    cap = Q.mps_size(Q.canonical_bonds(n, chi))
+    base = [Q.from_dense(ctx, torch.from_numpy(np.ascontiguousarray(u[c])).cuda(), chi, 1e-12,
+                         capacity=cap) for c in range(2)]
+    del u
+    runs = {}
+    for tag, prec in (('f64', Q.PREC_F64), ('f32', Q.PREC_F32)):
+        x = [Q.MPS(list(b.bonds), b.data.clone()) for b in base]
+        prm = Q.params(re=1e7, dt=2e-5, chi=chi, dx=dx, cg_rtol=1e-10, max_sweeps=10,
+                       sweep_rtol=1e-5, prec=prec)
+        rc, st = Q.rk4_step(ctx, x, prm)
+        assert rc == 0, rc
+        runs[tag] = x
+    for i in range(2):
+        b = runs['f64'][i].bonds
+        assert all(b[k] <= min(chi, 4 ** k, 4 ** (n - k)) for k in range(1, n))
+    d2 = y2 = 0.0
+    for i in range(2):
+        dd = Q.add(ctx, [1.0, -1.0], [runs['f32'][i], runs['f64'][i]])
+        Q.truncate(ctx, dd, 4 * chi, 0.0)
+        d2 += max(Q.inner(ctx, dd, dd), 0.0)
+        y2 += Q.inner(ctx, runs['f64'][i], runs['f64'][i])
+    assert (d2 / y2) ** 0.5 < 1e-5
+    e0 = sum(Q.inner(ctx, x, x) for x in base)
+    e1 = sum(Q.inner(ctx, x, x) for x in runs['f64'])
+    assert e1 <= e0 * (1 + 1e-6)

@@ -434,3 +434,26 @@ def test_nan_input_rejected(Q, ctx):
     with pytest.raises(Q.QttError) as e:
         Q.project(ctx, a, a, 1e-3, prm, [dev(Q, c.cores()) for c in a])
     assert e.value.code == -5
+
+
+def test_svd_sweep_cap_warns(Q, monkeypatch):
+    """A Jacobi SVD stopped at its sweep cap with rotations pending makes the
+    call return QTT_W_SVD_MAXIT (the cap forced to one sweep from the host);
+    at the default cap the same truncation converges and returns 0."""
+    n = 9   # sum bonds 160 at sites 4, 5: blocked Jacobi with several outer sweeps
+    xs = [rand(I.canonical_bonds(n, 40), 90 + t) for t in range(4)]
+    y = M.add([1.0, 0.3, -0.7, 0.5], xs)
+    monkeypatch.setenv('QTT_SVD_MAX_SWEEPS', '1')
+    capped = Q.Context(0)
+    monkeypatch.delenv('QTT_SVD_MAX_SWEEPS')
+    d = dev(Q, y)
+    Q.truncate(capped, d, 48, 1e-12)
+    assert capped.last_warning == Q.W_SVD_MAXIT
+    capped.close()
+    normal = Q.Context(0)
+    d = dev(Q, y)
+    Q.truncate(normal, d, 48, 1e-12)
+    assert normal.last_warning == 0
+    ref, _ = M.truncate(y, 48, 1e-12)
+    assert M.rel_l2(d.cores(), ref) < TOL
+    normal.close()

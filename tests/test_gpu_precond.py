@@ -100,7 +100,14 @@ def test_pcg_reaches_the_cg_solution(Q):
     ctx.close()
 
 
-def test_training_lowers_loss_and_reports_gain(Q):
+def test_training_lowers_loss_but_not_cg_iterations(Q):
+    """On-line training lowers the probe loss, PCG with the trained network
+    or the exact 4 x 4 block inverse reaches the CG solution, and neither
+    lowers the CG iteration count of a projection (the gain over the method
+    without a preconditioner is negative: the local matrix's spread comes
+    from the coupling of positions and components by the grad-div penalty,
+    which no block-diagonal form captures; the CPU bounds are in
+    test_oracle_precond_bound.py)."""
     n, chi = 7, 32
     ctx = Q.Context(0)
     Q.precond_config(ctx, 4, 2e-3, 9, reset=True)
@@ -130,4 +137,6 @@ def test_training_lowers_loss_and_reports_gain(Q):
             assert M.rel_l2(sols[name][i], sols['none'][i]) < 1e-8
     print('\n[precond] probe loss first %.4g last %.4g; CG iterations %s' %
           (info['first_loss'], info['last_loss'], iters), flush=True)
+    assert iters['block_jacobi'] >= iters['none'], iters
+    assert iters['learned'] > iters['none'], iters
     ctx.close()
