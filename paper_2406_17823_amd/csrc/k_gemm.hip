@@ -72,6 +72,10 @@ struct Prob {
   double alpha, beta;
   double *part;  // partial mode: part[ks][b][m][n]
   int c32;  // result stored as float32 (operand storage is a template argument)
+  // A / B qualify for 16-byte vector loads along their unit-stride dimension:
+  // that dimension's extent, the other strides and the base are multiples of
+  // the vector (so a vector lies wholly inside or wholly outside the operand)
+  int va, vb;
   const double *Bw, *Bs;  // CG operand: B read as B - alpha (Bw + beta Bs)
 };
 
@@ -220,8 +224,10 @@ __device__ inline bf3 to_op<bf3>(double v) {
 // networks of the mixed mode, with T = float); the operand words go through
 // registers in their storage type and are converted on the way into LDS.
 // BCG: B is the next CG residual r - alpha (w + beta s), formed as it loads
+// VEC: every problem's A and B qualify for 16-byte loads (Prob::va, vb): a
+// thread loads whole vectors along each operand's unit-stride dimension
 template <typename T, int BM, int BN, int WGM, int WGN, int KD, typename SA = double,
-          typename SB = double, bool BCG = false>
+          typename SB = double, bool BCG = false, bool VEC = false>
 __global__ __launch_bounds__(64 * WGM * WGN) void k_gemm(GemmK g) {
   if (g.skip && *g.skip) return;
   double cg_a = 0.0, cg_b = 0.0;
@@ -318,7 +324,50 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_gemm(GemmK g) {
   }
   SA ra[AL];
   SB rb[BL];
+  // vector maps: a thread loads VA (VB) consecutive elements along the
+  // unit-stride dimension in AL / VA (BL / VB) slots stepping along the other
+  // one; m (n) unit-stride: thread -> (vector column, k row), k unit-stride:
+  // thread -> (vector along k, m column)
+  constexpr int VA = 16 / sizeof(SA), VB = 16 / sizeof(SB);
+  constexpr int AV = AL / VA, BV = BL / VB;
+  static_assert(!VEC || (AV * VA == AL && BV * VB == BL), "vector slots");
+  static_assert(!VEC || (NTHR % (BM / VA) == 0 && NTHR % (KD / VA) == 0 &&
+                         NTHR % (BN / VB) == 0 && NTHR % (KD / VB) == 0),
+                "vector slot map");
+  typedef SA VecA __attribute__((ext_vector_type(VA)));
+  typedef SB VecB __attribute__((ext_vector_type(VB)));
+  const int va_u = a_m_unit ? (tid % (BM / VA)) * VA : (tid % (KD / VA)) * VA;
+  const int va_o = a_m_unit ? tid / (BM / VA) : tid / (KD / VA);
+  const int va_d = a_m_unit ? NTHR * VA / BM : NTHR * VA / KD;
+  const int vb_u = b_n_unit ? (tid % (BN / VB)) * VB : (tid % (KD / VB)) * VB;
+  const int vb_o = b_n_unit ? tid / (BN / VB) : tid / (KD / VB);
+  const int vb_d = b_n_unit ? NTHR * VB / BN : NTHR * VB / KD;
   auto gload = [&](int k0) {
+    if constexpr (VEC) {
+#pragma unroll
+      for (int i = 0; i < AV; ++i) {
+        const int gm = m0 + (a_m_unit ? va_u : va_o + va_d * i);
+        const int gk = k0 + (a_m_unit ? va_o + va_d * i : va_u);
+        VecA v = VecA(SA(0));
+        if (gm < P.M && gk < kend)
+          v = *reinterpret_cast<const VecA *>(Ap + aoff + (int64_t)gm * P.sAm +
+                                              (int64_t)gk * P.sAk);
+#pragma unroll
+        for (int e = 0; e < VA; ++e) ra[i * VA + e] = v[e];
+      }
+#pragma unroll
+      for (int i = 0; i < BV; ++i) {
+        const int gn = n0 + (b_n_unit ? vb_u : vb_o + vb_d * i);
+        const int gk = k0 + (b_n_unit ? vb_o + vb_d * i : vb_u);
+        VecB v = VecB(SB(0));
+        if (gn < P.N && gk < kend)
+          v = *reinterpret_cast<const VecB *>(Bp + boff + (int64_t)gn * P.sBn +
+                                              (int64_t)gk * P.sBk);
+#pragma unroll
+        for (int e = 0; e < VB; ++e) rb[i * VB + e] = v[e];
+      }
+      return;
+    }
     const int64_t ak = (int64_t)k0 * P.sAk, bk = (int64_t)k0 * P.sBk;
 #pragma unroll
     for (int i = 0; i < AL; ++i) {
@@ -343,6 +392,21 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_gemm(GemmK g) {
     }
   };
   auto sstore = [&](int buf) {
+    if constexpr (VEC) {
+#pragma unroll
+      for (int i = 0; i < AV; ++i)
+#pragma unroll
+        for (int e = 0; e < VA; ++e)
+          As[buf][a_m_unit ? va_o + va_d * i : va_u + e][a_m_unit ? va_u + e : va_o + va_d * i] =
+              to_op<T>((double)ra[i * VA + e]);
+#pragma unroll
+      for (int i = 0; i < BV; ++i)
+#pragma unroll
+        for (int e = 0; e < VB; ++e)
+          Bs[buf][b_n_unit ? vb_o + vb_d * i : vb_u + e][b_n_unit ? vb_u + e : vb_o + vb_d * i] =
+              to_op<T>((double)rb[i * VB + e]);
+      return;
+    }
 #pragma unroll
     for (int i = 0; i < AL; ++i)
       As[buf][a_kk0 + a_dk * i][a_mm0 + a_dm * i] = to_op<T>((double)ra[i]);
@@ -649,6 +713,17 @@ void check_operands(Ctx &c, const Gemm &q) {
 
 // launch of one tile configuration with the operands' storage types (float32
 // storage only with float32 MFMAs; every problem of a launch shares them)
+template <typename T, int BM, int WGM, int WGN, int KD, typename SA = double,
+          typename SB = double>
+void launch_k(bool vec, const dim3 &grid, hipStream_t st, const GemmK &g) {
+  const dim3 blk(64 * WGM * WGN);
+  if (vec)
+    hipLaunchKernelGGL((k_gemm<T, BM, BM, WGM, WGN, KD, SA, SB, false, true>), grid, blk, 0, st, g);
+  else
+    hipLaunchKernelGGL((k_gemm<T, BM, BM, WGM, WGN, KD, SA, SB, false, false>), grid, blk, 0, st,
+                       g);
+}
+
 template <typename T>
 void launch_tile(int MT, int sa, int sb, int64_t blocks, hipStream_t st, const GemmK &g) {
   const dim3 grid((unsigned)blocks);
@@ -659,34 +734,27 @@ void launch_tile(int MT, int sa, int sb, int64_t blocks, hipStream_t st, const G
                        dim3(256), 0, st, g);
     return;
   }
+  // vector loads when every problem of the launch qualifies
+  bool vec = true;
+  for (int i = 0; i < g.np; ++i) vec = vec && g.p[i].va && g.p[i].vb;
   if constexpr (std::is_same<T, float>::value) {
     if (MT == 128) {
-      if (sa && sb)
-        hipLaunchKernelGGL((k_gemm<T, 128, 128, 2, 4, 32, float, float>), grid, dim3(512), 0, st, g);
-      else if (sa)
-        hipLaunchKernelGGL((k_gemm<T, 128, 128, 2, 4, 32, float, double>), grid, dim3(512), 0, st,
-                           g);
-      else if (sb)
-        hipLaunchKernelGGL((k_gemm<T, 128, 128, 2, 4, 32, double, float>), grid, dim3(512), 0, st,
-                           g);
-      else
-        hipLaunchKernelGGL((k_gemm<T, 128, 128, 2, 4, 32>), grid, dim3(512), 0, st, g);
+      if (sa && sb) launch_k<T, 128, 2, 4, 32, float, float>(vec, grid, st, g);
+      else if (sa) launch_k<T, 128, 2, 4, 32, float, double>(vec, grid, st, g);
+      else if (sb) launch_k<T, 128, 2, 4, 32, double, float>(vec, grid, st, g);
+      // (float64 operands into float32 128-tiles: the vector form needs more
+      // than the 128 registers that keep two workgroups per compute unit)
+      else launch_k<T, 128, 2, 4, 32>(false, grid, st, g);
     } else {
-      if (sa && sb)
-        hipLaunchKernelGGL((k_gemm<T, 64, 64, 2, 2, 16, float, float>), grid, dim3(256), 0, st, g);
-      else if (sa)
-        hipLaunchKernelGGL((k_gemm<T, 64, 64, 2, 2, 16, float, double>), grid, dim3(256), 0, st, g);
-      else if (sb)
-        hipLaunchKernelGGL((k_gemm<T, 64, 64, 2, 2, 16, double, float>), grid, dim3(256), 0, st, g);
-      else
-        hipLaunchKernelGGL((k_gemm<T, 64, 64, 2, 2, 16>), grid, dim3(256), 0, st, g);
+      if (sa && sb) launch_k<T, 64, 2, 2, 16, float, float>(vec, grid, st, g);
+      else if (sa) launch_k<T, 64, 2, 2, 16, float, double>(vec, grid, st, g);
+      else if (sb) launch_k<T, 64, 2, 2, 16, double, float>(vec, grid, st, g);
+      else launch_k<T, 64, 2, 2, 16>(vec, grid, st, g);
     }
   } else {
     if (sa || sb) fail(QTT_E_ARG, "gemm: float32 operand storage needs float32 MFMAs");
-    if (MT == 128)
-      hipLaunchKernelGGL((k_gemm<T, 128, 128, 2, 4, 32>), grid, dim3(512), 0, st, g);
-    else
-      hipLaunchKernelGGL((k_gemm<T, 64, 64, 2, 2, 16>), grid, dim3(256), 0, st, g);
+    if (MT == 128) launch_k<T, 128, 2, 4, 32>(vec, grid, st, g);
+    else launch_k<T, 64, 2, 2, 16>(vec, grid, st, g);
   }
 }
 
@@ -814,6 +882,19 @@ void launch_group(Ctx &c, int np, const Gemm *q, int ngroups, const int *group,
       P.beta = s.beta;
       P.part = nullptr;
       P.c32 = s.c32 ? 1 : 0;
+      {
+        // elements of one 16-byte vector in A's and B's storage
+        const int VA = s.a32 ? 4 : 2, VB = s.b32 ? 4 : 2;
+        auto al = [](const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
+        P.va = (al(s.A) && s.sAb1 % VA == 0 && s.sAb2 % VA == 0 &&
+                ((s.sAm == 1 && s.sAk % VA == 0 && s.M % VA == 0) ||
+                 (s.sAm != 1 && s.sAk == 1 && s.sAm % VA == 0 && s.K % VA == 0)))
+                   ? 1 : 0;
+        P.vb = (!s.cgst && al(s.B) && s.sBb1 % VB == 0 && s.sBb2 % VB == 0 &&
+                ((s.sBn == 1 && s.sBk % VB == 0 && s.N % VB == 0) ||
+                 (s.sBn != 1 && s.sBk == 1 && s.sBn % VB == 0 && s.K % VB == 0)))
+                   ? 1 : 0;
+      }
       P.Bw = s.Bw;
       P.Bs = s.Bs;
       g.flops += 2.0 * s.M * (double)s.N * s.K * s.B1 * s.B2;
@@ -903,10 +984,11 @@ void launch_group(Ctx &c, int np, const Gemm *q, int ngroups, const int *group,
     HIPC(hipEventRecord(sev.second, c.stream));
     char key[200];
     const Prob &P = g.p[0];
-    std::snprintf(key, sizeof key, "%s x%d M=%d N=%d K=%d B=%dx%d split=%d t%d %s%s",
+    std::snprintf(key, sizeof key, "%s x%d M=%d N=%d K=%d B=%dx%d split=%d t%d %s%s%s%s",
                   kind == 0 ? "f64" : (kind == 1 ? "f32" : (kind == 2 ? "bf16" : "bf16x3")), g.np,
                   P.M, P.N, P.K, P.B1, P.B2, P.ksplit, MT,
-                  P.sAm == 1 ? "Am" : "Ak", P.sBn == 1 ? "Bn" : "Bk");
+                  P.sAm == 1 ? "Am" : "Ak", P.sBn == 1 ? "Bn" : "Bk", q[0].a32 ? " a32" : "",
+                  q[0].b32 ? " b32" : "");
     c.shape_pending.push_back({key, sev});
     c.shape_flops_pending.push_back(g.flops);
     if (c.shape_pending.size() > 8192) c.resolve_shapes();

@@ -416,9 +416,11 @@ struct Sweep {
     for (Net *N : all) {
       N->eoff.assign(n + 2, 0);
       int64_t o = 0;
+      // every environment starts on a 16-byte boundary (multiples of four
+      // elements), so the GEMMs that read them can take 16-byte vector loads
       for (int b = 0; b <= n; ++b) {
         N->eoff[b] = o;
-        o += env_size(*N, b);
+        o += (env_size(*N, b) + 3) & ~(int64_t)3;
       }
       // float32 storage: sizes in float elements, buffers in doubles
       const bool f = N->f32s();

@@ -5,6 +5,11 @@
         of one benchmark path (the window markers bench.py logs), and the
         fraction of the window in which the GPU ran a kernel;
 
+    python -m paper_2406_17823_amd.tracesum mfma COUNTER_CSV CLOCK_GHZ
+        MFMA busy fraction per kernel family from a counter-collection run with
+        SQ_VALU_MFMA_BUSY_CYCLES and GRBM_GUI_ACTIVE: busy cycles summed over
+        the dispatches / (dispatch durations x clock x 1024 SIMDs);
+
     python -m paper_2406_17823_amd.tracesum bytes FETCH_CSV WRITE_CSV KERNEL COPY_MIB
         HBM bytes per dispatch of KERNEL (a name, or a GEMM family
         'k_gemm<T, BM, BN, WGM, WGN, KD, *>') from two counter-collection runs
@@ -31,10 +36,11 @@ def _short(name):
 
 
 def _family(name):
-    """GEMM instantiations differing only in operand storage types (and the
-    CG-operand flag) form one family, 'k_gemm<T, BM, BN, WGM, WGN, KD, *>'
-    (the library times them as one kind)."""
-    return re.sub(r', (double|float), (double|float)(, (true|false))?>$', ', *>', name)
+    """GEMM instantiations differing only in operand storage types and the
+    CG-operand and vector-load flags form one family,
+    'k_gemm<T, BM, BN, WGM, WGN, KD, *>' (the library times them as one
+    kind)."""
+    return re.sub(r', (double|float), (double|float)(, (true|false))*>$', ', *>', name)
 
 
 def _matches(name, kernel):
@@ -142,10 +148,29 @@ def bytes_per_dispatch(fetch_csv, write_csv, kernel, copy_mib):
     print(f'traffic_bytes_per_dispatch {tb:.6g}')
 
 
+def mfma(counter_csv, clock_ghz):
+    agg = collections.defaultdict(lambda: collections.defaultdict(float))
+    with open(counter_csv) as f:
+        for d in csv.DictReader(f):
+            a = agg[_family(_short(d['Kernel_Name']))]
+            if d['Counter_Name'] == 'GRBM_GUI_ACTIVE':
+                a['dur_ns'] += float(d['End_Timestamp']) - float(d['Start_Timestamp'])
+                a['n'] += 1
+            a[d['Counter_Name']] += float(d['Counter_Value'])
+    print(f'{"MFMA busy":>10} {"dispatches":>10} {"avg us":>8}  kernel family')
+    for k, a in sorted(agg.items(), key=lambda kv: -kv[1].get('SQ_VALU_MFMA_BUSY_CYCLES', 0))[:8]:
+        if not a['dur_ns']:
+            continue
+        util = a['SQ_VALU_MFMA_BUSY_CYCLES'] / (a['dur_ns'] * clock_ghz * 1024)
+        print(f'{100 * util:9.1f}% {int(a["n"]):10d} {a["dur_ns"] / a["n"] / 1e3:8.1f}  {k}')
+
+
 if __name__ == '__main__':
     mode = sys.argv[1]
     if mode == 'window':
         window(sys.argv[2], sys.argv[3], sys.argv[4])
+    elif mode == 'mfma':
+        mfma(sys.argv[2], float(sys.argv[3]))
     elif mode == 'bytes':
         bytes_per_dispatch(sys.argv[2], sys.argv[3], sys.argv[4], int(sys.argv[5]))
     else:
