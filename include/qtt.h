@@ -364,6 +364,14 @@ int qtt_precond_info(qtt_ctx *ctx, int64_t *nparam, int64_t *steps, double *firs
  * W3 [OUT][W], b3 [OUT], row-major, packed in this order) to (set = 0) or
  * from (set = 1) the host array w of n = nparam doubles. */
 int qtt_precond_weights(qtt_ctx *ctx, int32_t set, double *w, int64_t n);
+/* Write the weights to the file `path` / read them back (the host-side
+ * persistence of a trained network): an 8-byte tag "QTTPCNET", four int64
+ * (nparam, QTT_PC_IN, QTT_PC_WIDTH, QTT_PC_OUT), then the nparam float64 of
+ * qtt_precond_weights, host byte order.  A file that cannot be opened or
+ * written, or that is not a weights file of this network, gives QTT_E_ARG
+ * (load leaves the weights unchanged). */
+int qtt_precond_save(qtt_ctx *ctx, const char *path);
+int qtt_precond_load(qtt_ctx *ctx, const char *path);
 /* Network forward and backward on given rows (device pointers): X is
  * npos x QTT_PC_IN, dY and Y are npos x QTT_PC_OUT, grad holds nparam
  * doubles.  Y = network output, grad = gradient of sum(dY * Y) with respect

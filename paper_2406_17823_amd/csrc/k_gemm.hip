@@ -1151,11 +1151,12 @@ void gemm_bf16x3(Ctx &c, const Gemm &g) {
 }
 
 void gemm_grouped(Ctx &c, int np, const Gemm *q, int ngroups, const int *group,
-                  const double *const *X, const int *skip, bool f32, const GemmDot *dot,
+                  const double *const *X, const int *skip, int prec, const GemmDot *dot,
                   const GemmCg *cg) {
   if (np < 1 || np > GEMM_GROUP) fail(QTT_E_ARG, "gemm_grouped: 1..4 problems");
   if (dot && cg) fail(QTT_E_ARG, "gemm_grouped: dot and cg are exclusive");
-  if (f32) launch_group<float>(c, np, q, ngroups, group, X, skip, dot, cg);
+  if (prec == QTT_PREC_F32) launch_group<float>(c, np, q, ngroups, group, X, skip, dot, cg);
+  else if (prec == QTT_PREC_BF16X3) launch_group<bf3>(c, np, q, ngroups, group, X, skip, dot, cg);
   else launch_group<double>(c, np, q, ngroups, group, X, skip, dot, cg);
 }
 

@@ -4,10 +4,12 @@
 #include "qtt_internal.h"
 
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <sstream>
 #include <thread>
+#include <vector>
 
 static_assert(qtt::PC_IN == QTT_PC_IN && qtt::PC_W == QTT_PC_WIDTH && qtt::PC_OUT == QTT_PC_OUT,
               "preconditioner sizes");
@@ -561,6 +563,50 @@ int qtt_precond_weights(qtt_ctx *ctx, int32_t set, double *w, int64_t n) {
     } else {
       HIPC(hipMemcpy(w, c.pc.w, n * sizeof(double), hipMemcpyDeviceToHost));
     }
+  });
+}
+
+// file form of the weights: 8-byte tag, four int64 (nparam, QTT_PC_IN,
+// QTT_PC_WIDTH, QTT_PC_OUT), then nparam float64, host byte order
+static const char PC_TAG[8] = {'Q', 'T', 'T', 'P', 'C', 'N', 'E', 'T'};
+
+int qtt_precond_save(qtt_ctx *ctx, const char *path) {
+  return guard(ctx, [&] {
+    qtt::Ctx &c = ctx->c;
+    qtt::pc_init(c);
+    if (!path) qtt::fail(QTT_E_ARG, "precond_save: null path");
+    std::vector<double> w(c.pc.nparam);
+    c.sync();
+    HIPC(hipMemcpy(w.data(), c.pc.w, w.size() * sizeof(double), hipMemcpyDeviceToHost));
+    std::FILE *f = std::fopen(path, "wb");
+    if (!f) qtt::fail(QTT_E_ARG, std::string("precond_save: cannot open ") + path);
+    const int64_t hdr[4] = {(int64_t)w.size(), QTT_PC_IN, QTT_PC_WIDTH, QTT_PC_OUT};
+    bool ok = std::fwrite(PC_TAG, 1, 8, f) == 8 && std::fwrite(hdr, sizeof(hdr), 1, f) == 1 &&
+              std::fwrite(w.data(), sizeof(double), w.size(), f) == w.size();
+    ok = (std::fclose(f) == 0) && ok;
+    if (!ok) qtt::fail(QTT_E_ARG, std::string("precond_save: write failed: ") + path);
+  });
+}
+
+int qtt_precond_load(qtt_ctx *ctx, const char *path) {
+  return guard(ctx, [&] {
+    qtt::Ctx &c = ctx->c;
+    qtt::pc_init(c);
+    if (!path) qtt::fail(QTT_E_ARG, "precond_load: null path");
+    std::FILE *f = std::fopen(path, "rb");
+    if (!f) qtt::fail(QTT_E_ARG, std::string("precond_load: cannot open ") + path);
+    char tag[8];
+    int64_t hdr[4];
+    std::vector<double> w(c.pc.nparam);
+    const bool ok = std::fread(tag, 1, 8, f) == 8 && std::memcmp(tag, PC_TAG, 8) == 0 &&
+                    std::fread(hdr, sizeof(hdr), 1, f) == 1 && hdr[0] == (int64_t)w.size() &&
+                    hdr[1] == QTT_PC_IN && hdr[2] == QTT_PC_WIDTH && hdr[3] == QTT_PC_OUT &&
+                    std::fread(w.data(), sizeof(double), w.size(), f) == w.size() &&
+                    std::fgetc(f) == EOF;
+    std::fclose(f);
+    if (!ok) qtt::fail(QTT_E_ARG, std::string("precond_load: not a weights file of this network: ") + path);
+    c.sync();
+    HIPC(hipMemcpy(c.pc.w, w.data(), w.size() * sizeof(double), hipMemcpyHostToDevice));
   });
 }
 

@@ -271,8 +271,10 @@ struct GemmCg {
   double *part;
   int nparts;
 };
+// prec: QTT_PREC_F64, QTT_PREC_F32 (float32 MFMAs) or QTT_PREC_BF16X3 (split
+// bfloat16 MFMAs) for every problem of the launch
 void gemm_grouped(Ctx &c, int np, const Gemm *q, int ngroups, const int *group,
-                  const double *const *X, const int *skip, bool f32,
+                  const double *const *X, const int *skip, int prec,
                   const GemmDot *dot = nullptr, const GemmCg *cg = nullptr);
 // float32-MFMA variant with float64 inputs/outputs (mixed precision mode)
 void gemm_f32(Ctx &c, const Gemm &g);

@@ -90,8 +90,6 @@ struct Sweep {
   std::vector<Net> pen;   // penalty networks, index 2*i + j
   double mu_h2;
   bool fit = false;       // fit of B(b): the local solution is the right-hand side
-  double *tmp = nullptr, *Tpen = nullptr;
-  int64_t tmp_size = 0;
   CGState *st = nullptr;
   CGState *st_host = nullptr;
   double *part = nullptr;
@@ -126,12 +124,6 @@ struct Sweep {
       }
     }
     return mx;
-  }
-
-  void gemm_for(const Net &N, const Gemm &g) {
-    if (N.prec == QTT_PREC_F32) gemm_f32(c, g);
-    else if (N.prec == QTT_PREC_BF16X3) gemm_bf16x3(c, g);
-    else gemm(c, g);
   }
 
   // one step of a network chain: a GEMM or an MPO layer
@@ -220,21 +212,6 @@ struct Sweep {
     return ns;
   }
 
-  // T = chain through site d from the environment at the input bond
-  void chain(const Net &N, int d, bool rev, const double *E, const double *ketcore, double *T,
-             const int *skip) {
-    ChainStep steps[3];
-    const int ns = chain_plan(N, d, rev, E, ketcore, T, tmp, skip, steps);
-    for (int t = 0; t < ns; ++t) {
-      const ChainStep &st = steps[t];
-      if (st.mpo)
-        mpo_layer(c, st.j.T, st.j.Tout, *st.j.W, st.j.site, st.j.rev, st.j.pre, st.j.mi, st.j.mo,
-                  st.j.post, skip, N.f32s());
-      else
-        gemm_for(N, st.g);
-    }
-  }
-
   // out_i += alpha * (T contracted with the opposite environment)
   Gemm open_gemm(const Net &N, int d, bool rev, const double *T, double *out, double alpha) {
     const int al = v[N.bra].bond[d], ar = v[N.bra].bond[d + 1];
@@ -279,10 +256,6 @@ struct Sweep {
     return q;
   }
 
-  void open_into(const Net &N, int d, bool rev, const double *T, double *out, double alpha) {
-    gemm_for(N, open_gemm(N, d, rev, T, out, alpha));
-  }
-
   // environment at the output bond from T and the (new) bra core of site d
   Gemm env_gemm(const Net &N, int d, bool rev, const double *T) {
     const int al = v[N.bra].bond[d], ar = v[N.bra].bond[d + 1];
@@ -314,18 +287,13 @@ struct Sweep {
     return q;
   }
 
-  void env_from_T(const Net &N, int d, bool rev, const double *T) {
-    gemm_for(N, env_gemm(N, d, rev, T));
-  }
-
   // ---- grouped network contractions: the networks of one group share a
-  // contraction precision (float64 or float32 MFMA) and each step of their
-  // chains, their environment updates and their right-hand-side terms go
-  // out as one grouped launch for the whole group (the GEMMs of a step can
-  // have different shapes; MPO layers of a step share one launch)
-  static bool groupable(const Net &N) { return N.prec != QTT_PREC_BF16X3; }
+  // contraction precision (float64, float32 or split bfloat16 MFMA) and each
+  // step of their chains, their environment updates and their right-hand-
+  // side terms go out as one grouped launch for the whole group (the GEMMs of
+  // a step can have different shapes; MPO layers of a step share one launch)
 
-  void launch_gemms(int cnt, Gemm *q, bool f32, bool sum_outputs) {
+  void launch_gemms(int cnt, Gemm *q, int prec, bool sum_outputs) {
     int grp[GEMM_GROUP];
     const double *C[GEMM_GROUP];
     const double *X[GEMM_GROUP] = {nullptr, nullptr, nullptr, nullptr};
@@ -341,7 +309,7 @@ struct Sweep {
       }
       grp[k] = gi;
     }
-    gemm_grouped(c, cnt, q, ng, grp, X, nullptr, f32);
+    gemm_grouped(c, cnt, q, ng, grp, X, nullptr, prec);
   }
 
   // chains of the group's networks; E[k] is network k's input environment,
@@ -365,7 +333,7 @@ struct Sweep {
         if (steps[k][t].mpo) j[nj++] = steps[k][t].j;
         else q[nq++] = steps[k][t].g;
       }
-      if (nq) launch_gemms(nq, q, f32, false);
+      if (nq) launch_gemms(nq, q, Ns[0]->prec, false);
       if (nj) mpo_layer_grouped(c, nj, j, nullptr, f32);
     }
   }
@@ -373,7 +341,7 @@ struct Sweep {
   void env_group(int cnt, Net *const *Ns, int d, bool rev, double *const *T) {
     Gemm q[GEMM_GROUP];
     for (int k = 0; k < cnt; ++k) q[k] = env_gemm(*Ns[k], d, rev, T[k]);
-    launch_gemms(cnt, q, Ns[0]->f32s(), false);
+    launch_gemms(cnt, q, Ns[0]->prec, false);
   }
 
   // groups of up to GEMM_GROUP networks of one precision, in list order
@@ -381,11 +349,7 @@ struct Sweep {
     std::vector<std::vector<Net *>> out;
     std::vector<Net *> open[3];
     for (Net *N : nets) {
-      if (!groupable(*N)) {
-        out.push_back({N});
-        continue;
-      }
-      auto &o = open[N->prec == QTT_PREC_F32 ? 1 : 0];
+      auto &o = open[N->prec == QTT_PREC_F32 ? 1 : (N->prec == QTT_PREC_BF16X3 ? 2 : 0)];
       o.push_back(N);
       if ((int)o.size() == GEMM_GROUP) {
         out.push_back(o);
@@ -411,7 +375,6 @@ struct Sweep {
   // environments and chain buffers live in context buffers that persist
   // across calls (no allocation once the largest shapes have been seen)
   void alloc(std::vector<Net *> all) {
-    int64_t tmx = 1;
     int idx = 0;
     for (Net *N : all) {
       N->eoff.assign(n + 2, 0);
@@ -434,15 +397,10 @@ struct Sweep {
       }
       int64_t own = 1;
       for (int d = 0; d < n; ++d) own = std::max(own, chain_max(*N, d));
-      tmx = std::max(tmx, own);
       N->T = c.buf("sw_T" + std::to_string(idx), f ? (own + 1) / 2 : own);
-      if (groupable(*N))
-        N->tmpn = c.buf("sw_Tb" + std::to_string(idx), f ? (own + 1) / 2 : own);
+      N->tmpn = c.buf("sw_Tb" + std::to_string(idx), f ? (own + 1) / 2 : own);
       ++idx;
     }
-    tmp = c.buf("sw_tmp", tmx);
-    Tpen = c.buf("sw_Tpen", tmx);
-    tmp_size = tmx;
   }
 
   int64_t centre_size(int i, int d) const { return v[i].core_size(d); }
@@ -525,7 +483,7 @@ struct Sweep {
       o.beta = 1.0;
       ogrp[k] = i;
     }
-    gemm_grouped(c, 4, kg, 4, kgrp, kX, skip, false);
+    gemm_grouped(c, 4, kg, 4, kgrp, kX, skip, QTT_PREC_F64);
     mpo_layer_grouped(c, 4, mj, skip);
     if (dot) {
       GemmDot gd{};
@@ -535,9 +493,9 @@ struct Sweep {
       gd.ctr = &st->counter;
       gd.part = dpart;
       gd.nparts = DPART;
-      gemm_grouped(c, 4, og, 2, ogrp, oX, skip, false, &gd);
+      gemm_grouped(c, 4, og, 2, ogrp, oX, skip, QTT_PREC_F64, &gd);
     } else {
-      gemm_grouped(c, 4, og, 2, ogrp, oX, skip, false, nullptr, cg);
+      gemm_grouped(c, 4, og, 2, ogrp, oX, skip, QTT_PREC_F64, nullptr, cg);
     }
   }
   static constexpr int DPART = 1024;
@@ -577,8 +535,6 @@ struct Sweep {
     add(dpart);
     add(st);
     add(part);
-    add(tmp);
-    add(Tpen);
     add(c.kt.flop_ctr);
     for (const Net &N : pen) {
       add(N.env + N.eoff[d]);
@@ -764,14 +720,6 @@ struct Sweep {
     auto t0 = std::chrono::steady_clock::now();
     for (auto &grp : rhs_groups) {
       const int cnt = (int)grp.size();
-      if (!groupable(*grp[0])) {
-        for (Net *N : grp) {
-          const double *E = rev ? N->envp(d + 1) : N->envp(d);
-          chain(*N, d, rev, E, ket_core(*N, d, rev), N->T, nullptr);
-          open_into(*N, d, rev, N->T, rh[N->bra], N->coef);
-        }
-        continue;
-      }
       const double *E[GEMM_GROUP];
       double *T[GEMM_GROUP], *tm[GEMM_GROUP];
       Gemm q[GEMM_GROUP];
@@ -784,7 +732,7 @@ struct Sweep {
       // the terms of one component are summed in the reduction of one launch
       for (int k = 0; k < cnt; ++k)
         q[k] = open_gemm(*grp[k], d, rev, grp[k]->T, rh[grp[k]->bra], grp[k]->coef);
-      launch_gemms(cnt, q, grp[0]->f32s(), true);
+      launch_gemms(cnt, q, grp[0]->prec, true);
     }
     if (fit) {
       // identity local matrix: the centres are the projected right-hand side
@@ -935,7 +883,7 @@ struct Sweep {
     {
       const int grp[2] = {0, 1};
       const double *X[2] = {nullptr, nullptr};
-      gemm_grouped(c, 2, g, 2, grp, X, nullptr, false);
+      gemm_grouped(c, 2, g, 2, grp, X, nullptr, QTT_PREC_F64);
     }
     {
       const double *const src[2] = {Tb + doff[0], Tb + doff[1]};
@@ -950,10 +898,6 @@ struct Sweep {
   // change), the penalty networks contract the new trial cores
   void update_envs(int d, bool rev) {
     for (auto &grp : rhs_groups) {
-      if (!groupable(*grp[0])) {
-        for (Net *N : grp) env_from_T(*N, d, rev, N->T);
-        continue;
-      }
       double *T[GEMM_GROUP];
       for (size_t k = 0; k < grp.size(); ++k) T[k] = grp[k]->T;
       env_group((int)grp.size(), grp.data(), d, rev, T);
@@ -965,14 +909,6 @@ struct Sweep {
   // d, from the environment at the input bond
   void envs_through(std::vector<Net *> &grp, int d, bool rev) {
     const int cnt = (int)grp.size();
-    if (!groupable(*grp[0])) {
-      for (Net *N : grp) {
-        const double *E = rev ? N->envp(d + 1) : N->envp(d);
-        chain(*N, d, rev, E, ket_core(*N, d, rev), Tpen, nullptr);
-        env_from_T(*N, d, rev, Tpen);
-      }
-      return;
-    }
     const double *E[GEMM_GROUP];
     double *T[GEMM_GROUP], *tm[GEMM_GROUP];
     for (int k = 0; k < cnt; ++k) {

@@ -64,7 +64,7 @@ SYMBOLS = ['qtt_kernel_timing', 'qtt_kernel_stats_read', 'qtt_ctx_create', 'qtt_
            'qtt_precond_config', 'qtt_precond_info', 'qtt_precond_weights', 'qtt_precond_grad',
            'qtt_rk4_step_batched', 'qtt_rk_step', 'qtt_schmidt_counts', 'qtt_dns_rhs',
            'qtt_dns_project', 'qtt_dns_step', 'qtt_fidelity', 'qtt_tke_shells', 'qtt_tke_spectrum',
-           'qtt_inner_noalloc']
+           'qtt_inner_noalloc', 'qtt_precond_save', 'qtt_precond_load']
 
 _lib = None
 
@@ -110,6 +110,8 @@ def lib():
         'qtt_precond_config': (I32, [P, I32, D, ctypes.c_uint64, I32]),
         'qtt_precond_info': (I32, [P, ctypes.POINTER(I64), ctypes.POINTER(I64), pd, pd]),
         'qtt_precond_weights': (I32, [P, I32, pd, I64]),
+        'qtt_precond_save': (I32, [P, ctypes.c_char_p]),
+        'qtt_precond_load': (I32, [P, ctypes.c_char_p]),
         'qtt_precond_grad': (I32, [P, P, I64, P, P, P]),
         'qtt_rk4_step_batched': (I32, [P, I32, pm, ctypes.POINTER(c_params),
                                        ctypes.POINTER(c_stats), I32]),
@@ -518,6 +520,14 @@ def precond_weights(ctx, w=None):
     ctx.check(lib().qtt_precond_weights(ctx.h, 1, w.ctypes.data_as(
         ctypes.POINTER(ctypes.c_double)), w.size), 'precond_weights')
     return w
+
+
+def precond_save(ctx, path):
+    ctx.check(lib().qtt_precond_save(ctx.h, os.fsencode(path)), 'precond_save')
+
+
+def precond_load(ctx, path):
+    ctx.check(lib().qtt_precond_load(ctx.h, os.fsencode(path)), 'precond_load')
 
 
 def precond_grad(ctx, X, dY):

@@ -140,3 +140,27 @@ def test_training_lowers_loss_but_not_cg_iterations(Q):
     assert iters['block_jacobi'] >= iters['none'], iters
     assert iters['learned'] > iters['none'], iters
     ctx.close()
+
+
+def test_weights_save_and_load(Q, tmp_path):
+    """Weights written to a file come back bitwise into a context whose
+    network was drawn from another seed; a file of another form is refused
+    and leaves the weights unchanged."""
+    a = Q.Context(0)
+    Q.precond_config(a, 0, 1e-3, 11, reset=True)
+    w = Q.precond_weights(a)
+    path = str(tmp_path / 'net.bin')
+    Q.precond_save(a, path)
+    b = Q.Context(0)
+    Q.precond_config(b, 0, 1e-3, 12, reset=True)
+    assert not np.array_equal(Q.precond_weights(b), w)
+    Q.precond_load(b, path)
+    assert np.array_equal(Q.precond_weights(b), w)
+    bad = tmp_path / 'bad.bin'
+    bad.write_bytes(b'QTTPCNET' + b'\0' * 40)
+    with pytest.raises(Q.QttError) as e:
+        Q.precond_load(b, str(bad))
+    assert e.value.code == -1
+    assert np.array_equal(Q.precond_weights(b), w)
+    a.close()
+    b.close()
