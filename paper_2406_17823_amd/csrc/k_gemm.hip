@@ -18,10 +18,11 @@
 // loader picks the thread-to-element map from the operand's unit-stride
 // dimension so that global loads stay coalesced.
 // float64: v_mfma_f64_16x16x4_f64; float32: v_mfma_f32_16x16x4_f32 with
-// float64 operands rounded to float32 on the way into LDS (float64 sums of
-// the float32 16-deep slices); bfloat16: v_mfma_f32_16x16x16_bf16;
+// float64 operands rounded to float32 on the way into LDS and float32
+// accumulation over the tile's K range; bfloat16: v_mfma_f32_16x16x16_bf16;
 // compensated split bfloat16 (each operand as hi + lo bfloat16, three MFMAs
-// per block dropping lo*lo, float32 within a slice, float64 across slices).
+// per block dropping lo*lo, float32 accumulation over the tile's K range).
+// Split-K partial tiles are summed in float64.
 // When the output tiles cannot fill the 256 compute units, K is split across
 // workgroups; the partial tiles are summed in split order by a second kernel
 // (deterministic).  That kernel also sums several problems into one output
@@ -50,11 +51,12 @@ template <> struct GemmKind<float> { static constexpr int value = 1; };
 template <> struct GemmKind<__bf16> { static constexpr int value = 2; };
 template <> struct GemmKind<bf3> { static constexpr int value = 3; };
 
-// accumulator of a 16 x 16 MFMA block: float32 for float32 MFMAs, float64
-// otherwise (bfloat16 products are summed in float32 per 16-deep step and in
-// float64 across steps)
+// accumulator of a 16 x 16 MFMA block: float32 for the float32 and split
+// bfloat16 MFMAs, float64 otherwise (plain bfloat16 products are summed in
+// float32 per 16-deep step and in float64 across steps)
 template <typename T> struct AccOf { typedef d4v type; };
 template <> struct AccOf<float> { typedef f4v type; };
+template <> struct AccOf<bf3> { typedef f4v type; };
 
 namespace {
 
@@ -165,10 +167,12 @@ struct Mfma<__bf16, FM, FN, LD> {
 };
 
 // compensated split bfloat16: three v_mfma_f32_16x16x16_bf16 per block
+// (lo*hi, hi*lo, then hi*hi), accumulated in float32 over the whole K range
+// of the tile like the float32 MFMAs
 template <int FM, int FN, int LD>
 struct Mfma<bf3, FM, FN, LD> {
   __device__ static void step(const bf3 (*As)[LD], const bf3 (*Bs)[LD], int lane, int m0, int n0,
-                              d4v (&acc)[FM][FN]) {
+                              f4v (&acc)[FM][FN]) {
     b4v ah[FM], al[FM], bh[FN], bl[FN];
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
@@ -190,12 +194,9 @@ struct Mfma<bf3, FM, FN, LD> {
     for (int i = 0; i < FM; ++i)
 #pragma unroll
       for (int j = 0; j < FN; ++j) {
-        f4v f = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al[i], bh[j], f4v{0.f, 0.f, 0.f, 0.f},
-                                                          0, 0, 0);
-        f = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[i], bl[j], f, 0, 0, 0);
-        f = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[i], bh[j], f, 0, 0, 0);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) acc[i][j][r] += (double)f[r];
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al[i], bh[j], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[i], bl[j], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[i], bh[j], acc[i][j], 0, 0, 0);
       }
   }
 };
@@ -751,8 +752,25 @@ void launch_tile(int MT, int sa, int sb, int64_t blocks, hipStream_t st, const G
       else if (sb) launch_k<T, 64, 2, 2, 16, double, float>(vec, grid, st, g);
       else launch_k<T, 64, 2, 2, 16>(vec, grid, st, g);
     }
+  } else if constexpr (std::is_same<T, bf3>::value) {
+    // split bfloat16: float32 or float64 operand storage (float32 for the
+    // convection networks, whose environments and chains are stored in float32)
+    // 128 x 128 tiles on 2 x 2 waves (64 x 64 per wave): each operand value
+    // read from LDS feeds four blocks, which keeps the three-MFMA step from
+    // being bound by LDS reads
+    if (MT == 128) {
+      if (sa && sb) launch_k<T, 128, 2, 2, 32, float, float>(vec, grid, st, g);
+      else if (sa) launch_k<T, 128, 2, 2, 32, float, double>(vec, grid, st, g);
+      else if (sb) launch_k<T, 128, 2, 2, 32, double, float>(vec, grid, st, g);
+      else launch_k<T, 128, 2, 2, 32>(vec, grid, st, g);
+    } else {
+      if (sa && sb) launch_k<T, 64, 2, 2, 16, float, float>(vec, grid, st, g);
+      else if (sa) launch_k<T, 64, 2, 2, 16, float, double>(vec, grid, st, g);
+      else if (sb) launch_k<T, 64, 2, 2, 16, double, float>(vec, grid, st, g);
+      else launch_k<T, 64, 2, 2, 16>(vec, grid, st, g);
+    }
   } else {
-    if (sa || sb) fail(QTT_E_ARG, "gemm: float32 operand storage needs float32 MFMAs");
+    if (sa || sb) fail(QTT_E_ARG, "gemm: float32 operand storage needs float32 or split bfloat16 MFMAs");
     if (MT == 128) launch_k<T, 128, 2, 4, 32>(vec, grid, st, g);
     else launch_k<T, 64, 2, 2, 16>(vec, grid, st, g);
   }

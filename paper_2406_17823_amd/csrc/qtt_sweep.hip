@@ -70,10 +70,11 @@ struct Net {
   std::vector<int64_t> eoff;
   double *T = nullptr;
   double *tmpn = nullptr;  // the other half of T's ping-pong pair (grouped chains)
-  // float32-MFMA networks keep their environments and chain intermediates in
-  // float32 storage (half the bytes of the largest tensors of the step); env
-  // and T then point at float arrays and eoff counts float elements
-  bool f32s() const { return prec == QTT_PREC_F32; }
+  // float32-MFMA and split-bfloat16 networks keep their environments and
+  // chain intermediates in float32 storage (half the bytes of the largest
+  // tensors of the step); env and T then point at float arrays and eoff
+  // counts float elements
+  bool f32s() const { return prec == QTT_PREC_F32 || prec == QTT_PREC_BF16X3; }
   double *envp(int b) const {
     return f32s() ? reinterpret_cast<double *>(reinterpret_cast<float *>(env) + eoff[b])
                   : env + eoff[b];
