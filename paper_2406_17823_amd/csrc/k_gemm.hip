@@ -16,7 +16,11 @@
 // slice suffices, and the deeper slice gives the loads of the large tiles
 // twice the MFMA time to arrive.  The
 // loader picks the thread-to-element map from the operand's unit-stride
-// dimension so that global loads stay coalesced.
+// dimension so that global loads stay coalesced.  float32 slices are laid
+// out for vector fragment reads (each lane reads its operands of all the
+// wave's MFMA blocks in one 8- or 16-byte LDS read) with row offsets that
+// keep the reads and the transposed stores free of bank conflicts; the
+// other types read one element per block from rows padded by one element.
 // float64: v_mfma_f64_16x16x4_f64; float32: v_mfma_f32_16x16x4_f32 with
 // float64 operands rounded to float32 on the way into LDS and float32
 // accumulation over the tile's K range; bfloat16: v_mfma_f32_16x16x16_bf16;
@@ -115,21 +119,63 @@ struct Mfma<double, FM, FN, LD> {
   }
 };
 
+// float32 and split-bfloat16 operand slices (4-byte elements) in LDS are
+// read as vector fragments: lane l supplies the V = FM (or FN) consecutive
+// columns V (l % 16) .. V (l % 16) + V - 1 of a row, one per MFMA block
+// (block i takes wave-tile row V r + i as its row r), in one 8- or 16-byte
+// LDS read.  Row k starts at word (k / 2) PP + (k % 2) PO:
+//   V = 4: PO = W + 4, PP = 2 PO (rows padded by 4 words): a 16-byte read of
+//          16 lanes covers one row, and the transposed stores of a
+//          k-contiguous operand (consecutive threads, consecutive rows) spread
+//          over the banks;
+//   V = 2: the 8-byte reads of 32 lanes take two rows, k and k + KS (KS = 1
+//          for the float32 MFMA, whose lane groups step one row; 4 for the
+//          bfloat16 MFMA, whose lane groups step four): PO = 32 and PP = 2
+//          modulo 64 banks (KS = 1), or PO = 8 and PP = 16 (KS = 4), put the
+//          two rows on the two bank halves, and the rows of a transposed store
+//          on different banks (two to a bank at most).
+// Other element types: rows of W + 1 elements (PO = W + 1, PP = 2 PO).
+// The row part of an access is a per-lane row plus an even compile-time row
+// step (or an even per-lane row plus a compile-time one), which adds a
+// compile-time word offset.
+template <int W, int V, bool FRAG, int KS = 1>
+struct Lay {
+  static constexpr int up(int x, int r) { return (x - r + 63) / 64 * 64 + r; }  // >= x, = r mod 64
+  static constexpr int PO = !FRAG ? W + 1 : V == 4 ? W + 4 : up(W, KS == 1 ? 32 : 8);
+  static constexpr int PP = !FRAG || V == 4 ? 2 * PO : up(PO + W, KS == 1 ? 2 : 16);
+  static_assert(!FRAG || V == 2 || V == 4, "fragments of two or four elements");
+  static_assert(KS == 1 || KS == 4, "row step of the MFMA lane groups");
+  static_assert(PO >= W && PP >= PO + W, "rows do not overlap");
+  __device__ __forceinline__ static int row(int k) { return (k >> 1) * PP + (k & 1) * PO; }
+  static constexpr int words(int kd) { return (kd / 2) * PP; }
+};
+
+template <int V>
+__device__ __forceinline__ void frag_load(const float *p, float (&v)[V]) {
+  typedef float fv __attribute__((ext_vector_type(V)));
+  const fv x = *reinterpret_cast<const fv *>(p);
+#pragma unroll
+  for (int e = 0; e < V; ++e) v[e] = x[e];
+}
+
 // float32: the accumulators stay float32 over the whole K range of the
 // tile (float32 accumulation, as the mixed mode prescribes); split-K
-// partials are summed in float64 by the reduction kernel
-template <int FM, int FN, int LD>
-struct Mfma<float, FM, FN, LD> {
-  __device__ static void step(const float (*As)[LD], const float (*Bs)[LD], int lane, int m0,
-                              int n0, f4v (&acc)[FM][FN]) {
+// partials are summed in float64 by the reduction kernel.  As, Bs: the
+// slice buffers; kb: the first slice row of this step
+template <int FM, int FN, int BM, int BN>
+struct MfmaF32 {
+  typedef Lay<BM, FM, true> LA;
+  typedef Lay<BN, FN, true> LB;
+  __device__ static void step(const float *As, const float *Bs, int lane, int m0, int n0, int kb,
+                              f4v (&acc)[FM][FN]) {
+    // lane terms: row lane / 16 of each group of four, the lane's columns
+    const float *ap = As + LA::row(lane >> 4) + m0 + FM * (lane & 15);
+    const float *bp = Bs + LB::row(lane >> 4) + n0 + FN * (lane & 15);
 #pragma unroll
     for (int kq = 0; kq < KT / 4; ++kq) {
-      const int kk = kq * 4 + (lane >> 4);
       float a[FM], b[FN];
-#pragma unroll
-      for (int i = 0; i < FM; ++i) a[i] = As[kk][m0 + i * 16 + (lane & 15)];
-#pragma unroll
-      for (int j = 0; j < FN; ++j) b[j] = Bs[kk][n0 + j * 16 + (lane & 15)];
+      frag_load<FM>(ap + ((kb + kq * 4) >> 1) * LA::PP, a);
+      frag_load<FN>(bp + ((kb + kq * 4) >> 1) * LB::PP, b);
 #pragma unroll
       for (int i = 0; i < FM; ++i)
 #pragma unroll
@@ -201,6 +247,46 @@ struct Mfma<bf3, FM, FN, LD> {
   }
 };
 
+// split bfloat16 from fragments: lane l takes rows 4 (l / 16) + e, e = 0..3,
+// of the 16-row step, each as one fragment of V bf3 words
+template <int FM, int FN, int BM, int BN>
+struct MfmaBf3F {
+  typedef Lay<BM, FM, true, 4> LA;
+  typedef Lay<BN, FN, true, 4> LB;
+  template <int V>
+  __device__ static void frag(const bf3 *p, b4v (&h)[V], b4v (&l)[V], int e) {
+    typedef unsigned uv __attribute__((ext_vector_type(V)));
+    const uv x = *reinterpret_cast<const uv *>(p);
+#pragma unroll
+    for (int i = 0; i < V; ++i) {
+      const bf3 v = __builtin_bit_cast(bf3, (unsigned)x[i]);
+      h[i][e] = v.hi;
+      l[i][e] = v.lo;
+    }
+  }
+  __device__ static void step(const bf3 *As, const bf3 *Bs, int lane, int m0, int n0, int kb,
+                              f4v (&acc)[FM][FN]) {
+    // row kb + 4 q + e: (kb / 2 + 2 q) PP + row(e), kb + 4 q even
+    const int q = lane >> 4;
+    const bf3 *ap = As + (kb / 2 + 2 * q) * LA::PP + m0 + FM * (lane & 15);
+    const bf3 *bp = Bs + (kb / 2 + 2 * q) * LB::PP + n0 + FN * (lane & 15);
+    b4v ah[FM], al[FM], bh[FN], bl[FN];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      frag<FM>(ap + LA::row(e), ah, al, e);
+      frag<FN>(bp + LB::row(e), bh, bl, e);
+    }
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j) {
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al[i], bh[j], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[i], bl[j], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[i], bh[j], acc[i][j], 0, 0, 0);
+      }
+  }
+};
+
 template <typename T>
 __device__ inline T to_op(double v) {
   return (T)v;
@@ -247,9 +333,17 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_gemm(GemmK g) {
   static_assert(BM == BN, "square tiles: the MFMA step takes one LDS pitch");
   static_assert(KD % KT == 0, "slices of whole MFMA steps");
   static_assert(AL * NTHR == BM * KD && BL * NTHR == BN * KD, "tile / thread mismatch");
+  // float32: the fragment layout above; other types: rows padded by one
+  // element, read element-wise
+  constexpr bool BF3 = std::is_same<T, bf3>::value;
+  constexpr bool FRAG = std::is_same<T, float>::value || BF3;
+  constexpr int VFA = BM / WGM / 16, VFB = BN / WGN / 16;  // fragment lengths
   constexpr int LDA = BM + PADM, LDB = BN + PADM;
-  __shared__ T As[2][KD][LDA];
-  __shared__ T Bs[2][KD][LDB];
+  typedef Lay<BM, VFA, FRAG, BF3 ? 4 : 1> LA;
+  typedef Lay<BN, VFB, FRAG, BF3 ? 4 : 1> LB;
+  static_assert(FRAG || (LA::PO == LDA && LB::PO == LDB), "padded rows of the element-wise types");
+  __shared__ __align__(16) T As[2][LA::words(KD)];
+  __shared__ __align__(16) T Bs[2][LB::words(KD)];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -343,6 +437,19 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_gemm(GemmK g) {
   const int vb_u = b_n_unit ? (tid % (BN / VB)) * VB : (tid % (KD / VB)) * VB;
   const int vb_o = b_n_unit ? tid / (BN / VB) : tid / (KD / VB);
   const int vb_d = b_n_unit ? NTHR * VB / BN : NTHR * VB / KD;
+  // vector loads: per-thread base pointers and uniform slot steps set up
+  // once, the problem's fields in registers (not re-read from the kernel
+  // arguments inside the K loop)
+  const int PM = P.M, PN = P.N;
+  const int64_t sAk = P.sAk, sBk = P.sBk;
+  const SA *va_p = Ap + aoff + (int64_t)(m0 + (a_m_unit ? va_u : va_o)) * P.sAm +
+                   (int64_t)(a_m_unit ? va_o : va_u) * sAk;
+  const int64_t vb_e = boff + (int64_t)(n0 + (b_n_unit ? vb_u : vb_o)) * P.sBn +
+                       (int64_t)(b_n_unit ? vb_o : vb_u) * sBk;  // element offset
+  const SB *vb_p = Bp + vb_e;
+  const double *cg_w = P.Bw + vb_e, *cg_s = P.Bs + vb_e;  // CG operand (BCG)
+  const int64_t va_s = (int64_t)va_d * (a_m_unit ? sAk : P.sAm);
+  const int64_t vb_s = (int64_t)vb_d * (b_n_unit ? sBk : P.sBn);
   auto gload = [&](int k0) {
     if constexpr (VEC) {
 #pragma unroll
@@ -350,9 +457,8 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_gemm(GemmK g) {
         const int gm = m0 + (a_m_unit ? va_u : va_o + va_d * i);
         const int gk = k0 + (a_m_unit ? va_o + va_d * i : va_u);
         VecA v = VecA(SA(0));
-        if (gm < P.M && gk < kend)
-          v = *reinterpret_cast<const VecA *>(Ap + aoff + (int64_t)gm * P.sAm +
-                                              (int64_t)gk * P.sAk);
+        if (gm < PM && gk < kend)
+          v = *reinterpret_cast<const VecA *>(va_p + i * va_s + (int64_t)k0 * sAk);
 #pragma unroll
         for (int e = 0; e < VA; ++e) ra[i * VA + e] = v[e];
       }
@@ -361,9 +467,21 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_gemm(GemmK g) {
         const int gn = n0 + (b_n_unit ? vb_u : vb_o + vb_d * i);
         const int gk = k0 + (b_n_unit ? vb_o + vb_d * i : vb_u);
         VecB v = VecB(SB(0));
-        if (gn < P.N && gk < kend)
-          v = *reinterpret_cast<const VecB *>(Bp + boff + (int64_t)gn * P.sBn +
-                                              (int64_t)gk * P.sBk);
+        if (gn < PN && gk < kend) {
+          const int64_t o = i * vb_s + (int64_t)k0 * sBk;
+          v = *reinterpret_cast<const VecB *>(vb_p + o);
+          if constexpr (BCG) {
+            // the CG operand: B - alpha (w + beta s), w and s laid out like B
+            // (fused multiply-adds spelled out: the same roundings as the
+            // element-wise form below)
+            const VecB w = *reinterpret_cast<const VecB *>(cg_w + o);
+            VecB sv = w;
+            if (!cg_first) sv = *reinterpret_cast<const VecB *>(cg_s + o);
+#pragma unroll
+            for (int e = 0; e < VB; ++e)
+              v[e] = __builtin_fma(-cg_a, cg_first ? w[e] : __builtin_fma(cg_b, sv[e], w[e]), v[e]);
+          }
+        }
 #pragma unroll
         for (int e = 0; e < VB; ++e) rb[i * VB + e] = v[e];
       }
@@ -385,35 +503,106 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_gemm(GemmK g) {
         rb[i] = 0.0;
         if (gn < P.N && gk < kend) {
           const double w = P.Bw[off];
-          rb[i] = Bp[off] - cg_a * (cg_first ? w : w + cg_b * P.Bs[off]);
+          rb[i] = __builtin_fma(-cg_a, cg_first ? w : __builtin_fma(cg_b, P.Bs[off], w), Bp[off]);
         }
       } else {
         rb[i] = (gn < P.N && gk < kend) ? Bp[off] : SB(0);
       }
     }
   };
+  // LDS stores of the loaded slice; each branch is uniform (the operand's
+  // unit-stride dimension), and its offsets are a per-lane word offset plus a
+  // compile-time one.  A loaded vector along a float32 row goes into LDS in
+  // pieces of the fragment length at most (each piece contiguous and aligned
+  // there)
+  constexpr int PA = VA < VFA ? VA : VFA, PB = VB < VFB ? VB : VFB;
   auto sstore = [&](int buf) {
+    T *as = As[buf], *bs = Bs[buf];
     if constexpr (VEC) {
+      if (a_m_unit) {
+        // thread: row va_o + va_d i (va_d even), columns va_u ..
+        const int l0 = LA::row(va_o) + va_u;
 #pragma unroll
-      for (int i = 0; i < AV; ++i)
+        for (int i = 0; i < AV; ++i) {
+          T *dst = as + l0 + (va_d * i / 2) * LA::PP;
+          if constexpr (FRAG && PA > 1) {
+            typedef unsigned VT __attribute__((ext_vector_type(PA)));
 #pragma unroll
-        for (int e = 0; e < VA; ++e)
-          As[buf][a_m_unit ? va_o + va_d * i : va_u + e][a_m_unit ? va_u + e : va_o + va_d * i] =
-              to_op<T>((double)ra[i * VA + e]);
+            for (int e0 = 0; e0 < VA; e0 += PA) {
+              VT v;
 #pragma unroll
-      for (int i = 0; i < BV; ++i)
+              for (int e = 0; e < PA; ++e)
+                v[e] = __builtin_bit_cast(unsigned, to_op<T>((double)ra[i * VA + e0 + e]));
+              *reinterpret_cast<VT *>(dst + e0) = v;
+            }
+          } else {
 #pragma unroll
-        for (int e = 0; e < VB; ++e)
-          Bs[buf][b_n_unit ? vb_o + vb_d * i : vb_u + e][b_n_unit ? vb_u + e : vb_o + vb_d * i] =
-              to_op<T>((double)rb[i * VB + e]);
+            for (int e = 0; e < VA; ++e) dst[e] = to_op<T>((double)ra[i * VA + e]);
+          }
+        }
+      } else {
+        // thread: rows va_u + e (va_u even), column va_o + va_d i
+        const int l0 = (va_u >> 1) * LA::PP + va_o;
+#pragma unroll
+        for (int i = 0; i < AV; ++i)
+#pragma unroll
+          for (int e = 0; e < VA; ++e)
+            as[l0 + LA::row(e) + va_d * i] = to_op<T>((double)ra[i * VA + e]);
+      }
+      if (b_n_unit) {
+        const int l0 = LB::row(vb_o) + vb_u;
+#pragma unroll
+        for (int i = 0; i < BV; ++i) {
+          T *dst = bs + l0 + (vb_d * i / 2) * LB::PP;
+          if constexpr (FRAG && PB > 1) {
+            typedef unsigned VT __attribute__((ext_vector_type(PB)));
+#pragma unroll
+            for (int e0 = 0; e0 < VB; e0 += PB) {
+              VT v;
+#pragma unroll
+              for (int e = 0; e < PB; ++e)
+                v[e] = __builtin_bit_cast(unsigned, to_op<T>((double)rb[i * VB + e0 + e]));
+              *reinterpret_cast<VT *>(dst + e0) = v;
+            }
+          } else {
+#pragma unroll
+            for (int e = 0; e < VB; ++e) dst[e] = to_op<T>((double)rb[i * VB + e]);
+          }
+        }
+      } else {
+        const int l0 = (vb_u >> 1) * LB::PP + vb_o;
+#pragma unroll
+        for (int i = 0; i < BV; ++i)
+#pragma unroll
+          for (int e = 0; e < VB; ++e)
+            bs[l0 + LB::row(e) + vb_d * i] = to_op<T>((double)rb[i * VB + e]);
+      }
       return;
     }
+    if (a_m_unit) {
+      // thread: row tid / BM + (NTHR / BM) i, column tid % BM
+      constexpr int DR = NTHR / BM;
+      static_assert(DR % 2 == 0, "even row steps");
+      const int l0 = LA::row(tid / BM) + tid % BM;
 #pragma unroll
-    for (int i = 0; i < AL; ++i)
-      As[buf][a_kk0 + a_dk * i][a_mm0 + a_dm * i] = to_op<T>((double)ra[i]);
+      for (int i = 0; i < AL; ++i) as[l0 + (DR * i / 2) * LA::PP] = to_op<T>((double)ra[i]);
+    } else {
+      // thread: row tid % KD, column tid / KD + (NTHR / KD) i
+      const int l0 = LA::row(tid % KD) + tid / KD;
 #pragma unroll
-    for (int i = 0; i < BL; ++i)
-      Bs[buf][b_kk0 + b_dk * i][b_nn0 + b_dn * i] = to_op<T>((double)rb[i]);
+      for (int i = 0; i < AL; ++i) as[l0 + (NTHR / KD) * i] = to_op<T>((double)ra[i]);
+    }
+    if (b_n_unit) {
+      constexpr int DR = NTHR / BN;
+      static_assert(DR % 2 == 0, "even row steps");
+      const int l0 = LB::row(tid / BN) + tid % BN;
+#pragma unroll
+      for (int i = 0; i < BL; ++i) bs[l0 + (DR * i / 2) * LB::PP] = to_op<T>((double)rb[i]);
+    } else {
+      const int l0 = LB::row(tid % KD) + tid / KD;
+#pragma unroll
+      for (int i = 0; i < BL; ++i) bs[l0 + (NTHR / KD) * i] = to_op<T>((double)rb[i]);
+    }
   };
 
   if (kbeg < kend) {
@@ -426,37 +615,87 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_gemm(GemmK g) {
     const bool more = k0 + KD < kend;
     if (more) gload(k0 + KD);
 #pragma unroll
-    for (int h = 0; h < KD / KT; ++h)
-      Mfma<T, FM, FN, LDA>::step(As[buf] + h * KT, Bs[buf] + h * KT, lane, wm * WTM, wn * WTN,
-                                 acc);
+    for (int h = 0; h < KD / KT; ++h) {
+      if constexpr (BF3)
+        MfmaBf3F<FM, FN, BM, BN>::step(As[buf], Bs[buf], lane, wm * WTM, wn * WTN, h * KT, acc);
+      else if constexpr (FRAG)
+        MfmaF32<FM, FN, BM, BN>::step(As[buf], Bs[buf], lane, wm * WTM, wn * WTN, h * KT, acc);
+      else
+        Mfma<T, FM, FN, LDA>::step(reinterpret_cast<const T(*)[LDA]>(As[buf]) + h * KT,
+                                   reinterpret_cast<const T(*)[LDB]>(Bs[buf]) + h * KT, lane,
+                                   wm * WTM, wn * WTN, acc);
+    }
     if (more) sstore(buf ^ 1);
     __syncthreads();
     buf ^= 1;
   }
 
-  // D(16x16): lane l holds column l % 16.  float32 / bfloat16: register r is
-  // row 4*(l/16) + r; float64 16x16x4: register r is row 4*r + l/16.
-  // Output element (i, j, r) of the lane sits at row rowb + 16 i + rr(r) and
-  // column colb + 16 j: its offset is the lane's base plus a block term 16 i sm
-  // + 16 j sn (uniform) plus rr(r) sm, so the per-element address is a few
-  // adds; the store kind (partials, float32, float64, with beta) is uniform
-  // per problem and chosen outside the element loops.
-  const int rowb = m0 + wm * WTM, colb = n0 + wn * WTN + (lane & 15);
-  auto rr = [&](int r) {
-    return (GemmKind<T>::value == 0) ? (4 * r + (lane >> 4)) : ((lane >> 4) * 4 + r);
+  // D(16x16): lane l holds column l % 16 of the block.  float32 / bfloat16:
+  // register r is block row 4*(l/16) + r; float64 16x16x4: register r is
+  // block row 4*r + l/16.  Blocks of a float32 wave tile interleave (block i
+  // row r is wave-tile row FM r + i, block j column c is wave-tile column
+  // FN c + j, as the fragments were read); other types stack them (row
+  // 16 i + r, column 16 j + c).  The element offset is the lane's row and
+  // column terms; the store kind (partials, float32, float64, with beta) is
+  // uniform per problem and chosen outside the element loops.
+  const int rowb = m0 + wm * WTM, colb = n0 + wn * WTN;
+  auto row_of = [&](int i, int r) {
+    const int br = (GemmKind<T>::value == 0) ? (4 * r + (lane >> 4)) : ((lane >> 4) * 4 + r);
+    return FRAG ? rowb + FM * br + i : rowb + 16 * i + br;
+  };
+  auto col_of = [&](int j) {
+    return FRAG ? colb + FN * (lane & 15) + j : colb + 16 * j + (lane & 15);
   };
   auto store_all = [&](auto *Cp, int64_t base, int64_t sm, int64_t sn, double alpha, double beta) {
+    typedef std::remove_cv_t<std::remove_reference_t<decltype(*Cp)>> E;
+    if constexpr (FRAG) {
+      // unit column stride with every row start a multiple of FN elements:
+      // each lane's FN consecutive columns of a row go out as one vector
+      if (sn == 1 && base % FN == 0 && sm % FN == 0 &&
+          reinterpret_cast<uintptr_t>(Cp) % (FN * sizeof(E)) == 0) {
+        typedef E VE __attribute__((ext_vector_type(FN)));
+        const int gn0 = col_of(0);
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int gm = row_of(i, r);
+            if (gm >= P.M) continue;
+            E *cp = Cp + base + (int64_t)gm * sm + gn0;
+            if (gn0 + FN <= P.N) {
+              VE v;
+              VE old = beta != 0.0 ? *reinterpret_cast<const VE *>(cp) : VE(E(0));
+#pragma unroll
+              for (int j = 0; j < FN; ++j) {
+                double x = alpha * (double)acc[i][j][r];
+                if (beta != 0.0) x += beta * (double)old[j];
+                v[j] = (E)x;
+              }
+              *reinterpret_cast<VE *>(cp) = v;
+            } else {
+#pragma unroll
+              for (int j = 0; j < FN; ++j)
+                if (gn0 + j < P.N) {
+                  double x = alpha * (double)acc[i][j][r];
+                  if (beta != 0.0) x += beta * (double)cp[j];
+                  cp[j] = (E)x;
+                }
+            }
+          }
+        return;
+      }
+    }
 #pragma unroll
     for (int i = 0; i < FM; ++i)
 #pragma unroll
       for (int j = 0; j < FN; ++j) {
-        const int gn = colb + j * 16;
-        const int64_t bij = base + (int64_t)(rowb + i * 16) * sm + (int64_t)gn * sn;
+        const int gn = col_of(j);
+        const int64_t bj = base + (int64_t)gn * sn;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int gm = rowb + i * 16 + rr(r);
+          const int gm = row_of(i, r);
           if (gm < P.M && gn < P.N) {
-            auto *cp = Cp + bij + (int64_t)rr(r) * sm;
+            auto *cp = Cp + bj + (int64_t)gm * sm;
             double v = alpha * (double)acc[i][j][r];
             if (beta != 0.0) v += beta * (double)*cp;
             *cp = (decltype(+*cp))v;
@@ -540,6 +779,27 @@ __device__ inline double red_wave_sum(double v) {
   return v;
 }
 
+// one element of the fused CG step (unpreconditioned, single reduction):
+// s = w + beta s, p = r + beta p (first step: w, r), x += alpha p,
+// r -= alpha s, w = A r = v + beta_X r; with the partial sums of r.r and w.r
+// (fused multiply-adds spelled out: the roundings do not hang on the
+// compiler's contraction choices)
+__device__ __forceinline__ void cg_elem(const RedK &R, int64_t j, double wi, double ri, double so,
+                                        double po, double xo, double v, double bx, double a,
+                                        double b, bool first, double &rr, double &wr) {
+  const double si = first ? wi : __builtin_fma(b, so, wi);
+  const double pi = first ? ri : __builtin_fma(b, po, ri);
+  R.cs[j] = si;
+  R.cp[j] = pi;
+  R.cx[j] = __builtin_fma(a, pi, xo);
+  const double rn = __builtin_fma(-a, si, ri);
+  const double wn = __builtin_fma(bx, rn, v);
+  R.cr[j] = rn;
+  R.cw[j] = wn;
+  rr = __builtin_fma(rn, rn, rr);
+  wr = __builtin_fma(wn, rn, wr);
+}
+
 // out = alpha * (sum over sources, splits in order) + beta * X, or with
 // per-source alphas sum_q alpha_q (sum over q's splits) + beta * X
 __global__ __launch_bounds__(256) void k_splitk_reduce(RedK R) {
@@ -592,17 +852,8 @@ __global__ __launch_bounds__(256) void k_splitk_reduce(RedK R) {
       // beta term of the matvec takes the new residual
       const int64_t j = O.cgoff + co;
       const double wi = R.cw[j], ri = R.cr[j];
-      const double si = cg_first ? wi : wi + cg_b * R.cs[j];
-      const double pi = cg_first ? ri : ri + cg_b * R.cp[j];
-      R.cs[j] = si;
-      R.cp[j] = pi;
-      R.cx[j] += cg_a * pi;
-      const double rn = ri - cg_a * si;
-      const double wn = v + O.beta * rn;
-      R.cr[j] = rn;
-      R.cw[j] = wn;
-      cg_rr += rn * rn;
-      cg_wr += wn * rn;
+      cg_elem(R, j, wi, ri, cg_first ? 0.0 : R.cs[j], cg_first ? 0.0 : R.cp[j], R.cx[j], v,
+              O.beta, cg_a, cg_b, cg_first, cg_rr, cg_wr);
       continue;
     }
     if (O.c32) reinterpret_cast<float *>(O.C)[co] = (float)v;
@@ -731,8 +982,14 @@ void launch_tile(int MT, int sa, int sb, int64_t blocks, hipStream_t st, const G
   if (g.cgst) {
     if (!std::is_same<T, double>::value || MT != 64 || sa || sb)
       fail(QTT_E_ARG, "gemm: the CG operand needs float64 64-tiles");
-    hipLaunchKernelGGL((k_gemm<double, 64, 64, 2, 2, 16, double, double, true>), grid,
-                       dim3(256), 0, st, g);
+    bool vec = true;
+    for (int i = 0; i < g.np; ++i) vec = vec && g.p[i].va && g.p[i].vb;
+    if (vec)
+      hipLaunchKernelGGL((k_gemm<double, 64, 64, 2, 2, 16, double, double, true, true>), grid,
+                         dim3(256), 0, st, g);
+    else
+      hipLaunchKernelGGL((k_gemm<double, 64, 64, 2, 2, 16, double, double, true, false>), grid,
+                         dim3(256), 0, st, g);
     return;
   }
   // vector loads when every problem of the launch qualifies
@@ -743,9 +1000,7 @@ void launch_tile(int MT, int sa, int sb, int64_t blocks, hipStream_t st, const G
       if (sa && sb) launch_k<T, 128, 2, 4, 32, float, float>(vec, grid, st, g);
       else if (sa) launch_k<T, 128, 2, 4, 32, float, double>(vec, grid, st, g);
       else if (sb) launch_k<T, 128, 2, 4, 32, double, float>(vec, grid, st, g);
-      // (float64 operands into float32 128-tiles: the vector form needs more
-      // than the 128 registers that keep two workgroups per compute unit)
-      else launch_k<T, 128, 2, 4, 32>(false, grid, st, g);
+      else launch_k<T, 128, 2, 4, 32>(vec, grid, st, g);
     } else {
       if (sa && sb) launch_k<T, 64, 2, 2, 16, float, float>(vec, grid, st, g);
       else if (sa) launch_k<T, 64, 2, 2, 16, float, double>(vec, grid, st, g);
@@ -908,7 +1163,8 @@ void launch_group(Ctx &c, int np, const Gemm *q, int ngroups, const int *group,
                 ((s.sAm == 1 && s.sAk % VA == 0 && s.M % VA == 0) ||
                  (s.sAm != 1 && s.sAk == 1 && s.sAm % VA == 0 && s.K % VA == 0)))
                    ? 1 : 0;
-        P.vb = (!s.cgst && al(s.B) && s.sBb1 % VB == 0 && s.sBb2 % VB == 0 &&
+        P.vb = ((!s.cgst || (al(s.Bw) && al(s.Bs))) && al(s.B) && s.sBb1 % VB == 0 &&
+                s.sBb2 % VB == 0 &&
                 ((s.sBn == 1 && s.sBk % VB == 0 && s.N % VB == 0) ||
                  (s.sBn != 1 && s.sBk == 1 && s.sBn % VB == 0 && s.K % VB == 0)))
                    ? 1 : 0;
