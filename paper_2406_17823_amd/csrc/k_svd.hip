@@ -332,38 +332,46 @@ __device__ void svg_apply_j(double *Xs, const double *J, int rows, int wave, int
 }
 
 // column slots of a column-major m x n matrix (slot c holds column colidx[c],
-// -1: zero) into rows 0..mp of the row-major LDS block, rows >= m zero; the
-// global loads go out SVG_UNROLL at a time before their LDS stores
-constexpr int SVG_UNROLL = 8;
-template <int NC>
+// -1: zero) into rows 0..mp of the row-major LDS block, rows >= m zero.  A
+// thread takes row i of every slot (consecutive threads, consecutive rows:
+// coalesced column reads), UNR slots' loads issued before their LDS stores
+// (no index division)
+template <int NC, int UNR>
 __device__ void svg_stage(double *Xs, const double *src, int m, int mp, const int *colidx,
                           int tid) {
+  static_assert(NC % UNR == 0, "whole slot groups");
   constexpr int LD = NC + 1;
-  const int total = mp * NC;
-  for (int base = tid; base < total; base += SVG_UNROLL * SVG_THREADS) {
-    double v[SVG_UNROLL];
+  for (int i = tid; i < mp; i += SVG_THREADS) {
 #pragma unroll
-    for (int u = 0; u < SVG_UNROLL; ++u) {
-      const int idx = base + u * SVG_THREADS;
-      v[u] = 0.0;
-      if (idx < total) {
-        const int c = idx / mp, i = idx - c * mp;
-        const int gc = colidx[c];
-        if (gc >= 0 && i < m) v[u] = src[(int64_t)gc * m + i];
-      }
-    }
+    for (int c0 = 0; c0 < NC; c0 += UNR) {
+      double v[UNR];
 #pragma unroll
-    for (int u = 0; u < SVG_UNROLL; ++u) {
-      const int idx = base + u * SVG_THREADS;
-      if (idx < total) {
-        const int c = idx / mp, i = idx - c * mp;
-        Xs[i * LD + c] = v[u];
+      for (int u = 0; u < UNR; ++u) {
+        const int gc = colidx[c0 + u];
+        v[u] = (gc >= 0 && i < m) ? src[(int64_t)gc * m + i] : 0.0;
       }
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) Xs[i * LD + c0 + u] = v[u];
     }
   }
 }
 
+// the LDS block's first m rows back to the slots' columns (column by column,
+// consecutive threads on consecutive rows)
 template <int NC>
+__device__ void svg_unstage(double *dst, const double *Xs, int m, const int *colidx, int tid) {
+  constexpr int LD = NC + 1;
+  for (int c = 0; c < NC; ++c) {
+    const int gc = colidx[c];
+    if (gc < 0) continue;
+    for (int i = tid; i < m; i += SVG_THREADS) dst[(int64_t)gc * m + i] = Xs[i * LD + c];
+  }
+}
+
+// ACC: the launch accumulates rotations into V for some matrix (else the V
+// registers are not allocated and the staging issues all NC slots' loads at
+// once)
+template <int NC, bool ACC>
 __global__ __launch_bounds__(SVG_THREADS) void k_svg_round(SvBatch B, int round) {
   static_assert(NC == 16 || NC == 32, "block pairs of 16 or 32 column slots");
   constexpr int LD = NC + 1, P = NC / 2, NT16 = NC / 16;
@@ -416,10 +424,11 @@ __global__ __launch_bounds__(SVG_THREADS) void k_svg_round(SvBatch B, int round)
   __syncthreads();
   // V slots of the pair: loads issued now into registers when they fit
   const int np16 = (n + 15) & ~15;
-  const bool vreg = D.accumulate && np16 * NC <= SVG_VREG * SVG_THREADS;
-  double vr[SVG_VREG];
+  constexpr int VREG = ACC ? SVG_VREG : 1;
+  const bool vreg = ACC && D.accumulate && np16 * NC <= SVG_VREG * SVG_THREADS;
+  double vr[VREG];
 #pragma unroll
-  for (int u = 0; u < SVG_VREG; ++u) {
+  for (int u = 0; u < VREG; ++u) {
     const int idx = tid + u * SVG_THREADS;
     vr[u] = 0.0;
     if (vreg && idx < np16 * NC) {
@@ -428,7 +437,7 @@ __global__ __launch_bounds__(SVG_THREADS) void k_svg_round(SvBatch B, int round)
       if (gc >= 0 && i < n) vr[u] = D.V[(int64_t)gc * n + i];
     }
   }
-  svg_stage<NC>(Xs, D.W, m, mp, colidx, tid);
+  svg_stage<NC, ACC ? 8 : NC>(Xs, D.W, m, mp, colidx, tid);
   for (int idx = tid; idx < NC * NC; idx += SVG_THREADS) {
     const int i = idx / NC, j = idx - i * NC;
     J[i * LD + j] = (i == j) ? 1.0 : 0.0;
@@ -563,17 +572,13 @@ __global__ __launch_bounds__(SVG_THREADS) void k_svg_round(SvBatch B, int round)
   if (total == 0) return;  // J = I: columns and V unchanged
   svg_apply_j<NC>(Xs, J, mp, wave, lane);
   __syncthreads();
-  for (int idx = tid; idx < NC * m; idx += SVG_THREADS) {
-    const int c = idx / m, i = idx - c * m;
-    const int gc = colidx[c];
-    if (gc >= 0) D.W[(int64_t)gc * m + i] = Xs[i * LD + c];
-  }
-  if (D.accumulate) {
+  svg_unstage<NC>(D.W, Xs, m, colidx, tid);
+  if (ACC && D.accumulate) {
     // V[:, cols] (n x NC) <- V[:, cols] J through the same LDS rows (n <= m)
     __syncthreads();
     if (vreg) {
 #pragma unroll
-      for (int u = 0; u < SVG_VREG; ++u) {
+      for (int u = 0; u < VREG; ++u) {
         const int idx = tid + u * SVG_THREADS;
         if (idx < np16 * NC) {
           const int c = idx / np16, i = idx - c * np16;
@@ -581,16 +586,12 @@ __global__ __launch_bounds__(SVG_THREADS) void k_svg_round(SvBatch B, int round)
         }
       }
     } else {
-      svg_stage<NC>(Xs, D.V, n, np16, colidx, tid);
+      svg_stage<NC, 8>(Xs, D.V, n, np16, colidx, tid);
     }
     __syncthreads();
     svg_apply_j<NC>(Xs, J, np16, wave, lane);
     __syncthreads();
-    for (int idx = tid; idx < NC * n; idx += SVG_THREADS) {
-      const int c = idx / n, i = idx - c * n;
-      const int gc = colidx[c];
-      if (gc >= 0) D.V[(int64_t)gc * n + i] = Xs[i * LD + c];
-    }
+    svg_unstage<NC>(D.V, Xs, n, colidx, tid);
   }
   if (tid == 0) atomicAdd(D.count, total);
 }
@@ -653,8 +654,12 @@ size_t sv_lds_limit(Ctx &c) {
   int maxsh = 0;
   HIPC(hipDeviceGetAttribute(&maxsh, hipDeviceAttributeMaxSharedMemoryPerBlock, c.device));
   size_t stat = 0;
-  const void *kerns[4] = {(const void *)k_sv_round<SV_THREADS>, (const void *)k_sv_round<SVB_THREADS>,
-                          (const void *)k_svg_round<32>, (const void *)k_svg_round<16>};
+  const void *kerns[6] = {(const void *)k_sv_round<SV_THREADS>,
+                          (const void *)k_sv_round<SVB_THREADS>,
+                          (const void *)k_svg_round<32, true>,
+                          (const void *)k_svg_round<16, true>,
+                          (const void *)k_svg_round<32, false>,
+                          (const void *)k_svg_round<16, false>};
   for (const void *k : kerns) {
     hipFuncAttributes fa;
     HIPC(hipFuncGetAttributes(&fa, k));
@@ -945,6 +950,8 @@ void svd_jacobi_group(Ctx &c, int count, const ConstMatView *A, const MatView *U
     }
     hipLaunchKernelGGL(k_sv_init, dim3(cnt), dim3(SV_THREADS), 0, c.stream, B);
     HIPC(hipGetLastError());
+    bool acc_any = false;  // some matrix accumulates V (the round kernels' V path)
+    for (int i = 0; i < cnt; ++i) acc_any = acc_any || B.d[i].accumulate;
     // rounds per sweep: the largest block count decides
     int rounds = 1;
     for (int i = 0; i < cnt; ++i)
@@ -972,12 +979,18 @@ void svd_jacobi_group(Ctx &c, int count, const ConstMatView *A, const MatView *U
         if (single_group)
           hipLaunchKernelGGL(k_sv_round<SV_THREADS>, dim3(wg), dim3(SV_THREADS), lds_round,
                              c.stream, R, r);
+        else if (gram_nc == 32 && acc_any)
+          hipLaunchKernelGGL((k_svg_round<32, true>), dim3(wg), dim3(SVG_THREADS), lds_round,
+                             c.stream, R, r);
         else if (gram_nc == 32)
-          hipLaunchKernelGGL(k_svg_round<32>, dim3(wg), dim3(SVG_THREADS), lds_round, c.stream,
-                             R, r);
+          hipLaunchKernelGGL((k_svg_round<32, false>), dim3(wg), dim3(SVG_THREADS), lds_round,
+                             c.stream, R, r);
+        else if (gram_nc == 16 && acc_any)
+          hipLaunchKernelGGL((k_svg_round<16, true>), dim3(wg), dim3(SVG_THREADS), lds_round,
+                             c.stream, R, r);
         else if (gram_nc == 16)
-          hipLaunchKernelGGL(k_svg_round<16>, dim3(wg), dim3(SVG_THREADS), lds_round, c.stream,
-                             R, r);
+          hipLaunchKernelGGL((k_svg_round<16, false>), dim3(wg), dim3(SVG_THREADS), lds_round,
+                             c.stream, R, r);
         else
           hipLaunchKernelGGL(k_sv_round<SVB_THREADS>, dim3(wg), dim3(SVB_THREADS), lds_round,
                              c.stream, R, r);
