@@ -524,7 +524,7 @@ __device__ void qrb_apply_tile(const QrbDesc &D, int j0, int jb, double *X, cons
     const double b0 = (rv && li < nc) ? X[(int64_t)(c0 + li) * m + r] : 0.0;
     const double b1 = (rv && 16 + li < nc) ? X[(int64_t)(c0 + 16 + li) * m + r] : 0.0;
     z[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b0, z[0], 0, 0, 0);
-    z[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b1, z[1], 0, 0, 0);
+    if (nc > 16) z[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b1, z[1], 0, 0, 0);
   }
   // D register q: row 4 q + lane / 16, column lane % 16
 #pragma unroll
@@ -629,17 +629,20 @@ __global__ __launch_bounds__(QA_THREADS) void k_qrb_apply_la(QrbBatch B, int j0)
 }
 
 // explicit Q = H_0 H_1 ... [I; 0] in one launch: the columns of Q are
-// independent, so each workgroup takes its 32-column tile through every
-// panel's block reflector, last panel first (a panel whose rows start at or
-// right of the tile's last column leaves it unchanged and is skipped).  The
-// tile's own global writes are visible to the whole workgroup after the
-// barrier; the arithmetic per column is that of one apply launch per panel.
+// independent, so each workgroup takes its tile of FQ_COLS = 16 columns
+// through every panel's block reflector, last panel first (a panel whose rows
+// start at or right of the tile's last column leaves it unchanged and is
+// skipped); narrower tiles than the trailing updates' put twice the
+// workgroups on this chain of dependent panel steps.  The tile's own global
+// writes are visible to the whole workgroup after the barrier; the arithmetic
+// per column is that of one apply launch per panel.
+constexpr int FQ_COLS = 16;
 __global__ __launch_bounds__(QA_THREADS) void k_qrb_formq(QrbBatch B) {
   const QrbDesc &D = B.d[blockIdx.y];
   if (!D.Q) return;
-  const int c0 = (int)blockIdx.x * QA_COLS;
+  const int c0 = (int)blockIdx.x * FQ_COLS;
   if (c0 >= D.k) return;
-  const int nc = min(QA_COLS, D.k - c0);
+  const int nc = min(FQ_COLS, D.k - c0);
   __shared__ double Zs[QA_WAVES][QR_NB][QA_COLS + 1];
   for (int j0 = ((D.k - 1) / QR_NB) * QR_NB; j0 >= 0; j0 -= QR_NB) {
     if (j0 >= c0 + nc) continue;
@@ -789,7 +792,7 @@ void qr_blocked(Ctx &c, int cnt, const ConstMatView *A, const MatView *Q, const 
   {
     int tiles = 0;
     for (int i = 0; i < cnt; ++i)
-      if (b.d[i].Q) tiles = std::max(tiles, (b.d[i].k + QA_COLS - 1) / QA_COLS);
+      if (b.d[i].Q) tiles = std::max(tiles, (b.d[i].k + FQ_COLS - 1) / FQ_COLS);
     if (tiles > 0) {
       hipLaunchKernelGGL(k_qrb_formq, dim3(tiles, cnt), dim3(QA_THREADS), 0, c.stream, b);
       HIPC(hipGetLastError());
