@@ -129,6 +129,7 @@ typedef struct {
   int32_t cg_solves;        /* local solves                                    */
   int32_t cg_maxit_hits;    /* local solves that stopped at cg_maxit           */
   int32_t fallbacks;        /* learned preconditioner rejections               */
+  int32_t graph_replays;    /* replays of captured CG chunk graphs             */
   double discarded_sq;      /* summed discarded singular weight of truncations */
   double phase_ms[8];       /* host-timed phases: 0 add/truncate, 1 env build,
                                2 local rhs, 3 CG, 4 shift, 5 env update        */

@@ -97,6 +97,7 @@ struct KernelTimer {
 struct CgGraph {
   hipGraphExec_t exec = nullptr;
   std::vector<int64_t> key;
+  int hits = 0;  // lookups in a row that found the same key
   int64_t launches[KT_KINDS] = {0, 0, 0, 0};  // GEMM launches per replay, by timer kind
 };
 

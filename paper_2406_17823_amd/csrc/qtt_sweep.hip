@@ -37,11 +37,13 @@ namespace qtt {
 namespace {
 
 enum { LAYER_MPO = 0, LAYER_HAD = 1 };
-// CG iterations are enqueued in an eager first chunk sized from the
-// iteration count of the previous solve at the same site and direction, then
-// in replayed graphs of GRAPH_CHUNK iterations until the device flag says
-// done; iterations enqueued past convergence return at once but still cost a
-// launch each, so both chunks are kept short
+// CG iterations are enqueued in a first chunk sized from the iteration count
+// of the previous solve at the same site and direction, then in replayed
+// graphs of GRAPH_CHUNK iterations until the device flag says done; the first
+// chunk is one eager iteration and then replays of the same graph once its
+// configuration has recurred (else eager launches); iterations enqueued past
+// convergence return at once but still cost a launch each, so both chunks
+// are kept short
 constexpr int GRAPH_CHUNK = 4;
 
 struct Layer {
@@ -555,8 +557,11 @@ struct Sweep {
     const std::string k =
         std::to_string(d) + (rev ? "r" : "f") + (pre ? "p" : "c") + std::to_string(mh);
     CgGraph &g = c.cg_graphs[k];
-    if (g.exec && g.key != key) {
-      HIPC(hipGraphExecDestroy(g.exec));
+    if (g.key == key) {
+      g.hits += 1;
+    } else {
+      g.hits = 0;
+      if (g.exec) HIPC(hipGraphExecDestroy(g.exec));
       g.exec = nullptr;
     }
     g.key = key;
@@ -619,10 +624,9 @@ struct Sweep {
     pc_forward(c, X, rows, pcM, false);
   }
 
-  // CG / PCG iterations until the device flag says done: the first chunk
-  // runs eagerly (it also allocates every buffer the iteration needs); later
-  // chunks replay a captured graph of GRAPH_CHUNK iterations, one graph per
-  // (site, direction, mu h^2, preconditioning)
+  // CG / PCG iterations until the device flag says done, as replays of a
+  // captured graph of GRAPH_CHUNK iterations, one graph per (site, direction,
+  // mu h^2, preconditioning) and the buffers and shapes it was captured with
   void run_cg(int d, bool rev, bool pre, double *x, double *r, double *pp, double *q,
               const double *rhs, int64_t ntot) {
     auto enqueue_iters = [&](int k) {
@@ -656,34 +660,52 @@ struct Sweep {
     const int hkey = (d * 2 + (rev ? 1 : 0)) * 2 + (pre ? 1 : 0);
     auto h = c.cg_hist.find(hkey);
     const int first_chunk = (h == c.cg_hist.end()) ? 8 : std::max(2, std::min(64, h->second + 1));
-    enqueue_iters(first_chunk);
+    auto capture = [&](CgGraph *g) {
+      c.capturing = true;
+      for (int k = 0; k < KT_KINDS; ++k) c.cap_launches[k] = 0;
+      hipGraph_t graph = nullptr;
+      HIPC(hipStreamBeginCapture(c.stream, hipStreamCaptureModeRelaxed));
+      try {
+        enqueue_iters(GRAPH_CHUNK);
+      } catch (...) {
+        c.capturing = false;
+        (void)hipStreamEndCapture(c.stream, &graph);
+        if (graph) (void)hipGraphDestroy(graph);
+        (void)hipGetLastError();
+        throw;
+      }
+      c.capturing = false;
+      HIPC(hipStreamEndCapture(c.stream, &graph));
+      HIPC(hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0));
+      HIPC(hipGraphDestroy(graph));
+      for (int k = 0; k < KT_KINDS; ++k) g->launches[k] = c.cap_launches[k];
+    };
+    auto replay = [&](CgGraph *g) {
+      HIPC(hipGraphLaunch(g->exec, c.stream));
+      if (stats) stats->graph_replays += 1;
+      for (int k = 0; k < KT_KINDS; ++k) c.kt.launches[k] += c.kt.on ? g->launches[k] : 0;
+    };
+    // one eager iteration (it allocates what the iteration needs, so that
+    // the graph key below sees the final buffers); the rest of the first
+    // chunk as replays of the chunk graph when this configuration has been
+    // seen before (iterations past convergence return at once), else eager
+    enqueue_iters(1);
+    {
+      CgGraph *g = c.use_graphs ? graph_for(d, rev, pre, x, r, pp, q, rhs) : nullptr;
+      if (g && (g->exec || g->hits >= 1)) {
+        if (!g->exec) capture(g);
+        for (int i = 0; i < (first_chunk - 1 + GRAPH_CHUNK - 1) / GRAPH_CHUNK; ++i) replay(g);
+      } else {
+        enqueue_iters(first_chunk - 1);
+      }
+    }
     HIPC(hipMemcpyAsync(st_host, st, sizeof(CGState), hipMemcpyDeviceToHost, c.stream));
     c.sync();
     while (!st_host->done) {
       CgGraph *g = c.use_graphs ? graph_for(d, rev, pre, x, r, pp, q, rhs) : nullptr;
-      if (g && !g->exec) {
-        c.capturing = true;
-        for (int k = 0; k < KT_KINDS; ++k) c.cap_launches[k] = 0;
-        hipGraph_t graph = nullptr;
-        HIPC(hipStreamBeginCapture(c.stream, hipStreamCaptureModeRelaxed));
-        try {
-          enqueue_iters(GRAPH_CHUNK);
-        } catch (...) {
-          c.capturing = false;
-          (void)hipStreamEndCapture(c.stream, &graph);
-          if (graph) (void)hipGraphDestroy(graph);
-          (void)hipGetLastError();
-          throw;
-        }
-        c.capturing = false;
-        HIPC(hipStreamEndCapture(c.stream, &graph));
-        HIPC(hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0));
-        HIPC(hipGraphDestroy(graph));
-        for (int k = 0; k < KT_KINDS; ++k) g->launches[k] = c.cap_launches[k];
-      }
+      if (g && !g->exec) capture(g);
       if (g) {
-        HIPC(hipGraphLaunch(g->exec, c.stream));
-        for (int k = 0; k < KT_KINDS; ++k) c.kt.launches[k] += c.kt.on ? g->launches[k] : 0;
+        replay(g);
       } else {
         enqueue_iters(GRAPH_CHUNK);
       }

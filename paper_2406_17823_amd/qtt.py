@@ -44,12 +44,14 @@ class c_stats(ctypes.Structure):
     _fields_ = [('sweeps', ctypes.c_int32 * 4), ('cg_iters_total', ctypes.c_int32),
                 ('cg_iters_max', ctypes.c_int32), ('cg_solves', ctypes.c_int32),
                 ('cg_maxit_hits', ctypes.c_int32), ('fallbacks', ctypes.c_int32),
+                ('graph_replays', ctypes.c_int32),
                 ('discarded_sq', ctypes.c_double), ('phase_ms', ctypes.c_double * 8)]
 
     def as_dict(self):
         return dict(sweeps=list(self.sweeps), cg_iters_total=self.cg_iters_total,
                     cg_iters_max=self.cg_iters_max, cg_solves=self.cg_solves,
                     cg_maxit_hits=self.cg_maxit_hits, fallbacks=self.fallbacks,
+                    graph_replays=self.graph_replays,
                     discarded_sq=self.discarded_sq, phase_ms=list(self.phase_ms))
 
 
