@@ -15,7 +15,11 @@
         'k_gemm<T, BM, BN, WGM, WGN, KD, *>') from two counter-collection runs
         (FETCH_SIZE, WRITE_SIZE), each scaled by what the same counter reads
         for the calibration copy of COPY_MIB MiB (which reads and writes
-        exactly that many bytes).
+        exactly that many bytes);
+
+    python -m paper_2406_17823_amd.tracesum sq COUNTER_CSV CLOCK_GHZ KERNEL
+        per-dispatch means of every counter in a counter-collection run for
+        KERNEL (a name or a GEMM family), and each over the dispatches' cycles.
 """
 import collections
 import csv
@@ -165,12 +169,41 @@ def mfma(counter_csv, clock_ghz):
         print(f'{100 * util:9.1f}% {int(a["n"]):10d} {a["dur_ns"] / a["n"] / 1e3:8.1f}  {k}')
 
 
+def sq(counter_csv, clock_ghz, kernel):
+    """Per-dispatch means of every counter in the file for one kernel family, and each as a
+    fraction of the dispatches' cycles (duration x clock)."""
+    agg = collections.defaultdict(float)
+    seen = set()
+    n = 0
+    dur = 0.0
+    with open(counter_csv) as f:
+        for d in csv.DictReader(f):
+            if not _matches(d['Kernel_Name'], kernel):
+                continue
+            key = d.get('Dispatch_Id', d.get('Correlation_Id'))
+            if key not in seen:
+                seen.add(key)
+                n += 1
+                dur += float(d['End_Timestamp']) - float(d['Start_Timestamp'])
+            agg[d['Counter_Name']] += float(d['Counter_Value'])
+    if not n:
+        print(f'no dispatches of {kernel}')
+        return
+    cyc = dur * clock_ghz
+    print(f'{kernel}: {n} dispatches, {dur / n / 1e3:.1f} us each, {cyc / n:.4g} cycles each')
+    print(f'{"counter":>28} {"per dispatch":>14} {"/ cycles":>10}')
+    for c, v in sorted(agg.items()):
+        print(f'{c:>28} {v / n:14.5g} {v / cyc:10.4g}')
+
+
 if __name__ == '__main__':
     mode = sys.argv[1]
     if mode == 'window':
         window(sys.argv[2], sys.argv[3], sys.argv[4])
     elif mode == 'mfma':
         mfma(sys.argv[2], float(sys.argv[3]))
+    elif mode == 'sq':
+        sq(sys.argv[2], float(sys.argv[3]), sys.argv[4])
     elif mode == 'bytes':
         bytes_per_dispatch(sys.argv[2], sys.argv[3], sys.argv[4], int(sys.argv[5]))
     else:
