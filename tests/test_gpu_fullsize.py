@@ -64,18 +64,20 @@ def _golden_project():
     return gen, kv, np.array(pts), np.array(vals)
 
 
-@pytest.mark.parametrize('prec,tol', [('f64', 1e-10), ('f32', 1e-5)])
+@pytest.mark.parametrize('prec,tol', [('f64', 1e-10), ('f32', 1e-5), ('bf16x3', 1e-5)])
 def test_project_saturated_chi128_matches_oracle(Q, ctx, prec, tol):
     """One sweep at 2048 x 2048 with bonds [1, 4, 16, 64, 128 x 6, 64, 16, 4, 1]:
-    the shapes of the benchmark's largest contractions (float32 128 x 128
-    tiles with float32 storage in the f32 mode, split-K, the blocked QR of
-    the shifts).  Bonds bit-exact; sampled values and norms within 1e-10
-    (float64) or 1e-5 (float32 convection networks) of the oracle."""
+    the shapes of the benchmark's largest contractions (float32 or split
+    bfloat16 128 x 128 tiles with float32 storage in the reduced modes,
+    split-K, the blocked QR of the shifts).  Bonds bit-exact; sampled values
+    and norms within 1e-10 (float64) or 1e-5 (float32 or split-bfloat16
+    convection networks) of the oracle."""
     gen, kv, pts, vals = _golden_project()
     a, b, h, oprm = gen.case()
     n, chi = gen.N_SITES, gen.CHI
     prm = Q.params(re=oprm.re, dt=oprm.dt, chi=chi, dx=oprm.dx, max_sweeps=1,
-                   cg_rtol=oprm.cg_rtol, prec=Q.PREC_F32 if prec == 'f32' else Q.PREC_F64)
+                   cg_rtol=oprm.cg_rtol,
+                   prec={'f64': Q.PREC_F64, 'f32': Q.PREC_F32, 'bf16x3': Q.PREC_BF16X3}[prec])
     v = [Q.MPS.from_cores(c) for c in a]
     Q.kernel_timing(ctx, True, 1 << 30)
     rc, st = Q.project(ctx, [Q.MPS.from_cores(c) for c in a], [Q.MPS.from_cores(c) for c in b],
