@@ -31,6 +31,10 @@ struct MJobs {
   MJob j[4];
 };
 
+// largest core mode of the staged column tables: 4 x a bond of 9 (the
+// composed penalty cores)
+constexpr int MPO_MAXK = 36;
+
 template <typename TS, int V> struct VecOf;
 template <> struct VecOf<float, 4> { typedef float __attribute__((ext_vector_type(4))) type; };
 template <> struct VecOf<double, 2> { typedef double __attribute__((ext_vector_type(2))) type; };
@@ -53,28 +57,51 @@ __global__ __launch_bounds__(256) void k_mpo_rows_grouped(MJobs J, const int *sk
   const unsigned post = (unsigned)M.post;
   const TS *T = static_cast<const TS *>(M.T);
   TS *Tout = static_cast<TS *>(M.Tout);
-  for (unsigned idx = (blockIdx.x - M.blk0) * 256u + threadIdx.x; idx < nvec;
-       idx += M.nblk * 256u) {
-    const unsigned row = idx / qv;
-    const unsigned qi = idx - row * qv;
-    const unsigned p = row / (unsigned)KO;
-    const int o = (int)(row - p * (unsigned)KO);
-    const TS *src = T + (size_t)p * KI * post + (size_t)qi * V;
-    double s[V];
-#pragma unroll
-    for (int v = 0; v < V; ++v) s[v] = 0.0;
-    const int end = M.colptr[o + 1];
-    for (int z = M.colptr[o]; z < end; ++z) {
-      const double w = M.val[z];
-      const VT x = *reinterpret_cast<const VT *>(src + (size_t)M.rowidx[z] * post);
-#pragma unroll
-      for (int v = 0; v < V; ++v) s[v] += w * (double)x[v];
+  // the job's compressed columns staged in LDS (a core has at most 36 x 36
+  // entries), so that a row's input loads wait on LDS reads only, not on
+  // dependent global reads of the column tables; for large layers only (a
+  // small layer's rows do not repay the staging and its barrier: measured
+  // 36.4 -> 34.0 us on the float32 chain layers, 5.7 -> 6.1 us on the small
+  // float64 ones)
+  __shared__ int s_cp[MPO_MAXK + 1];
+  __shared__ int s_ri[MPO_MAXK * MPO_MAXK];
+  __shared__ double s_val[MPO_MAXK * MPO_MAXK];
+  const int c0 = M.colptr[0], nz = M.colptr[KO] - c0;
+  const bool staged = KO <= MPO_MAXK && nz <= MPO_MAXK * MPO_MAXK && nvec >= (1u << 20);
+  if (staged) {  // uniform across the workgroup (the job's fields)
+    for (int i = threadIdx.x; i <= KO; i += 256) s_cp[i] = M.colptr[i] - c0;
+    for (int i = threadIdx.x; i < nz; i += 256) {
+      s_ri[i] = M.rowidx[c0 + i];
+      s_val[i] = M.val[c0 + i];
     }
-    VT y;
-#pragma unroll
-    for (int v = 0; v < V; ++v) y[v] = (TS)s[v];
-    *reinterpret_cast<VT *>(Tout + (size_t)row * post + (size_t)qi * V) = y;
+    __syncthreads();
   }
+  auto rows = [&](const int *cp, const int *ri, const double *va) {
+    for (unsigned idx = (blockIdx.x - M.blk0) * 256u + threadIdx.x; idx < nvec;
+         idx += M.nblk * 256u) {
+      const unsigned row = idx / qv;
+      const unsigned qi = idx - row * qv;
+      const unsigned p = row / (unsigned)KO;
+      const int o = (int)(row - p * (unsigned)KO);
+      const TS *src = T + (size_t)p * KI * post + (size_t)qi * V;
+      double s[V];
+#pragma unroll
+      for (int v = 0; v < V; ++v) s[v] = 0.0;
+      const int end = cp[o + 1];
+      for (int z = cp[o]; z < end; ++z) {
+        const double w = va[z];
+        const VT x = *reinterpret_cast<const VT *>(src + (size_t)ri[z] * post);
+#pragma unroll
+        for (int v = 0; v < V; ++v) s[v] += w * (double)x[v];
+      }
+      VT y;
+#pragma unroll
+      for (int v = 0; v < V; ++v) y[v] = (TS)s[v];
+      *reinterpret_cast<VT *>(Tout + (size_t)row * post + (size_t)qi * V) = y;
+    }
+  };
+  if (staged) rows(s_cp, s_ri, s_val);
+  else rows(M.colptr, M.rowidx, M.val);
 }
 
 // scalar form (rows not a multiple of the vector width, unaligned tensors or
