@@ -41,6 +41,36 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
+// Jacobi rotation (cs, sn, t = sn / cs, the smaller angle) that zeroes the
+// off-diagonal of the symmetric 2 x 2 block [al ga; ga be], ga != 0.  With
+// a = be - al, b = 2 ga and r = sqrt(a^2 + b^2) the tangent is
+// sgn * |b| / (|a| + r) and 1 / cos^2 = 2 r / (|a| + r) (the half-angle form),
+// so cs = q m and sn = p m with q = |a| + r, p = sgn |b|, m = 1 / sqrt(2 r q):
+// one square root and one reciprocal square root, no division, on the chain.
+// a and b are first scaled by a power of two (exact) into [0.5, 1), so
+// a^2 + b^2 neither overflows nor underflows.  The reciprocal square root is
+// the hardware estimate refined by three Newton steps (quadratic convergence
+// to the rounding level from any estimate within 2^-10).  The sign convention
+// of the quotient form is kept: a = 0 takes the positive tangent.
+__device__ inline void jacobi_rotation(double al, double be, double ga, double &cs, double &sn,
+                                       double &t) {
+  double a = be - al, b = 2.0 * ga;
+  const int e = __builtin_amdgcn_frexp_exp(fmax(fabs(a), fabs(b)));
+  a = __builtin_amdgcn_ldexp(a, -e);
+  b = __builtin_amdgcn_ldexp(b, -e);
+  const double r = sqrt(fma(a, a, b * b));
+  const double q = fabs(a) + r;
+  const bool neg = (a != 0.0) & ((a < 0.0) != (b < 0.0));
+  const double p = neg ? -fabs(b) : fabs(b);
+  const double x = 2.0 * r * q;
+  double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
+  cs = q * y;
+  sn = p * y;
+  t = sn * (2.0 * r * y);
+}
+
 struct SvMat {
   const double *A;
   int m, n;
@@ -141,10 +171,8 @@ __device__ int inner_sweep(double *cols, int m, int nc, double *Wacc, int *rot, 
       be = grp16_sum(be);
       ga = grp16_sum(ga);
       if (ga != 0.0 && al > floor2 && be > floor2 && fabs(ga) > tol * sqrt(al * be)) {
-        const double zeta = (be - al) / (2.0 * ga);
-        const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-        const double cs = 1.0 / sqrt(1.0 + t * t);
-        const double sn = cs * t;
+        double cs, sn, t;
+        jacobi_rotation(al, be, ga, cs, sn, t);
         for (int i = gl; i < m; i += 16) {
           const double x = cp[i], y = cq[i];
           cp[i] = cs * x - sn * y;
@@ -386,7 +414,7 @@ __global__ __launch_bounds__(SVG_THREADS) void k_svg_round(SvBatch B, int round)
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   __shared__ int colidx[NC];
   __shared__ double rc[P], rs[P], rt[P];
-  __shared__ int rp[P], rq[P], rf[P];
+  __shared__ int rf[P];
   __shared__ int rot;
   if (tid == 0) {
     int o = 0;
@@ -489,65 +517,94 @@ __global__ __launch_bounds__(SVG_THREADS) void k_svg_round(SvBatch B, int round)
     G[i * LD + j] += Gp[i * LD + j];
   }
   __syncthreads();
-  // one inner sweep: NC - 1 rounds of P disjoint pairs (round-robin)
+  // one inner sweep: NC - 1 rounds of P disjoint pairs (round-robin).  Pair
+  // k of inner round r is (r, NC - 1) for k = 0, else {(r + k), (r - k)}
+  // modulo NC - 1 (one conditional step each: both stay within one period),
+  // so every thread derives the pairs it needs without an LDS round trip.
+  // Phase A: P threads compute the rotations from G.  Phase B: every thread
+  // updates its 2 x 2 block of G (thread (k1, k2), k1 <= k2) and its row pair
+  // of J (row k1, pair k2), all loads issued before any store; a pair that
+  // did not rotate has cs = 1, sn = 0, t = 0, which leaves its entries
+  // unchanged exactly, so the updates need no branch on it.
+  static_assert(NC * P <= SVG_THREADS, "one G block and one J row pair per thread");
+  auto pair_of = [](int r, int k, int &p, int &q) {
+    if (k == 0) {
+      p = r;
+      q = NC - 1;
+    } else {
+      int x = r + k, y = r - k;
+      x -= (x >= NC - 1) ? NC - 1 : 0;
+      y += (y < 0) ? NC - 1 : 0;
+      p = min(x, y);
+      q = max(x, y);
+    }
+  };
+  const int k1 = tid / P, k2 = tid - k1 * P;
+  const bool gdo = tid < P * P && k1 <= k2, jdo = tid < NC * P;
   for (int r = 0; r < NC - 1; ++r) {
     if (tid < P) {
       int p, q;
-      if (tid == 0) {
-        p = NC - 1;
-        q = r;
-      } else {
-        p = (r + tid) % (NC - 1);
-        q = (r - tid + NC - 1) % (NC - 1);
-      }
-      if (p > q) {
-        const int x = p;
-        p = q;
-        q = x;
-      }
+      pair_of(r, tid, p, q);
       const double al = G[p * LD + p], be = G[q * LD + q], ga = G[p * LD + q];
       double cs = 1.0, sn = 0.0, tt = 0.0;
       int f = 0;
       // |cos| > tol without a square root (al, be > 0 past the floor test)
       if (ga != 0.0 && al > floor2 && be > floor2 && ga * ga > tol2 * (al * be)) {
-        const double zeta = (be - al) / (2.0 * ga);
-        tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-        cs = 1.0 / sqrt(1.0 + tt * tt);
-        sn = cs * tt;
+        jacobi_rotation(al, be, ga, cs, sn, tt);
         f = 1;
         atomicAdd(&rot, 1);
       }
-      rp[tid] = p;
-      rq[tid] = q;
       rc[tid] = cs;
       rs[tid] = sn;
       rt[tid] = tt;
       rf[tid] = f;
     }
     __syncthreads();
-    // G <- R^T G R: thread per 2 x 2 block (pair a, pair b), a <= b, which
-    // also writes the mirrored block; blocks are disjoint
-    for (int u = tid; u < P * P; u += SVG_THREADS) {
-      const int a = u / P, c = u - a * P;
-      if (a > c || !(rf[a] | rf[c])) continue;
-      const int pa = rp[a], qa = rq[a];
-      if (a == c) {
-        const double al = G[pa * LD + pa], be = G[qa * LD + qa], ga = G[pa * LD + qa];
-        G[pa * LD + pa] = al - rt[a] * ga;
-        G[qa * LD + qa] = be + rt[a] * ga;
-        G[pa * LD + qa] = 0.0;
-        G[qa * LD + pa] = 0.0;
-        continue;
+    // G <- R^T G R and J <- J R
+    int pa = 0, qa = 0, pb, qb;
+    pair_of(r, k2, pb, qb);
+    if (gdo) pair_of(r, k1, pa, qa);
+    const double cb = rc[k2], sb = rs[k2];
+    double x = 0.0, y = 0.0, g11 = 0.0, g12 = 0.0, g21 = 0.0, g22 = 0.0, ca = 1.0, sa = 0.0,
+           ta = 0.0;
+    int fa = 0;
+    if (jdo) {
+      x = J[k1 * LD + pb];
+      y = J[k1 * LD + qb];
+    }
+    if (gdo) {
+      g11 = G[pa * LD + pb];
+      g12 = G[pa * LD + qb];
+      g21 = G[qa * LD + pb];
+      g22 = G[qa * LD + qb];
+      ca = rc[k1];
+      sa = rs[k1];
+      ta = rt[k1];
+      fa = rf[k1];
+    }
+    if (jdo) {
+      J[k1 * LD + pb] = cb * x - sb * y;
+      J[k1 * LD + qb] = sb * x + cb * y;
+    }
+    if (gdo) {
+      double n11, n12, n21, n22;
+      if (k1 == k2) {
+        // the pair's own block: stable diagonal, off-diagonal zeroed
+        n11 = g11 - ta * g12;
+        n22 = g22 + ta * g12;
+        n12 = fa ? 0.0 : g12;
+        n21 = n12;
+      } else {
+        // columns (pb, qb) rotated, then rows (pa, qa)
+        const double h11 = cb * g11 - sb * g12, h12 = sb * g11 + cb * g12;
+        const double h21 = cb * g21 - sb * g22, h22 = sb * g21 + cb * g22;
+        n11 = ca * h11 - sa * h21;
+        n21 = sa * h11 + ca * h21;
+        n12 = ca * h12 - sa * h22;
+        n22 = sa * h12 + ca * h22;
       }
-      const int pb = rp[c], qb = rq[c];
-      const double ca = rc[a], sa = rs[a], cb = rc[c], sb = rs[c];
-      const double g11 = G[pa * LD + pb], g12 = G[pa * LD + qb];
-      const double g21 = G[qa * LD + pb], g22 = G[qa * LD + qb];
-      // columns (pb, qb) rotated, then rows (pa, qa)
-      const double h11 = cb * g11 - sb * g12, h12 = sb * g11 + cb * g12;
-      const double h21 = cb * g21 - sb * g22, h22 = sb * g21 + cb * g22;
-      const double n11 = ca * h11 - sa * h21, n21 = sa * h11 + ca * h21;
-      const double n12 = ca * h12 - sa * h22, n22 = sa * h12 + ca * h22;
+      // the mirrored entries too (for the own block the same addresses,
+      // written with the same values)
       G[pa * LD + pb] = n11;
       G[pb * LD + pa] = n11;
       G[pa * LD + qb] = n12;
@@ -556,15 +613,6 @@ __global__ __launch_bounds__(SVG_THREADS) void k_svg_round(SvBatch B, int round)
       G[pb * LD + qa] = n21;
       G[qa * LD + qb] = n22;
       G[qb * LD + qa] = n22;
-    }
-    // J <- J R
-    for (int u = tid; u < NC * P; u += SVG_THREADS) {
-      const int i = u / P, a = u - i * P;
-      if (!rf[a]) continue;
-      const int pa = rp[a], qa = rq[a];
-      const double x = J[i * LD + pa], y = J[i * LD + qa];
-      J[i * LD + pa] = rc[a] * x - rs[a] * y;
-      J[i * LD + qa] = rs[a] * x + rc[a] * y;
     }
     __syncthreads();
   }
