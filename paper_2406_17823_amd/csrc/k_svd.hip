@@ -308,8 +308,10 @@ __global__ __launch_bounds__(NT) void k_sv_round(SvBatch B, int round) {
 
 // ---- Gram-matrix form of a block-pair round (blocked matrices)
 //
-// Same outer schedule, same rotation angles and the same threshold test as
-// k_sv_round, organised around the Gram matrix of the block pair: its NC
+// Same outer schedule, rotation angles and threshold test as k_sv_round
+// (the inner sweep of outer rounds past the first takes only the pairs
+// across the two blocks, see below), organised around the Gram matrix of
+// the block pair: its NC
 // column slots (m rows, zero-padded to a multiple of 16 rows; empty slots
 // are zero columns and never rotate) are staged row-major in LDS, G = X^T X
 // is formed with float64 MFMAs, and the inner sweep runs on G as two-sided
@@ -517,18 +519,33 @@ __global__ __launch_bounds__(SVG_THREADS) void k_svg_round(SvBatch B, int round)
     G[i * LD + j] += Gp[i * LD + j];
   }
   __syncthreads();
-  // one inner sweep: NC - 1 rounds of P disjoint pairs (round-robin).  Pair
-  // k of inner round r is (r, NC - 1) for k = 0, else {(r + k), (r - k)}
-  // modulo NC - 1 (one conditional step each: both stay within one period),
-  // so every thread derives the pairs it needs without an LDS round trip.
+  // one inner sweep over the slot pairs, rounds of P disjoint pairs.  Round 0
+  // of an outer sweep (and a matrix that is one block pair) takes every pair:
+  // NC - 1 rounds of the round-robin, pair k of inner round r being
+  // (r, NC - 1) for k = 0, else {(r + k), (r - k)} modulo NC - 1 (one
+  // conditional step each: both stay within one period).  The other outer
+  // rounds take only the pairs across the two blocks: P rounds, pair k of
+  // round r being (k, P + (k + r) mod P).  A block meets every other block
+  // once per outer sweep but takes part in every round, so its own pairs were
+  // otherwise swept in each of them; in round 0 every block is in exactly one
+  // pair, so each column pair is still tested at least once per outer sweep
+  // and a sweep without rotations still means every pair passed the
+  // threshold test.  Every thread derives the pairs it needs without an LDS
+  // round trip.
   // Phase A: P threads compute the rotations from G.  Phase B: every thread
   // updates its 2 x 2 block of G (thread (k1, k2), k1 <= k2) and its row pair
   // of J (row k1, pair k2), all loads issued before any store; a pair that
   // did not rotate has cs = 1, sn = 0, t = 0, which leaves its entries
   // unchanged exactly, so the updates need no branch on it.
   static_assert(NC * P <= SVG_THREADS, "one G block and one J row pair per thread");
-  auto pair_of = [](int r, int k, int &p, int &q) {
-    if (k == 0) {
+  static_assert((P & (P - 1)) == 0, "cross-block schedule modulo a power of two");
+  const bool full = D.single || round == 0;
+  const int nr = full ? NC - 1 : P;
+  auto pair_of = [full](int r, int k, int &p, int &q) {
+    if (!full) {
+      p = k;
+      q = P + ((k + r) & (P - 1));
+    } else if (k == 0) {
       p = r;
       q = NC - 1;
     } else {
@@ -541,7 +558,7 @@ __global__ __launch_bounds__(SVG_THREADS) void k_svg_round(SvBatch B, int round)
   };
   const int k1 = tid / P, k2 = tid - k1 * P;
   const bool gdo = tid < P * P && k1 <= k2, jdo = tid < NC * P;
-  for (int r = 0; r < NC - 1; ++r) {
+  for (int r = 0; r < nr; ++r) {
     if (tid < P) {
       int p, q;
       pair_of(r, tid, p, q);
