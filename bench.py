@@ -131,10 +131,19 @@ def parse():
     return ap.parse_args()
 
 
-def measured_traffic(kernel):
-    """HBM bytes per dispatch of `kernel` from the committed byte-counter
-    profile, or None when there is none or the kernel source has changed
-    since the counters were taken."""
+def workload_name(args, n, chi):
+    """The workload string of the JSON line's config (also the key of the
+    byte-counter profiles)."""
+    field = ('decaying jet' if args.field == 'jet' else
+             f'random-phase spectrum (k0 = {args.k0:g}, seed {args.seed})')
+    return (f'{field}, {1 << n}x{1 << n} grid ({n} sites), '
+            f'chi={chi}, Re={args.re:g}, dt={args.dt:g}')
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per dispatch of `kernel` on `workload` from the committed
+    byte-counter profile, or None when there is none for this workload or
+    the kernel source has changed since the counters were taken."""
     import glob
     import hashlib
     src = os.path.join(ROOT, 'paper_2406_17823_amd', 'csrc', 'k_gemm.hip')
@@ -145,7 +154,8 @@ def measured_traffic(kernel):
             if ':' in line and not line.startswith(' '):
                 k, v = line.split(':', 1)
                 kv[k.strip()] = v.strip()
-        if kv.get('kernel') == kernel and kv.get('source', '').endswith(sha):
+        if (kv.get('kernel') == kernel and kv.get('workload') == workload
+                and kv.get('source', '').endswith(sha)):
             return float(kv['traffic_bytes_per_dispatch'])
     return None
 
@@ -554,7 +564,7 @@ def main():
     avg_ms = s['timed_ms'] / max(s['timed'], 1)
     flops_per_launch = s['flops'] / max(s['launches'], 1)
     achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
-    traffic = measured_traffic(Q.KERNEL_NAMES[dom])
+    traffic = measured_traffic(Q.KERNEL_NAMES[dom], workload_name(args, n, chi))
     roofline = dict(bound='mfma', kernel=Q.KERNEL_NAMES[dom], achieved=round(achieved, 3),
                     peak=PEAK[dom], unit='TFLOP/s', frac=round(achieved / PEAK[dom], 4),
                     traffic=traffic, launches=s['launches'], avg_launch_ms=round(avg_ms, 5),
@@ -708,8 +718,6 @@ def main():
         if full is not None:
             cpu['full_step_measured'] = full
 
-    field = ('decaying jet' if args.field == 'jet' else
-             f'random-phase spectrum (k0 = {args.k0:g}, seed {args.seed})')
     line = dict(metric=f'RK4 steps/s, 2^{n}^2 grid chi={chi}, mixed vs FP64 plain at <=1e-5 rel L2 '
                        '(velocity field, one step from the common FP64 state)',
                 value=round(results[main_path]['steps_per_s'], 5), unit='RK4 steps/s',
@@ -717,8 +725,7 @@ def main():
                 ms_per_step=round(1e3 * results[main_path]['seconds'] / args.steps, 2),
                 higher_is_better=True, scaling='weak', vs_baseline=None,
                 dtype='f32' if main_path == 'mixed' else 'f64', data='synthetic',
-                config=dict(workload=f'{field}, {1 << n}x{1 << n} grid ({n} sites), '
-                                     f'chi={chi}, Re={args.re:g}, dt={args.dt:g}',
+                config=dict(workload=workload_name(args, n, chi),
                             spinup_steps=spin, bonds=[state[0].bonds, state[1].bonds],
                             sweeps=(args.sweeps if args.sweeps else
                                     'stop rule: relative change of sum <v_i|v_i> <= 1e-5, at most 10'),
