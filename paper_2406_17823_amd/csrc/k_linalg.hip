@@ -15,6 +15,8 @@
 // The working matrix lives column-major in a workspace slice in HBM/L2 so
 // that a wave64 reads one column with unit stride; reductions along a column
 // are wave-level (DPP/shuffle), the Householder vector is staged in LDS.
+#include <utility>
+
 #include "qtt_internal.h"
 
 namespace qtt {
@@ -321,6 +323,18 @@ __device__ inline double wave_sum16(const double (&v)[16], int lane) {
 // never indexed by i.
 // (ROWS = 1, 2 or 4 with 8 waves: the per-thread work of a column step
 // scales with ROWS, so the panel of a short matrix spreads over the waves)
+// f(integral_constant<int, 0>), ..., f(integral_constant<int, N - 1>): a loop
+// whose index is a compile-time constant in every step (the unroller does not
+// take loops with barriers and a run-time exit)
+template <typename F, int... Is>
+__device__ __forceinline__ void static_for_seq(F &&f, std::integer_sequence<int, Is...>) {
+  (f(std::integral_constant<int, Is>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F &&f) {
+  static_for_seq(f, std::make_integer_sequence<int, N>{});
+}
+
 template <int NW, int ROWS>
 __device__ void qrb_panel_reg(const QrbDesc &D, int j0) {
   constexpr int NT = 64 * NW;
@@ -342,7 +356,13 @@ __device__ void qrb_panel_reg(const QrbDesc &D, int j0) {
     for (int t = 0; t < QR_NB; ++t)
       P[s][t] = (r >= j0 && r < m && t < jb) ? D.W[(int64_t)(j0 + t) * m + r] : 0.0;
   }
-  for (int i = 0; i < jb; ++i) {
+  // one column step; with one row per thread the steps are expanded with a
+  // compile-time column index, so the register columns are selected directly
+  // (more rows per thread would spill so expanded); jb < 16 only for a
+  // matrix's last panel
+  auto column_step = [&](auto I_) __attribute__((always_inline)) {
+    const int i = I_;
+    if (i >= jb) return;
     const int c = j0 + i, bf = i & 1;
     double pc[ROWS];
 #pragma unroll
@@ -406,6 +426,11 @@ __device__ void qrb_panel_reg(const QrbDesc &D, int j0) {
     // the products of the earlier reflectors with this one and tau, for T
     if (tid < i) Y[tid][i] = rowc[bf][tid] + sc * red[bf][tid];
     if (tid == 0) taus[i] = tau;
+  };
+  if constexpr (ROWS == 1) {
+    static_for<QR_NB>(column_step);
+  } else {
+    for (int i = 0; i < jb; ++i) column_step(i);
   }
   __syncthreads();
   // T (upper triangular) after the column loop, off its critical path:
