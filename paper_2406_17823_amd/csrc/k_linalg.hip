@@ -15,6 +15,7 @@
 // The working matrix lives column-major in a workspace slice in HBM/L2 so
 // that a wave64 reads one column with unit stride; reductions along a column
 // are wave-level (DPP/shuffle), the Householder vector is staged in LDS.
+#include <mutex>
 #include <utility>
 
 #include "qtt_internal.h"
@@ -678,6 +679,114 @@ __global__ __launch_bounds__(QA_THREADS) void k_qrb_formq(QrbBatch B) {
   }
 }
 
+// explicit Q as k_qrb_formq, with the workgroup's tile of Q resident in
+// LDS from [I; 0] to the end (matrices of at most FQL_MAXM rows): a panel
+// step reads its V_p and V_p T_p columns from HBM/L2 but the tile only from
+// LDS, so the chain of panel steps no longer waits on the tile's own global
+// stores and reloads.  Columns left of a panel's first row are zero in that
+// panel's rows, so they take part with Z = 0 and stay exactly unchanged.
+// Tile layout: row-major, leading dimension FQ_COLS + 1.
+constexpr int FQL_MAXM = 1024, FQL_LD = FQ_COLS + 1;
+__global__ __launch_bounds__(QA_THREADS) void k_qrb_formq_lds(QrbBatch B) {
+  const QrbDesc &D = B.d[blockIdx.y];
+  if (!D.Q) return;
+  const int c0 = (int)blockIdx.x * FQ_COLS;
+  if (c0 >= D.k) return;
+  const int nc = min(FQ_COLS, D.k - c0), m = D.m;
+  extern __shared__ double Xs[];
+  __shared__ double Zs[QA_WAVES][QR_NB][FQ_COLS + 1];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  for (int e = tid; e < m * FQ_COLS; e += QA_THREADS) {
+    const int r = e / FQ_COLS, cc = e % FQ_COLS;
+    Xs[r * FQL_LD + cc] = (cc < nc && r == c0 + cc) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int j0 = ((D.k - 1) / QR_NB) * QR_NB; j0 >= 0; j0 -= QR_NB) {
+    if (j0 >= c0 + nc) continue;
+    const int jb = min(QR_NB, D.k - j0), R = m - j0;
+    // Z = V_p^T X: A[t][k] = V[j0 + k][j0 + t], B[k][c] = X[j0 + k][c]
+    d4v z = d4v{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 8
+    for (int k0 = 4 * wave; k0 < R; k0 += 4 * QA_WAVES) {
+      const int kr = k0 + lk, r = j0 + kr;
+      const bool rv = kr < R;
+      const double a = (rv && li < jb) ? D.V[(int64_t)(j0 + li) * m + r] : 0.0;
+      const double b = rv ? Xs[r * FQL_LD + li] : 0.0;
+      z = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, z, 0, 0, 0);
+    }
+    // D register q: row 4 q + lane / 16, column lane % 16; waves summed in
+    // wave order
+#pragma unroll
+    for (int q = 0; q < 4; ++q) Zs[wave][4 * q + lk][li] = z[q];
+    __syncthreads();
+    if (tid < QR_NB * FQ_COLS) {
+      const int t = tid / FQ_COLS, cc = tid % FQ_COLS;
+      double sum = Zs[0][t][cc];
+#pragma unroll
+      for (int w = 1; w < QA_WAVES; ++w) sum += Zs[w][t][cc];
+      Zs[0][t][cc] = sum;
+    }
+    __syncthreads();
+    // X^T[c][r] -= sum_t Z[t][c] U[r][t] on 16-row tiles (U = V_p T_p):
+    // A[c][t] = Z[t][c], B[t][r] = U[r][t]; a batch of tiles' loads issued
+    // before their MFMAs
+    const int ntiles = (R + 15) / 16;
+    for (int base = wave; base < ntiles; base += QA_WAVES * QA_BATCH) {
+      double ub[QA_BATCH][4], xo[QA_BATCH][4];
+#pragma unroll
+      for (int j = 0; j < QA_BATCH; ++j) {
+        const int rt = base + j * QA_WAVES;
+        const int r = j0 + 16 * rt + li;
+        const bool ok = rt < ntiles && r < m;
+#pragma unroll
+        for (int t0 = 0; t0 < 4; ++t0) {
+          const int t = 4 * t0 + lk;
+          ub[j][t0] = (ok && t < jb) ? D.VT[(int64_t)(j0 + t) * m + r] : 0.0;
+          xo[j][t0] = ok ? Xs[r * FQL_LD + 4 * t0 + lk] : 0.0;
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < QA_BATCH; ++j) {
+        const int rt = base + j * QA_WAVES;
+        if (rt >= ntiles) continue;  // wave-uniform
+        const int r = j0 + 16 * rt + li;
+        d4v acc = d4v{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int t0 = 0; t0 < 4; ++t0)
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Zs[0][4 * t0 + lk][li], ub[j][t0], acc, 0, 0, 0);
+        if (r < m)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) Xs[r * FQL_LD + 4 * q + lk] = xo[j][q] - acc[q];
+      }
+    }
+    __syncthreads();
+  }
+  // the tile back to the column-major Q workspace (consecutive threads on
+  // consecutive rows)
+  for (int e = tid; e < m * nc; e += QA_THREADS) {
+    const int cc = e / m, r = e - cc * m;
+    D.Qw[(int64_t)(c0 + cc) * m + r] = Xs[r * FQL_LD + cc];
+  }
+}
+
+// dynamic LDS of k_qrb_formq_lds for matrices of at most m rows
+size_t fql_lds(int m) { return (size_t)m * FQL_LD * sizeof(double); }
+
+// whether k_qrb_formq_lds may take FQL_MAXM rows (its LDS opt-in, once per
+// process)
+std::mutex g_fql_mutex;
+int g_fql_ok = -1;
+bool fql_enabled() {
+  std::lock_guard<std::mutex> lock(g_fql_mutex);
+  if (g_fql_ok < 0)
+    g_fql_ok = hipFuncSetAttribute((const void *)k_qrb_formq_lds,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)fql_lds(FQL_MAXM)) == hipSuccess;
+  if (!g_fql_ok) (void)hipGetLastError();
+  return g_fql_ok == 1;
+}
+
 // sign convention diag(R) >= 0; Q (m x k) and R (k x n) into the caller views
 __global__ void k_qrb_finish(QrbBatch B) {
   const QrbDesc &D = B.d[blockIdx.y];
@@ -819,7 +928,11 @@ void qr_blocked(Ctx &c, int cnt, const ConstMatView *A, const MatView *Q, const 
     for (int i = 0; i < cnt; ++i)
       if (b.d[i].Q) tiles = std::max(tiles, (b.d[i].k + FQ_COLS - 1) / FQ_COLS);
     if (tiles > 0) {
-      hipLaunchKernelGGL(k_qrb_formq, dim3(tiles, cnt), dim3(QA_THREADS), 0, c.stream, b);
+      if (mmax <= FQL_MAXM && fql_enabled())
+        hipLaunchKernelGGL(k_qrb_formq_lds, dim3(tiles, cnt), dim3(QA_THREADS), fql_lds(mmax),
+                           c.stream, b);
+      else
+        hipLaunchKernelGGL(k_qrb_formq, dim3(tiles, cnt), dim3(QA_THREADS), 0, c.stream, b);
       HIPC(hipGetLastError());
     }
   }
