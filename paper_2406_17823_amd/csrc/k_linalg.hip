@@ -687,6 +687,8 @@ __global__ __launch_bounds__(QA_THREADS) void k_qrb_formq(QrbBatch B) {
 // panel's rows, so they take part with Z = 0 and stay exactly unchanged.
 // Tile layout: row-major, leading dimension FQ_COLS + 1.
 constexpr int FQL_MAXM = 1024, FQL_LD = FQ_COLS + 1;
+// 16-row tiles of the update per wave, at most
+constexpr int FQL_TASKS = (FQL_MAXM / 16 + QA_WAVES - 1) / QA_WAVES;
 __global__ __launch_bounds__(QA_THREADS) void k_qrb_formq_lds(QrbBatch B) {
   const QrbDesc &D = B.d[blockIdx.y];
   if (!D.Q) return;
@@ -705,6 +707,21 @@ __global__ __launch_bounds__(QA_THREADS) void k_qrb_formq_lds(QrbBatch B) {
   for (int j0 = ((D.k - 1) / QR_NB) * QR_NB; j0 >= 0; j0 -= QR_NB) {
     if (j0 >= c0 + nc) continue;
     const int jb = min(QR_NB, D.k - j0), R = m - j0;
+    // the wave's operands of U = V_p T_p for the update below, issued first
+    // (they do not depend on Z): 16-row tile rt = wave + QA_WAVES j
+    const int ntiles = (R + 15) / 16;
+    double ub[FQL_TASKS][4];
+#pragma unroll
+    for (int j = 0; j < FQL_TASKS; ++j) {
+      const int rt = wave + j * QA_WAVES;
+      const int r = j0 + 16 * rt + li;
+      const bool ok = rt < ntiles && r < m;
+#pragma unroll
+      for (int t0 = 0; t0 < 4; ++t0) {
+        const int t = 4 * t0 + lk;
+        ub[j][t0] = (ok && t < jb) ? D.VT[(int64_t)(j0 + t) * m + r] : 0.0;
+      }
+    }
     // Z = V_p^T X: A[t][k] = V[j0 + k][j0 + t], B[k][c] = X[j0 + k][c]
     d4v z = d4v{0.0, 0.0, 0.0, 0.0};
 #pragma unroll 8
@@ -729,36 +746,22 @@ __global__ __launch_bounds__(QA_THREADS) void k_qrb_formq_lds(QrbBatch B) {
     }
     __syncthreads();
     // X^T[c][r] -= sum_t Z[t][c] U[r][t] on 16-row tiles (U = V_p T_p):
-    // A[c][t] = Z[t][c], B[t][r] = U[r][t]; a batch of tiles' loads issued
-    // before their MFMAs
-    const int ntiles = (R + 15) / 16;
-    for (int base = wave; base < ntiles; base += QA_WAVES * QA_BATCH) {
-      double ub[QA_BATCH][4], xo[QA_BATCH][4];
+    // A[c][t] = Z[t][c], B[t][r] = U[r][t]
 #pragma unroll
-      for (int j = 0; j < QA_BATCH; ++j) {
-        const int rt = base + j * QA_WAVES;
-        const int r = j0 + 16 * rt + li;
-        const bool ok = rt < ntiles && r < m;
+    for (int j = 0; j < FQL_TASKS; ++j) {
+      const int rt = wave + j * QA_WAVES;
+      if (rt >= ntiles) break;  // wave-uniform
+      const int r = j0 + 16 * rt + li;
+      double xo[4];
 #pragma unroll
-        for (int t0 = 0; t0 < 4; ++t0) {
-          const int t = 4 * t0 + lk;
-          ub[j][t0] = (ok && t < jb) ? D.VT[(int64_t)(j0 + t) * m + r] : 0.0;
-          xo[j][t0] = ok ? Xs[r * FQL_LD + 4 * t0 + lk] : 0.0;
-        }
-      }
+      for (int q = 0; q < 4; ++q) xo[q] = r < m ? Xs[r * FQL_LD + 4 * q + lk] : 0.0;
+      d4v acc = d4v{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int j = 0; j < QA_BATCH; ++j) {
-        const int rt = base + j * QA_WAVES;
-        if (rt >= ntiles) continue;  // wave-uniform
-        const int r = j0 + 16 * rt + li;
-        d4v acc = d4v{0.0, 0.0, 0.0, 0.0};
+      for (int t0 = 0; t0 < 4; ++t0)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Zs[0][4 * t0 + lk][li], ub[j][t0], acc, 0, 0, 0);
+      if (r < m)
 #pragma unroll
-        for (int t0 = 0; t0 < 4; ++t0)
-          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Zs[0][4 * t0 + lk][li], ub[j][t0], acc, 0, 0, 0);
-        if (r < m)
-#pragma unroll
-          for (int q = 0; q < 4; ++q) Xs[r * FQL_LD + 4 * q + lk] = xo[j][q] - acc[q];
-      }
+        for (int q = 0; q < 4; ++q) Xs[r * FQL_LD + 4 * q + lk] = xo[q] - acc[q];
     }
     __syncthreads();
   }
