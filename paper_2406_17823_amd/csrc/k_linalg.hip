@@ -679,29 +679,33 @@ __global__ __launch_bounds__(QA_THREADS) void k_qrb_formq(QrbBatch B) {
   }
 }
 
-// explicit Q as k_qrb_formq, with the workgroup's tile of Q resident in
-// LDS from [I; 0] to the end (matrices of at most FQL_MAXM rows): a panel
-// step reads its V_p and V_p T_p columns from HBM/L2 but the tile only from
-// LDS, so the chain of panel steps no longer waits on the tile's own global
-// stores and reloads.  Columns left of a panel's first row are zero in that
-// panel's rows, so they take part with Z = 0 and stay exactly unchanged.
-// Tile layout: row-major, leading dimension FQ_COLS + 1.
-constexpr int FQL_MAXM = 1024, FQL_LD = FQ_COLS + 1;
-// 16-row tiles of the update per wave, at most
-constexpr int FQL_TASKS = (FQL_MAXM / 16 + QA_WAVES - 1) / QA_WAVES;
+// explicit Q as k_qrb_formq, with the workgroup's tile of NCOL columns of Q
+// resident in LDS from [I; 0] to the end (matrices of at most MAXM rows: 16
+// columns up to 1024 rows, 8 up to 2048): a panel step reads its V_p and
+// V_p T_p columns from HBM/L2 but the tile only from LDS, so the chain of
+// panel steps no longer waits on the tile's own global stores and reloads.
+// Columns left of a panel's first row are zero in that panel's rows, so they
+// take part with Z = 0 and stay exactly unchanged.  Tile layout: row-major,
+// leading dimension NCOL + 1.  With 8 columns the MFMAs' upper 8 columns
+// carry zeros.
+template <int NCOL, int MAXM>
 __global__ __launch_bounds__(QA_THREADS) void k_qrb_formq_lds(QrbBatch B) {
+  static_assert(NCOL == 16 || NCOL == 8, "tiles of 16 or 8 columns");
+  constexpr int LD = NCOL + 1, NQ = NCOL / 4;
+  // 16-row tiles of the update per wave, at most
+  constexpr int TASKS = (MAXM / 16 + QA_WAVES - 1) / QA_WAVES;
   const QrbDesc &D = B.d[blockIdx.y];
   if (!D.Q) return;
-  const int c0 = (int)blockIdx.x * FQ_COLS;
+  const int c0 = (int)blockIdx.x * NCOL;
   if (c0 >= D.k) return;
-  const int nc = min(FQ_COLS, D.k - c0), m = D.m;
+  const int nc = min(NCOL, D.k - c0), m = D.m;
   extern __shared__ double Xs[];
-  __shared__ double Zs[QA_WAVES][QR_NB][FQ_COLS + 1];
+  __shared__ double Zs[QA_WAVES][QR_NB][NCOL + 1];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  for (int e = tid; e < m * FQ_COLS; e += QA_THREADS) {
-    const int r = e / FQ_COLS, cc = e % FQ_COLS;
-    Xs[r * FQL_LD + cc] = (cc < nc && r == c0 + cc) ? 1.0 : 0.0;
+  for (int e = tid; e < m * NCOL; e += QA_THREADS) {
+    const int r = e / NCOL, cc = e % NCOL;
+    Xs[r * LD + cc] = (cc < nc && r == c0 + cc) ? 1.0 : 0.0;
   }
   __syncthreads();
   for (int j0 = ((D.k - 1) / QR_NB) * QR_NB; j0 >= 0; j0 -= QR_NB) {
@@ -710,9 +714,9 @@ __global__ __launch_bounds__(QA_THREADS) void k_qrb_formq_lds(QrbBatch B) {
     // the wave's operands of U = V_p T_p for the update below, issued first
     // (they do not depend on Z): 16-row tile rt = wave + QA_WAVES j
     const int ntiles = (R + 15) / 16;
-    double ub[FQL_TASKS][4];
+    double ub[TASKS][4];
 #pragma unroll
-    for (int j = 0; j < FQL_TASKS; ++j) {
+    for (int j = 0; j < TASKS; ++j) {
       const int rt = wave + j * QA_WAVES;
       const int r = j0 + 16 * rt + li;
       const bool ok = rt < ntiles && r < m;
@@ -729,16 +733,17 @@ __global__ __launch_bounds__(QA_THREADS) void k_qrb_formq_lds(QrbBatch B) {
       const int kr = k0 + lk, r = j0 + kr;
       const bool rv = kr < R;
       const double a = (rv && li < jb) ? D.V[(int64_t)(j0 + li) * m + r] : 0.0;
-      const double b = rv ? Xs[r * FQL_LD + li] : 0.0;
+      const double b = (rv && li < NCOL) ? Xs[r * LD + li] : 0.0;
       z = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, z, 0, 0, 0);
     }
     // D register q: row 4 q + lane / 16, column lane % 16; waves summed in
     // wave order
+    if (li < NCOL)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) Zs[wave][4 * q + lk][li] = z[q];
+      for (int q = 0; q < 4; ++q) Zs[wave][4 * q + lk][li] = z[q];
     __syncthreads();
-    if (tid < QR_NB * FQ_COLS) {
-      const int t = tid / FQ_COLS, cc = tid % FQ_COLS;
+    if (tid < QR_NB * NCOL) {
+      const int t = tid / NCOL, cc = tid % NCOL;
       double sum = Zs[0][t][cc];
 #pragma unroll
       for (int w = 1; w < QA_WAVES; ++w) sum += Zs[w][t][cc];
@@ -748,20 +753,21 @@ __global__ __launch_bounds__(QA_THREADS) void k_qrb_formq_lds(QrbBatch B) {
     // X^T[c][r] -= sum_t Z[t][c] U[r][t] on 16-row tiles (U = V_p T_p):
     // A[c][t] = Z[t][c], B[t][r] = U[r][t]
 #pragma unroll
-    for (int j = 0; j < FQL_TASKS; ++j) {
+    for (int j = 0; j < TASKS; ++j) {
       const int rt = wave + j * QA_WAVES;
       if (rt >= ntiles) break;  // wave-uniform
       const int r = j0 + 16 * rt + li;
-      double xo[4];
+      double xo[NQ];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) xo[q] = r < m ? Xs[r * FQL_LD + 4 * q + lk] : 0.0;
+      for (int q = 0; q < NQ; ++q) xo[q] = r < m ? Xs[r * LD + 4 * q + lk] : 0.0;
       d4v acc = d4v{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
       for (int t0 = 0; t0 < 4; ++t0)
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Zs[0][4 * t0 + lk][li], ub[j][t0], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(li < NCOL ? Zs[0][4 * t0 + lk][li] : 0.0,
+                                                   ub[j][t0], acc, 0, 0, 0);
       if (r < m)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) Xs[r * FQL_LD + 4 * q + lk] = xo[q] - acc[q];
+        for (int q = 0; q < NQ; ++q) Xs[r * LD + 4 * q + lk] = xo[q] - acc[q];
     }
     __syncthreads();
   }
@@ -769,24 +775,28 @@ __global__ __launch_bounds__(QA_THREADS) void k_qrb_formq_lds(QrbBatch B) {
   // consecutive rows)
   for (int e = tid; e < m * nc; e += QA_THREADS) {
     const int cc = e / m, r = e - cc * m;
-    D.Qw[(int64_t)(c0 + cc) * m + r] = Xs[r * FQL_LD + cc];
+    D.Qw[(int64_t)(c0 + cc) * m + r] = Xs[r * LD + cc];
   }
 }
 
-// dynamic LDS of k_qrb_formq_lds for matrices of at most m rows
-size_t fql_lds(int m) { return (size_t)m * FQL_LD * sizeof(double); }
+// dynamic LDS of k_qrb_formq_lds<ncol, .> for matrices of at most m rows
+size_t fql_lds(int ncol, int m) { return (size_t)m * (ncol + 1) * sizeof(double); }
 
-// whether k_qrb_formq_lds may take FQL_MAXM rows (its LDS opt-in, once per
+// whether k_qrb_formq_lds may take its row limits (the LDS opt-in, once per
 // process)
 std::mutex g_fql_mutex;
 int g_fql_ok = -1;
 bool fql_enabled() {
   std::lock_guard<std::mutex> lock(g_fql_mutex);
-  if (g_fql_ok < 0)
-    g_fql_ok = hipFuncSetAttribute((const void *)k_qrb_formq_lds,
+  if (g_fql_ok < 0) {
+    g_fql_ok = hipFuncSetAttribute((const void *)k_qrb_formq_lds<16, 1024>,
                                    hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   (int)fql_lds(FQL_MAXM)) == hipSuccess;
-  if (!g_fql_ok) (void)hipGetLastError();
+                                   (int)fql_lds(16, 1024)) == hipSuccess &&
+               hipFuncSetAttribute((const void *)k_qrb_formq_lds<8, 2048>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)fql_lds(8, 2048)) == hipSuccess;
+    if (!g_fql_ok) (void)hipGetLastError();
+  }
   return g_fql_ok == 1;
 }
 
@@ -927,13 +937,18 @@ void qr_blocked(Ctx &c, int cnt, const ConstMatView *A, const MatView *Q, const 
   // Q = H_0 ... [I; 0], panels applied last to first (not for R-only requests):
   // Q[j0:m, j0:k] -= (V_p T_p)(V_p^T Q[j0:m, j0:k]), all panels in one launch
   {
+    const bool lds = mmax <= 2048 && fql_enabled();
+    const int ncol = !lds ? FQ_COLS : (mmax <= 1024 ? 16 : 8);
     int tiles = 0;
     for (int i = 0; i < cnt; ++i)
-      if (b.d[i].Q) tiles = std::max(tiles, (b.d[i].k + FQ_COLS - 1) / FQ_COLS);
+      if (b.d[i].Q) tiles = std::max(tiles, (b.d[i].k + ncol - 1) / ncol);
     if (tiles > 0) {
-      if (mmax <= FQL_MAXM && fql_enabled())
-        hipLaunchKernelGGL(k_qrb_formq_lds, dim3(tiles, cnt), dim3(QA_THREADS), fql_lds(mmax),
-                           c.stream, b);
+      if (lds && ncol == 16)
+        hipLaunchKernelGGL((k_qrb_formq_lds<16, 1024>), dim3(tiles, cnt), dim3(QA_THREADS),
+                           fql_lds(16, mmax), c.stream, b);
+      else if (lds)
+        hipLaunchKernelGGL((k_qrb_formq_lds<8, 2048>), dim3(tiles, cnt), dim3(QA_THREADS),
+                           fql_lds(8, mmax), c.stream, b);
       else
         hipLaunchKernelGGL(k_qrb_formq, dim3(tiles, cnt), dim3(QA_THREADS), 0, c.stream, b);
       HIPC(hipGetLastError());
