@@ -635,7 +635,8 @@ def main():
             for path in ('mixed', 'f64'):
                 pr = Q.params(re=args.re, dt=args.dt, chi=chi_x, dx=1.0 / Nn,
                               cg_rtol=args.cg_rtol if path == 'f64' else args.mixed_cg_rtol,
-                              cg_maxit=args.cg_maxit, max_sweeps=args.sweeps, svd_rtol=1e-12,
+                              cg_maxit=args.cg_maxit, max_sweeps=args.sweeps or 10,
+                              sweep_rtol=0.0 if args.sweeps else 1e-5, svd_rtol=1e-12,
                               prec=Q.PREC_F32 if path == 'mixed' else Q.PREC_F64)
                 st_ = [Q.from_dense(ctx, torch.from_numpy(np.ascontiguousarray(f[c])).cuda(), chi_x,
                                     1e-12, capacity=capn) for c in range(2)]
