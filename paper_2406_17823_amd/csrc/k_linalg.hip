@@ -703,13 +703,28 @@ __global__ __launch_bounds__(QA_THREADS) void k_qrb_formq_lds(QrbBatch B) {
   __shared__ double Zs[QA_WAVES][QR_NB][NCOL + 1];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
+  // the wave's V_p operands of the V_p^T X product (k0 = 4 wave + 32 i): up to
+  // 512 rows they are loaded one panel step ahead, under the current step's
+  // update (more rows would not fit the registers)
+  constexpr bool PF = MAXM <= 512;
+  constexpr int KITER = MAXM / (4 * QA_WAVES);
+  double va[PF ? KITER : 1];
+  auto load_v = [&](int j0) {
+    const int jb = min(QR_NB, D.k - j0), R = m - j0;
+#pragma unroll
+    for (int i = 0; i < (PF ? KITER : 1); ++i) {
+      const int kr = 4 * wave + 32 * i + lk;
+      va[i] = (kr < R && li < jb) ? D.V[(int64_t)(j0 + li) * m + j0 + kr] : 0.0;
+    }
+  };
+  const int jfirst = ((min(D.k, c0 + nc) - 1) / QR_NB) * QR_NB;
+  if (PF) load_v(jfirst);
   for (int e = tid; e < m * NCOL; e += QA_THREADS) {
     const int r = e / NCOL, cc = e % NCOL;
     Xs[r * LD + cc] = (cc < nc && r == c0 + cc) ? 1.0 : 0.0;
   }
   __syncthreads();
-  for (int j0 = ((D.k - 1) / QR_NB) * QR_NB; j0 >= 0; j0 -= QR_NB) {
-    if (j0 >= c0 + nc) continue;
+  for (int j0 = jfirst; j0 >= 0; j0 -= QR_NB) {
     const int jb = min(QR_NB, D.k - j0), R = m - j0;
     // the wave's operands of U = V_p T_p for the update below, issued first
     // (they do not depend on Z): 16-row tile rt = wave + QA_WAVES j
@@ -728,13 +743,27 @@ __global__ __launch_bounds__(QA_THREADS) void k_qrb_formq_lds(QrbBatch B) {
     }
     // Z = V_p^T X: A[t][k] = V[j0 + k][j0 + t], B[k][c] = X[j0 + k][c]
     d4v z = d4v{0.0, 0.0, 0.0, 0.0};
+    if constexpr (PF) {
+#pragma unroll
+      for (int i = 0; i < KITER; ++i) {
+        const int k0 = 4 * wave + 32 * i;
+        if (k0 < R) {  // wave-uniform
+          const int kr = k0 + lk, r = j0 + kr;
+          const double b = (kr < R && li < NCOL) ? Xs[r * LD + li] : 0.0;
+          z = __builtin_amdgcn_mfma_f64_16x16x4f64(va[i], b, z, 0, 0, 0);
+        }
+      }
+      // the next panel step's operands (independent of this step's results)
+      if (j0 >= QR_NB) load_v(j0 - QR_NB);
+    } else {
 #pragma unroll 8
-    for (int k0 = 4 * wave; k0 < R; k0 += 4 * QA_WAVES) {
-      const int kr = k0 + lk, r = j0 + kr;
-      const bool rv = kr < R;
-      const double a = (rv && li < jb) ? D.V[(int64_t)(j0 + li) * m + r] : 0.0;
-      const double b = (rv && li < NCOL) ? Xs[r * LD + li] : 0.0;
-      z = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, z, 0, 0, 0);
+      for (int k0 = 4 * wave; k0 < R; k0 += 4 * QA_WAVES) {
+        const int kr = k0 + lk, r = j0 + kr;
+        const bool rv = kr < R;
+        const double a = (rv && li < jb) ? D.V[(int64_t)(j0 + li) * m + r] : 0.0;
+        const double b = (rv && li < NCOL) ? Xs[r * LD + li] : 0.0;
+        z = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, z, 0, 0, 0);
+      }
     }
     // D register q: row 4 q + lane / 16, column lane % 16; waves summed in
     // wave order
@@ -789,7 +818,10 @@ int g_fql_ok = -1;
 bool fql_enabled() {
   std::lock_guard<std::mutex> lock(g_fql_mutex);
   if (g_fql_ok < 0) {
-    g_fql_ok = hipFuncSetAttribute((const void *)k_qrb_formq_lds<16, 1024>,
+    g_fql_ok = hipFuncSetAttribute((const void *)k_qrb_formq_lds<16, 512>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)fql_lds(16, 512)) == hipSuccess &&
+               hipFuncSetAttribute((const void *)k_qrb_formq_lds<16, 1024>,
                                    hipFuncAttributeMaxDynamicSharedMemorySize,
                                    (int)fql_lds(16, 1024)) == hipSuccess &&
                hipFuncSetAttribute((const void *)k_qrb_formq_lds<8, 2048>,
@@ -943,7 +975,10 @@ void qr_blocked(Ctx &c, int cnt, const ConstMatView *A, const MatView *Q, const 
     for (int i = 0; i < cnt; ++i)
       if (b.d[i].Q) tiles = std::max(tiles, (b.d[i].k + ncol - 1) / ncol);
     if (tiles > 0) {
-      if (lds && ncol == 16)
+      if (lds && mmax <= 512)
+        hipLaunchKernelGGL((k_qrb_formq_lds<16, 512>), dim3(tiles, cnt), dim3(QA_THREADS),
+                           fql_lds(16, mmax), c.stream, b);
+      else if (lds && ncol == 16)
         hipLaunchKernelGGL((k_qrb_formq_lds<16, 1024>), dim3(tiles, cnt), dim3(QA_THREADS),
                            fql_lds(16, mmax), c.stream, b);
       else if (lds)
